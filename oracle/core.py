@@ -1,0 +1,335 @@
+"""CPU reference of the VMS assembly / in-out path (TEST INFRASTRUCTURE ONLY).
+
+Only tests, the smoke check and the benchmark's CPU-baseline leg may import
+this module. It never touches the HIP library and the HIP library never
+touches it.
+
+It drives the plain C routines in ``oracle.c`` (physics with a complex-step
+Jacobian, exact predicates, recursive adaptive quadrature) and the numpy mesh
+derivation in ``mesh.py``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+from . import mesh as _mesh
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+OUT, IN, INTERCEPTED = 0, 1, 2
+ALL_TERMS = 0x3FF
+# Gauss abscissae, correctly rounded: 1/sqrt3 on [-1, 1]; (1 -+ 1/sqrt3)/2 on [0, 1]
+XI = float.fromhex("0x1.279a74590331cp-1")
+G_MINUS = float.fromhex("0x1.b0cb174df99c7p-3")
+G_PLUS = float.fromhex("0x1.93cd3a2c8198ep-1")
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (no FMA contraction)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", "-o", LIB,
+               SRC, "-lm"]
+        subprocess.check_call(cmd)
+    return LIB
+
+
+class Params(C.Structure):
+    _fields_ = [("rho", C.c_double), ("mu", C.c_double), ("dt", C.c_double),
+                ("theta", C.c_double), ("c_t", C.c_double), ("c_i", C.c_double),
+                ("term_mask", C.c_int32), ("pad", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        p = C.c_void_p
+        L.or_assemble.restype = C.c_int64
+        L.or_assemble.argtypes = [p, C.c_int64] + [p] * 7 + [p] * 7 + [p] * 4 + [C.c_int64, C.c_int64]
+        L.or_element.restype = None
+        L.or_element.argtypes = [p, C.c_double, C.c_int, p, p, C.c_int, p, p, p, p, p]
+        L.or_element_frozen.restype = None
+        L.or_element_frozen.argtypes = [p, C.c_double, C.c_int, p, p, C.c_int, p, p, p, p, p]
+        L.or_taus.restype = None
+        L.or_taus.argtypes = [p, C.c_double, C.c_int, p, p, p, p]
+        L.or_orient3d.restype = C.c_int
+        L.or_orient3d.argtypes = [p, p, p, p]
+        L.or_orient2d.restype = C.c_int
+        L.or_orient2d.argtypes = [p, p, p, C.c_int, C.c_int]
+        L.or_seg_tri.restype = C.c_int
+        L.or_seg_tri.argtypes = [p] * 5
+        L.or_label_points.restype = C.c_int64
+        L.or_label_points.argtypes = [C.c_int64, p, C.c_int64, p, C.c_int64, p, p]
+        L.or_subquad.restype = C.c_int64
+        L.or_subquad.argtypes = ([C.c_int64, p, C.c_int64, p, p, C.c_double, C.c_int, C.c_int,
+                                  C.c_int64, p, p, p, p, p, C.c_int64, p, p, p, p, p])
+        L.or_coords.restype = None
+        L.or_coords.argtypes = [p, C.c_double, C.c_int, C.c_int64, p, p, p, p]
+        L.or_unsigned_dist.restype = None
+        L.or_unsigned_dist.argtypes = [C.c_int64, p, p, C.c_int64, p, p]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def params(rho=1.0, mu=0.01, dt=0.01, theta=0.5, c_t=4.0, c_i=36.0, term_mask=ALL_TERMS):
+    return Params(rho, mu, dt, theta, c_t, c_i, term_mask, 0)
+
+
+# ---------------------------------------------------------------------------
+# Geometry: exact predicates, labels, markers, adaptive quadrature
+# ---------------------------------------------------------------------------
+
+
+def orient3d(a, b, c, d) -> int:
+    a, b, c, d = (_c(x, np.float64) for x in (a, b, c, d))
+    return lib().or_orient3d(_p(a), _p(b), _p(c), _p(d))
+
+
+def orient2d(a, b, c, i=0, j=1) -> int:
+    a, b, c = (_c(x, np.float64) for x in (a, b, c))
+    return lib().or_orient2d(_p(a), _p(b), _p(c), i, j)
+
+
+def seg_tri(P, Q, a, b, c) -> int:
+    P, Q, a, b, c = (_c(x, np.float64) for x in (P, Q, a, b, c))
+    return lib().or_seg_tri(_p(P), _p(Q), _p(a), _p(b), _p(c))
+
+
+def label_points(surf, xyz):
+    """Exact labels (1 IN / on surface, 0 OUT) of points (n, 3); returns (labels, n_degenerate)."""
+    v = _c(surf.verts, np.float64)
+    t = _c(surf.tris, np.int32)
+    x = _c(xyz, np.float64).reshape(-1, 3)
+    lab = np.zeros(x.shape[0], np.uint8)
+    nd = lib().or_label_points(v.shape[0], _p(v), t.shape[0], _p(t), x.shape[0], _p(x), _p(lab))
+    return lab, int(nd)
+
+
+def coords(origin, root_len, F, A, B, gsel):
+    """x = origin + root_len*((A + B*g) 2^-F) per axis; gsel in {0, -1 (g-), +1 (g+)}."""
+    A = _c(A, np.int64).reshape(-1, 3)
+    B = _c(B, np.int64).reshape(-1)
+    g = _c(gsel, np.int8).reshape(-1, 3)
+    o = _c(origin, np.float64)
+    out = np.zeros((A.shape[0], 3))
+    lib().or_coords(_p(o), float(root_len), int(F), A.shape[0], _p(A), _p(B), _p(g), _p(out))
+    return out
+
+
+def vertex_xyz(tree, ms):
+    """Physical coordinates of every vertex position (hanging included)."""
+    xi = _mesh._decode(ms.vertex_keys)
+    n = xi.shape[0]
+    return coords(tree.origin, tree.root_len, tree.max_level, xi, np.zeros(n, np.int64),
+                  np.zeros((n, 3), np.int8))
+
+
+def markers(tree, ms, surf):
+    """Alg. 4: count IN labels of the eight vertex positions of each element."""
+    vx = vertex_xyz(tree, ms)
+    vlab, nd = label_points(surf, vx)
+    cnt = vlab[ms.elem_vertex].astype(np.int64).sum(1)
+    mk = np.full(tree.n, INTERCEPTED, np.uint8)
+    mk[cnt == 8] = IN
+    mk[cnt == 0] = OUT
+    return mk, vlab, nd
+
+
+def subquad(tree, surf, el_idx, depth, cap=None):
+    """Kept (OUT) sub-cell Gauss points of the given elements, depth-first order.
+
+    Returns dict: el, key, lvl, xyz, n_labelled, n_degenerate."""
+    el_idx = _c(el_idx, np.int64)
+    v = _c(surf.verts, np.float64)
+    t = _c(surf.tris, np.int32)
+    if cap is None:
+        cap = max(1, int(el_idx.size) * 8 * 8 ** max(depth, 0))
+    out_el = np.zeros(cap, np.int64)
+    out_key = np.zeros(cap, np.int32)
+    out_lvl = np.zeros(cap, np.uint8)
+    out_xyz = np.zeros((cap, 3))
+    st = np.zeros(2, np.int64)
+    o = _c(tree.origin, np.float64)
+    n = lib().or_subquad(v.shape[0], _p(v), t.shape[0], _p(t), _p(o), float(tree.root_len),
+                         tree.max_level, depth, el_idx.size, _p(el_idx), _p(_c(tree.ax, np.int32)),
+                         _p(_c(tree.ay, np.int32)), _p(_c(tree.az, np.int32)),
+                         _p(_c(tree.level, np.uint8)), cap, _p(out_el), _p(out_key), _p(out_lvl),
+                         _p(out_xyz), _p(st))
+    if n > cap:
+        return subquad(tree, surf, el_idx, depth, cap=int(n))
+    return {"el": out_el[:n], "key": out_key[:n], "lvl": out_lvl[:n], "xyz": out_xyz[:n],
+            "n_labelled": int(st[0]), "n_degenerate": int(st[1])}
+
+
+def subgp_xi(tree, el, key, lvl, depth):
+    """Reference coordinates (in the parent element) and weights of sub-cell points."""
+    el = np.asarray(el, np.int64)
+    key = np.asarray(key, np.int64)
+    lvl = np.asarray(lvl, np.int64)
+    n = el.size
+    srel = np.zeros((n, 3), np.int64)   # sub-cell anchor relative to the element, fine units
+    M = tree.max_level
+    SE = (np.int64(1) << (M - tree.level[el].astype(np.int64) + depth))   # element side, fine units
+    gp = (key >> (3 * (depth - lvl))) & 7
+    for k in range(1, depth + 1):       # digit of level k, present if k <= lvl
+        d = (key >> (3 * (depth - k + 1))) & 7
+        on = k <= lvl
+        for ax in range(3):
+            srel[:, ax] += np.where(on & (((d >> ax) & 1) == 1), SE >> k, 0)
+    S = SE >> lvl
+    xi = np.zeros((n, 3))
+    for ax in range(3):
+        g = np.where((gp >> ax) & 1, G_PLUS, G_MINUS)
+        xi[:, ax] = 2.0 * (srel[:, ax] + S * g) / SE - 1.0
+    h = tree.root_len * (SE.astype(np.float64) / float(1 << (M + depth)))
+    w = (h / (2.0 ** (lvl + 1))) ** 3
+    return xi, w
+
+
+# ---------------------------------------------------------------------------
+# Assembly
+# ---------------------------------------------------------------------------
+
+
+def element_h(tree):
+    return tree.root_len * (tree.side().astype(np.float64) / float(1 << tree.max_level))
+
+
+def std_points(h):
+    """The 2x2x2 Gauss points (x fastest) and weights (h/2)^3."""
+    xi = np.array([[XI if (g >> k) & 1 else -XI for k in range(3)] for g in range(8)])
+    return xi, np.full(8, (h / 2.0) ** 3)
+
+
+def point_lists(tree, mk, sub, depth):
+    """Per element: 8 Gauss points for OUT, kept sub-cell points for INTERCEPTED, none for IN."""
+    E = tree.n
+    h = element_h(tree)
+    counts = np.where(mk == OUT, 8, 0).astype(np.int64)
+    if sub is not None and sub["el"].size:
+        np.add.at(counts, sub["el"], 1)
+    off = np.zeros(E + 1, np.int64)
+    off[1:] = np.cumsum(counts)
+    xi = np.zeros((off[-1], 3))
+    w = np.zeros(off[-1])
+    sxi = np.array([[XI if (g >> k) & 1 else -XI for k in range(3)] for g in range(8)])
+    outs = np.nonzero(mk == OUT)[0]
+    for g in range(8):
+        xi[off[outs] + g] = sxi[g]
+        w[off[outs] + g] = (h[outs] / 2.0) ** 3
+    if sub is not None and sub["el"].size:
+        sx, sw = subgp_xi(tree, sub["el"], sub["key"], sub["lvl"], depth)
+        # sub points come grouped by element in ascending element order
+        order = np.argsort(sub["el"], kind="stable")
+        el_sorted = sub["el"][order]
+        first = np.searchsorted(el_sorted, el_sorted, side="left")
+        rank = np.arange(el_sorted.size) - first
+        dst = off[el_sorted] + rank
+        xi[dst] = sx[order]
+        w[dst] = sw[order]
+    return off, xi, w
+
+
+def assemble(tree, ms, fields, prm=None, mk=None, sub=None, depth=3, vals=True, resid=True,
+             el_range=None):
+    """Global Jacobian values (CSR of ``ms``) and residual, FP64.
+
+    Inactive nodes (no contribution from any non-IN element) get an identity
+    diagonal block and a zero residual."""
+    prm = prm or params()
+    E = tree.n
+    mk = np.zeros(E, np.uint8) if mk is None else mk
+    off, xi, w = point_lists(tree, mk, sub, depth)
+    h = element_h(tree)
+    Cm = _c(ms.C, np.float64)
+    V = np.zeros(ms.nnz) if vals else None
+    R = np.zeros(4 * ms.n_nodes) if resid else None
+    f = {k: _c(fields[k], np.float64) for k in ("ux", "uy", "uz", "p", "ux0", "uy0", "uz0")}
+    b, e = (0, E) if el_range is None else el_range
+    rc = lib().or_assemble(C.byref(prm), E, _p(_c(ms.nm, np.int32)), _p(_c(ms.masters, np.int32)),
+                           _p(Cm), _p(_c(h, np.float64)), _p(off), _p(_c(xi, np.float64)),
+                           _p(_c(w, np.float64)), _p(f["ux"]), _p(f["uy"]), _p(f["uz"]),
+                           _p(f["p"]), _p(f["ux0"]), _p(f["uy0"]), _p(f["uz0"]),
+                           _p(ms.row_ptr), _p(ms.col_idx), _p(V), _p(R), b, e)
+    if rc != 0:
+        raise RuntimeError(f"pattern misses an entry of element {-rc - 1}")
+    if el_range is None and V is not None:
+        inact = np.nonzero(~ms.node_active)[0]
+        for n in inact:
+            for c in range(4):
+                r = 4 * n + c
+                k = ms.row_ptr[r] + np.searchsorted(ms.col_idx[ms.row_ptr[r]:ms.row_ptr[r + 1]], r)
+                V[k] = 1.0
+    return V, R
+
+
+def element(prm, h, xi, w, Cmat, Um, U0m):
+    """Residual (nm*4) and Jacobian ((nm*4)^2) of one element in master space."""
+    xi = _c(xi, np.float64).reshape(-1, 3)
+    w = _c(w, np.float64)
+    nm = Cmat.shape[1]
+    Cm = _c(Cmat, np.float64)
+    Um = _c(Um, np.float64).reshape(nm, 4)
+    U0m = _c(U0m, np.float64).reshape(nm, 3)
+    R = np.zeros(nm * 4)
+    J = np.zeros((nm * 4) ** 2)
+    lib().or_element(C.byref(prm), float(h), xi.shape[0], _p(xi), _p(w), nm, _p(Cm), _p(Um),
+                     _p(U0m), _p(R), _p(J))
+    return R, J.reshape(nm * 4, nm * 4)
+
+
+def element_frozen(prm, h, xi, w, Cmat, Ub, Ue, U0m):
+    """Residual at Ue with stabilisation parameters frozen at Ub (master space)."""
+    xi = _c(xi, np.float64).reshape(-1, 3)
+    nm = Cmat.shape[1]
+    R = np.zeros(nm * 4)
+    lib().or_element_frozen(C.byref(prm), float(h), xi.shape[0], _p(xi), _p(_c(w, np.float64)), nm,
+                            _p(_c(Cmat, np.float64)), _p(_c(Ub, np.float64)), _p(_c(Ue, np.float64)),
+                            _p(_c(U0m, np.float64)), _p(R))
+    return R
+
+
+def taus(prm, h, xi, Uv, U0v):
+    xi = _c(xi, np.float64).reshape(-1, 3)
+    out = np.zeros((xi.shape[0], 3))
+    lib().or_taus(C.byref(prm), float(h), xi.shape[0], _p(xi), _p(_c(Uv, np.float64)),
+                  _p(_c(U0v, np.float64)), _p(out))
+    return out
+
+
+def unsigned_distance(surf, xyz):
+    v = _c(surf.verts, np.float64)
+    t = _c(surf.tris, np.int32)
+    x = _c(xyz, np.float64).reshape(-1, 3)
+    out = np.zeros(x.shape[0])
+    lib().or_unsigned_dist(t.shape[0], _p(v), _p(t), x.shape[0], _p(x), _p(out))
+    return out
+
+
+def signed_distance(surf, xyz):
+    """Exact-sign distance: negative inside (labels from the exact test)."""
+    d = unsigned_distance(surf, xyz)
+    lab, _ = label_points(surf, xyz)
+    return np.where(lab == 1, -d, d)
+
+
+derive_mesh = _mesh.derive_mesh

@@ -1,0 +1,443 @@
+"""Seeded synthetic inputs: linear octrees, watertight triangle surfaces, nodal fields.
+
+This module only *generates* inputs. It holds none of the method's arithmetic:
+no node numbering, no hanging-node derivation, no quadrature, no in-out test,
+no physics. Both the CPU reference and the HIP library consume what it writes.
+
+Octree leaves are stored as a linear octree (Section "Octree based Mesh
+Generation" of the paper): integer anchors (ax, ay, az) in units of
+2**-max_level of the root side, plus a level. A leaf at level L has side
+2**(max_level - L) units. Leaves are returned sorted by the Morton key of their
+anchor (x in the lowest bit) and are 2:1 balanced across faces, edges and
+vertices.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# Morton keys (x lowest bit), 21 bits per axis
+# ---------------------------------------------------------------------------
+
+
+def _spread3(v: np.ndarray) -> np.ndarray:
+    v = v.astype(np.uint64) & np.uint64(0x1FFFFF)
+    v = (v | (v << np.uint64(32))) & np.uint64(0x1F00000000FFFF)
+    v = (v | (v << np.uint64(16))) & np.uint64(0x1F0000FF0000FF)
+    v = (v | (v << np.uint64(8))) & np.uint64(0x100F00F00F00F00F)
+    v = (v | (v << np.uint64(4))) & np.uint64(0x10C30C30C30C30C3)
+    v = (v | (v << np.uint64(2))) & np.uint64(0x1249249249249249)
+    return v
+
+
+def morton_key(x, y, z) -> np.ndarray:
+    """Interleave the bits of non-negative integer coordinates, x lowest."""
+    return _spread3(np.asarray(x)) | (_spread3(np.asarray(y)) << np.uint64(1)) | (
+        _spread3(np.asarray(z)) << np.uint64(2))
+
+
+# ---------------------------------------------------------------------------
+# Octrees
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class Octree:
+    ax: np.ndarray          # int32 anchors, units of 2**-max_level of the root side
+    ay: np.ndarray
+    az: np.ndarray
+    level: np.ndarray       # uint8
+    max_level: int
+    origin: tuple = (0.0, 0.0, 0.0)
+    root_len: float = 1.0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return int(self.ax.shape[0])
+
+    def side(self) -> np.ndarray:
+        return (np.int64(1) << (self.max_level - self.level.astype(np.int64)))
+
+
+def _sort_leaves(ax, ay, az, lev):
+    key = morton_key(ax, ay, az)
+    o = np.argsort(key, kind="stable")
+    return ax[o], ay[o], az[o], lev[o], key[o]
+
+
+def _children(ax, ay, az, lev, M):
+    half = (np.int64(1) << (M - lev.astype(np.int64) - 1))
+    cx, cy, cz, cl = [], [], [], []
+    for c in range(8):  # Morton order of children, x fastest
+        dx, dy, dz = c & 1, (c >> 1) & 1, (c >> 2) & 1
+        cx.append(ax + dx * half)
+        cy.append(ay + dy * half)
+        cz.append(az + dz * half)
+        cl.append(lev + 1)
+    return (np.concatenate(cx), np.concatenate(cy), np.concatenate(cz),
+            np.concatenate(cl).astype(np.int64))
+
+
+def uniform_octree(level: int, max_level: int | None = None, origin=(0.0, 0.0, 0.0),
+                   root_len: float = 1.0) -> Octree:
+    M = level if max_level is None else max_level
+    n = 1 << level
+    s = 1 << (M - level)
+    g = np.arange(n, dtype=np.int64) * s
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    ax, ay, az = X.ravel(), Y.ravel(), Z.ravel()
+    lev = np.full(ax.shape, level, dtype=np.int64)
+    ax, ay, az, lev, _ = _sort_leaves(ax, ay, az, lev)
+    return Octree(ax.astype(np.int32), ay.astype(np.int32), az.astype(np.int32),
+                  lev.astype(np.uint8), M, tuple(origin), float(root_len),
+                  {"kind": "uniform", "level": level})
+
+
+def _locate(keys_sorted, px, py, pz):
+    """Index of the leaf containing each integer point (leaves cover the point)."""
+    k = morton_key(px, py, pz)
+    return np.searchsorted(keys_sorted, k, side="right") - 1
+
+
+def balance_21(ax, ay, az, lev, M, ext):
+    """Split leaves until face-, edge- and vertex-neighbours differ by <= 1 level.
+
+    ext = (ex, ey, ez): the domain extent in max-level units (leaves tile
+    [0,ex) x [0,ey) x [0,ez)).
+    """
+    ax = ax.astype(np.int64); ay = ay.astype(np.int64); az = az.astype(np.int64)
+    lev = lev.astype(np.int64)
+    ex, ey, ez = ext
+    dirs = [(i, j, k) for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)
+            if (i, j, k) != (0, 0, 0)]
+    while True:
+        ax, ay, az, lev, keys = _sort_leaves(ax, ay, az, lev)
+        side = np.int64(1) << (M - lev)
+        split = np.zeros(ax.shape[0], dtype=bool)
+        for (i, j, k) in dirs:
+            nx = ax + i * side
+            ny = ay + j * side
+            nz = az + k * side
+            ok = (nx >= 0) & (ny >= 0) & (nz >= 0) & (nx < ex) & (ny < ey) & (nz < ez)
+            idx = _locate(keys, nx[ok], ny[ok], nz[ok])
+            bad = lev[idx] < (lev[ok] - 1)
+            split[idx[bad]] = True
+        if not split.any():
+            return ax, ay, az, lev
+        cx, cy, cz, cl = _children(ax[split], ay[split], az[split], lev[split], M)
+        keep = ~split
+        ax = np.concatenate([ax[keep], cx])
+        ay = np.concatenate([ay[keep], cy])
+        az = np.concatenate([az[keep], cz])
+        lev = np.concatenate([lev[keep], cl])
+
+
+def refined_octree(M: int, lmin: int, refine, ext=None, origin=(0.0, 0.0, 0.0),
+                   root_len: float = 1.0, meta=None) -> Octree:
+    """Top-down construction: start uniform at lmin, split while refine() says so.
+
+    refine(cx, cy, cz, h, level) -> bool mask, with octant centres and side in
+    physical units. Leaves are then 2:1 balanced (faces, edges, vertices).
+    """
+    if ext is None:
+        ext = (1 << M, 1 << M, 1 << M)
+    s0 = 1 << (M - lmin)
+    gx = np.arange(0, ext[0], s0, dtype=np.int64)
+    gy = np.arange(0, ext[1], s0, dtype=np.int64)
+    gz = np.arange(0, ext[2], s0, dtype=np.int64)
+    X, Y, Z = np.meshgrid(gx, gy, gz, indexing="ij")
+    ax, ay, az = X.ravel(), Y.ravel(), Z.ravel()
+    lev = np.full(ax.shape, lmin, dtype=np.int64)
+    unit = root_len / float(1 << M)
+    done = ([], [], [], [])
+    while ax.size:
+        side = (np.int64(1) << (M - lev)).astype(np.float64)
+        h = side * unit
+        cx = origin[0] + (ax + 0.5 * side) * unit
+        cy = origin[1] + (ay + 0.5 * side) * unit
+        cz = origin[2] + (az + 0.5 * side) * unit
+        m = np.asarray(refine(cx, cy, cz, h, lev), dtype=bool) & (lev < M)
+        for lst, arr in zip(done, (ax, ay, az, lev)):
+            lst.append(arr[~m])
+        ax, ay, az, lev = _children(ax[m], ay[m], az[m], lev[m], M)
+    ax, ay, az, lev = (np.concatenate(l) for l in done)
+    n_pre = int(ax.shape[0])
+    ax, ay, az, lev = balance_21(ax, ay, az, lev, M, ext)
+    ax, ay, az, lev, _ = _sort_leaves(ax, ay, az, lev)
+    md = {"kind": "refined", "n_before_balance": n_pre}
+    if meta:
+        md.update(meta)
+    return Octree(ax.astype(np.int32), ay.astype(np.int32), az.astype(np.int32),
+                  lev.astype(np.uint8), M, tuple(origin), float(root_len), md)
+
+
+def sphere_refined_octree(center, r, lmin, lmax, beta, M=None) -> Octree:
+    """Refine octants whose centre lies within beta*h of the sphere |x-c| = r."""
+    M = lmax if M is None else M
+    c = np.asarray(center, dtype=np.float64)
+
+    def refine(cx, cy, cz, h, lev):
+        d = np.sqrt((cx - c[0]) ** 2 + (cy - c[1]) ** 2 + (cz - c[2]) ** 2)
+        return (np.abs(d - r) < beta * h) & (lev < lmax)
+
+    return refined_octree(M, lmin, refine, meta={"body": "sphere", "beta": beta,
+                                                  "lmin": lmin, "lmax": lmax})
+
+
+def check_balanced(t: Octree, ext=None) -> bool:
+    """True iff all face/edge/vertex neighbours differ by at most one level."""
+    M = t.max_level
+    ext = ext or (1 << M, 1 << M, 1 << M)
+    ax, ay, az, lev = (a.astype(np.int64) for a in (t.ax, t.ay, t.az, t.level))
+    ax2, ay2, az2, lev2 = balance_21(ax, ay, az, lev, M, ext)
+    return ax2.shape[0] == ax.shape[0]
+
+
+# ---------------------------------------------------------------------------
+# Watertight surfaces (outward-oriented, counter-clockwise seen from outside)
+# ---------------------------------------------------------------------------
+
+
+@dataclass
+class Surface:
+    verts: np.ndarray   # (nv, 3) float64
+    tris: np.ndarray    # (nt, 3) int32
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n_tri(self):
+        return int(self.tris.shape[0])
+
+
+def _icosahedron():
+    p = (1.0 + math.sqrt(5.0)) / 2.0
+    v = np.array([[-1, p, 0], [1, p, 0], [-1, -p, 0], [1, -p, 0],
+                  [0, -1, p], [0, 1, p], [0, -1, -p], [0, 1, -p],
+                  [p, 0, -1], [p, 0, 1], [-p, 0, -1], [-p, 0, 1]], dtype=np.float64)
+    f = np.array([[0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11],
+                  [1, 5, 9], [5, 11, 4], [11, 10, 2], [10, 7, 6], [7, 1, 8],
+                  [3, 9, 4], [3, 4, 2], [3, 2, 6], [3, 6, 8], [3, 8, 9],
+                  [4, 9, 5], [2, 4, 11], [6, 2, 10], [8, 6, 7], [9, 8, 1]], dtype=np.int64)
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    return v, f
+
+
+def icosphere(subdiv: int, r: float, center) -> Surface:
+    v, f = _icosahedron()
+    for _ in range(subdiv):
+        verts = [row for row in v]
+        cache = {}
+
+        def mid(a, b):
+            key = (a, b) if a < b else (b, a)
+            if key not in cache:
+                m = verts[a] + verts[b]
+                verts.append(m / np.linalg.norm(m))
+                cache[key] = len(verts) - 1
+            return cache[key]
+
+        nf = []
+        for a, b, c in f:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            nf += [[a, ab, ca], [b, bc, ab], [c, ca, bc], [ab, bc, ca]]
+        v = np.array(verts)
+        f = np.array(nf, dtype=np.int64)
+    s = Surface(v * r + np.asarray(center, dtype=np.float64), f.astype(np.int32),
+                {"kind": "icosphere", "subdiv": subdiv, "r": r, "center": list(center)})
+    orient_outward(s)
+    return s
+
+
+def random_rotation(rng) -> np.ndarray:
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def ellipsoid(semi, center, rot, n_lat: int, n_lon: int) -> Surface:
+    """Latitude-longitude tessellation with pole fans: 2*n_lon*(n_lat-1) triangles."""
+    th = np.pi * (np.arange(1, n_lat) / n_lat)          # interior latitudes
+    ph = 2 * np.pi * (np.arange(n_lon) / n_lon)
+    T, P = np.meshgrid(th, ph, indexing="ij")
+    ring = np.stack([np.sin(T) * np.cos(P), np.sin(T) * np.sin(P), np.cos(T)], -1).reshape(-1, 3)
+    v = np.concatenate([[[0, 0, 1.0]], ring, [[0, 0, -1.0]]])
+    v = v * np.asarray(semi)
+    v = v @ np.asarray(rot).T + np.asarray(center)
+    tris = []
+    idx = lambda i, j: 1 + i * n_lon + (j % n_lon)
+    for j in range(n_lon):
+        tris.append([0, idx(0, j), idx(0, j + 1)])
+    for i in range(n_lat - 2):
+        for j in range(n_lon):
+            a, b, c, d = idx(i, j), idx(i, j + 1), idx(i + 1, j), idx(i + 1, j + 1)
+            tris += [[a, c, b], [b, c, d]]
+    s_ = len(v) - 1
+    for j in range(n_lon):
+        tris.append([s_, idx(n_lat - 2, j + 1), idx(n_lat - 2, j)])
+    s = Surface(v, np.array(tris, dtype=np.int32),
+                {"kind": "ellipsoid", "semi": list(map(float, semi)), "center": list(map(float, center))})
+    orient_outward(s)
+    return s
+
+
+def rounded_box(half, fillet, center, n_face: int) -> Surface:
+    """Box with rounded edges and corners (fillet radius), from a cube-surface grid.
+
+    Each point p of the cube surface [-1,1]^3 scaled to the outer box maps to
+    c + fillet * (p - c)/|p - c|, with c the closest point of the inner box
+    (half - fillet). Grid lines are graded towards the face borders.
+    """
+    half = np.asarray(half, dtype=np.float64)
+    inner = half - fillet
+    t = np.linspace(-1.0, 1.0, n_face + 1)
+    t = np.sign(t) * np.abs(t) ** 0.5 * 0.0 + t  # uniform on the unit face grid
+    verts = {}
+    vl = []
+    tris = []
+
+    def vid(p):
+        key = tuple(np.round(p, 12))
+        if key not in verts:
+            verts[key] = len(vl)
+            vl.append(p)
+        return verts[key]
+
+    for axis in range(3):
+        for sgn in (-1.0, 1.0):
+            u_ax, v_ax = [a for a in range(3) if a != axis]
+            ids = np.empty((n_face + 1, n_face + 1), dtype=np.int64)
+            for i in range(n_face + 1):
+                for j in range(n_face + 1):
+                    p = np.zeros(3)
+                    p[axis] = sgn
+                    p[u_ax] = t[i]
+                    p[v_ax] = t[j]
+                    ids[i, j] = vid(p)
+            for i in range(n_face):
+                for j in range(n_face):
+                    a, b, c, d = ids[i, j], ids[i + 1, j], ids[i, j + 1], ids[i + 1, j + 1]
+                    tris += [[a, b, d], [a, d, c]]
+    cube = np.array(vl)
+    pts = cube * half
+    cl = np.clip(pts, -inner, inner)
+    dv = pts - cl
+    nrm = np.linalg.norm(dv, axis=1, keepdims=True)
+    nrm[nrm == 0] = 1.0
+    v = cl + fillet * dv / nrm + np.asarray(center)
+    s = Surface(v, np.array(tris, dtype=np.int32),
+                {"kind": "rounded_box", "half": half.tolist(), "fillet": fillet,
+                 "center": list(map(float, center))})
+    orient_outward(s)
+    return s
+
+
+def merge_surfaces(parts) -> Surface:
+    vs, ts, off = [], [], 0
+    for p in parts:
+        vs.append(p.verts)
+        ts.append(p.tris.astype(np.int64) + off)
+        off += p.verts.shape[0]
+    return Surface(np.concatenate(vs), np.concatenate(ts).astype(np.int32),
+                   {"kind": "union", "parts": [p.meta for p in parts]})
+
+
+def signed_volume(s: Surface) -> float:
+    a, b, c = (s.verts[s.tris[:, k]] for k in range(3))
+    return float(np.einsum("ij,ij->i", a, np.cross(b, c)).sum() / 6.0)
+
+
+def orient_outward(s: Surface) -> None:
+    """Flip all triangles if the enclosed signed volume is negative (in place)."""
+    if signed_volume(s) < 0:
+        s.tris[:] = s.tris[:, [0, 2, 1]]
+
+
+def is_watertight(s: Surface) -> bool:
+    """Every directed edge appears once and its reverse appears once."""
+    t = s.tris.astype(np.int64)
+    e = np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]])
+    nv = int(t.max()) + 1
+    fwd = e[:, 0] * nv + e[:, 1]
+    rev = e[:, 1] * nv + e[:, 0]
+    if np.unique(fwd).shape[0] != fwd.shape[0]:
+        return False
+    return bool(np.isin(rev, fwd).all())
+
+
+# ---------------------------------------------------------------------------
+# Nodal fields: sum of four random Fourier modes, pressure ~ U(-1, 1)
+# ---------------------------------------------------------------------------
+
+
+def _modes(rng):
+    k = rng.integers(1, 4, size=(4, 3))
+    a = rng.normal(size=(4, 3))
+    a /= np.linalg.norm(a, axis=1, keepdims=True)
+    phi = rng.uniform(0.0, 2 * np.pi, size=4)
+    return k, a, phi
+
+
+def fourier_velocity(xyz_hat, k, a, phi):
+    arg = 2 * np.pi * (xyz_hat @ k.T) + phi          # (n, 4)
+    return np.sin(arg) @ a                             # (n, 3)
+
+
+def make_fields(node_xyz: np.ndarray, seed: int, shortest_side: float = 1.0) -> dict:
+    """Seeded nodal fields at the given node coordinates (n, 3), float64 SoA.
+
+    Draw order per seed: mode wavenumbers k in {1,2,3}^3 (4x3), unit amplitudes,
+    phases U[0, 2pi), nodal p ~ U(-1, 1). The previous-step velocity uses the same
+    recipe with seed + 10000.
+    """
+    xh = np.asarray(node_xyz, dtype=np.float64) / shortest_side
+    n = xh.shape[0]
+    rng = np.random.default_rng(seed)
+    k, a, phi = _modes(rng)
+    p = rng.uniform(-1.0, 1.0, size=n)
+    u = fourier_velocity(xh, k, a, phi)
+    rng0 = np.random.default_rng(seed + 10000)
+    k0, a0, phi0 = _modes(rng0)
+    u0 = fourier_velocity(xh, k0, a0, phi0)
+    c = np.ascontiguousarray
+    return {"ux": c(u[:, 0]), "uy": c(u[:, 1]), "uz": c(u[:, 2]), "p": c(p),
+            "ux0": c(u0[:, 0]), "uy0": c(u0[:, 1]), "uz0": c(u0[:, 2])}
+
+
+FIELD_NAMES = ("ux", "uy", "uz", "p", "ux0", "uy0", "uz0")
+
+# Physical parameters shared by every workload (rho, mu, dt, theta, C_t, C_I)
+DEFAULT_PARAMS = dict(rho=1.0, mu=0.01, dt=0.01, theta=0.5, c_t=4.0, c_i=36.0)
+
+# Non-dyadic offset of the immersed bodies, so that no grid line or sub-cell
+# Gauss point coordinate coincides with a surface vertex plane.
+BODY_OFFSET = (1e-6 * math.pi, 1e-6 * math.e, 1e-6 * math.sqrt(2.0))
+
+
+def sphere_workload(lmin=5, lmax=8, beta=4.0, subdiv=4, r=0.1):
+    """Immersed sphere at the cube centre (plus a non-dyadic offset)."""
+    c = tuple(0.5 + o for o in BODY_OFFSET)
+    tree = sphere_refined_octree(c, r, lmin, lmax, beta)
+    surf = icosphere(subdiv, r, c)
+    return tree, surf
+
+
+def box_surface(lo, hi) -> Surface:
+    """Axis-aligned box as 12 outward triangles."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    v = np.array([[hi[0] if c & 1 else lo[0], hi[1] if c & 2 else lo[1], hi[2] if c & 4 else lo[2]]
+                  for c in range(8)])
+    quads = [(0, 2, 6, 4), (1, 5, 7, 3), (0, 4, 5, 1), (2, 3, 7, 6), (0, 1, 3, 2), (4, 6, 7, 5)]
+    t = []
+    for a, b, c, d in quads:
+        t += [[a, b, c], [a, c, d]]
+    s = Surface(v, np.array(t, np.int32), {"kind": "box", "lo": lo.tolist(), "hi": hi.tolist()})
+    orient_outward(s)
+    return s
