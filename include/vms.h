@@ -1,0 +1,222 @@
+/*
+ * libvms — C-ABI of the MI355X VMS assembly and in-out hot path.
+ *
+ * The method is the immersogeometric variational-multiscale (VMS) finite
+ * element assembly of Saurabh et al., "Industrial scale large eddy
+ * simulations with adaptive octree meshes using immersogeometric analysis"
+ * (arXiv 2009.00706):
+ *   - residual of the VMS weak form, eq. (vms), with the fine scales u' and p'
+ *     of eqs. (uprime) and (pprime), and its Jacobian (matrix assembly,
+ *     Alg. 2 and Alg. 6), for trilinear hexahedral octants, 2x2x2 Gauss points;
+ *   - hanging-node constraints M_e of Alg. 3, scattered into a global CSR;
+ *   - element markers IN / OUT / INTERCEPTED (Alg. 4) and exact in-out tests
+ *     of quadrature points (the ground truth that Alg. 5 and ray tracing
+ *     approximate);
+ *   - adaptive sub-cell quadrature of INTERCEPTED elements (Section
+ *     "Adaptive Quadrature" and the caption of its Gauss-point figure).
+ *
+ * Conventions shared by every entry point:
+ *   - every function returns an int status (VMS_OK or a negative code) and
+ *     never throws; vms_last_error() gives a message;
+ *   - "host" pointers are read during the call only; "device" pointers are
+ *     HIP device memory owned by the caller (the library never frees them);
+ *   - dof numbering: dof = 4*node + c, c in (ux, uy, uz, p); independent nodes
+ *     are numbered by the Morton key of their integer coordinates at
+ *     resolution 2^max_level (x in the lowest bit); hanging vertices are not
+ *     nodes;
+ *   - CSR: rows ascending, columns ascending within a row, full 4x4 blocks
+ *     for every node pair coupled by a non-IN element, plus every node's
+ *     diagonal block; row_ptr is int64, col_idx int32;
+ *   - signs: R = B^VMS - F^VMS with F = 0 (eq. ALE-VMS-form); J = dR/dU at the
+ *     new time level, with tau_M, tau_C and taubar frozen at the current state;
+ *   - nodes that receive no contribution from a non-IN element get an
+ *     identity diagonal block and a zero residual; no boundary condition is
+ *     imposed otherwise;
+ *   - calls enqueue work on the context's stream and return; outputs are
+ *     valid once the caller synchronises that stream. A context is bound to
+ *     one stream and is not thread-safe.
+ */
+#ifndef VMS_H
+#define VMS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vms_ctx vms_ctx; /* opaque */
+
+/* status codes */
+enum {
+    VMS_OK = 0,
+    VMS_EINVAL = -1,      /* bad argument (null pointer, size, NaN parameter, dt <= 0) */
+    VMS_EMESH = -2,       /* octree not 2:1 balanced, chained constraint, surface not watertight */
+    VMS_EHIP = -3,        /* a HIP runtime call failed */
+    VMS_ENOMEM = -4,      /* device allocation failed */
+    VMS_EOVERFLOW = -5,   /* a device-side capacity was exceeded */
+    VMS_EUNSUPPORTED = -6 /* option outside what this build implements */
+};
+
+/* arithmetic of the element contractions (vms_params.precision) */
+enum {
+    VMS_FP64 = 0,       /* everything FP64; CSR values are double */
+    VMS_MIXED_BF16 = 1, /* B^T D B on BF16 MFMA, FP32 accumulate; CSR values are float */
+    VMS_MIXED_FP16 = 2  /* B^T D B on FP16 MFMA, FP32 accumulate; CSR values are float */
+};
+
+/* in-out test of quadrature points (inout_classify mode) */
+enum {
+    VMS_INOUT_EXACT = 0,  /* exact segment parity with exact orientation predicates */
+    VMS_INOUT_LEARNED = 1 /* learned signed-distance filter, exact test inside the margin */
+};
+
+/* vms_assemble flags */
+enum {
+    VMS_RELABEL = 1u  /* recompute sub-cell quadrature points and their labels first */
+};
+
+/* vms_export selectors (all written to HOST memory, sizes from vms_sizes) */
+enum {
+    VMS_EXPORT_NODE_XYZ = 1,   /* int32 [3][n_nodes] integer coordinates (SoA) */
+    VMS_EXPORT_ROW_PTR = 2,    /* int64 [n_rows + 1] */
+    VMS_EXPORT_COL_IDX = 3,    /* int32 [nnz] */
+    VMS_EXPORT_MARKERS = 4,    /* uint8 [n_oct]: 0 OUT, 1 IN, 2 INTERCEPTED */
+    VMS_EXPORT_VERTEX_LAB = 5, /* uint8 [n_oct][8]: label of each element corner (0 OUT, 1 IN) */
+    VMS_EXPORT_SUBGP = 6,      /* int64 [n_subgp] element, int32 [n_subgp] key, uint8 [n_subgp]
+                                  level, double [n_subgp][3] xyz; canonical order (elements
+                                  ascending, depth-first, children and Gauss points x fastest) */
+    VMS_EXPORT_MASTERS = 7     /* int32 [n_oct][8] master nodes per element slot (-1 unused) */
+};
+
+/* Linear octree leaves, HOST pointers (copied at vms_create). A leaf at level L
+ * has anchor (ax, ay, az) in units of 2^-max_level of the root side and side
+ * 2^(max_level - L) units; physical x = origin + root_len * (integer / 2^max_level).
+ * Leaves must not overlap and must be 2:1 balanced across faces, edges and
+ * vertices (Section "Octree based Mesh Generation"). max_level <= 20. */
+typedef struct {
+    int64_t n_oct;
+    const int32_t *ax, *ay, *az;
+    const uint8_t *level;
+    int32_t max_level;
+    int32_t pad;
+    double origin[3];
+    double root_len;
+} vms_octree;
+
+/* Closed, watertight, consistently outward-oriented triangle surface, HOST
+ * pointers: verts [n_vert][3] interleaved, tri [n_tri][3] (counter-clockwise
+ * seen from outside). */
+typedef struct {
+    int32_t n_vert, n_tri;
+    const double *verts;
+    const int32_t *tri;
+} vms_surface;
+
+/* Physical and discretisation parameters. theta = 1/2 is Crank-Nicolson (the
+ * paper's remark on time stepping); tau_M = (c_t/dt^2 + u.G.u + c_i nu^2 G:G)^-1/2,
+ * tau_C = 1/(tau_M tr G), taubar = (u'.G.u')^-1/2 with G = (2/h)^2 I.
+ * quad_depth is the maximum split level of the adaptive quadrature (0..3). */
+typedef struct {
+    double rho, mu, dt, theta, c_t, c_i;
+    int32_t quad_depth;
+    uint32_t precision; /* VMS_FP64 | VMS_MIXED_BF16 | VMS_MIXED_FP16 */
+} vms_params;
+
+/* Nodal fields, DEVICE pointers, SoA over independent nodes (length n_nodes):
+ * new-level velocity and pressure, previous-level velocity. */
+typedef struct {
+    const double *ux, *uy, *uz, *p, *ux0, *uy0, *uz0;
+} vms_fields;
+
+/* Create a context: derives vertices, hanging constraints (Alg. 3) and nodes on
+ * the host; if surf is non-null, labels every corner exactly and sets element
+ * markers (Alg. 4), gathers the background triangles of each INTERCEPTED
+ * element and generates its adaptive sub-cell quadrature points (device);
+ * builds the CSR pattern. stream is a hipStream_t (0 = null stream).
+ * Errors: VMS_EINVAL, VMS_EMESH (unbalanced tree, chained constraint, surface
+ * not watertight), VMS_EUNSUPPORTED (quad_depth > 3, max_level > 20),
+ * VMS_ENOMEM, VMS_EHIP. On error *out is null. */
+int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
+               const vms_params *prm, void *stream);
+
+/* Sizes of the derived mesh: independent nodes, rows (= 4 n_nodes), nonzeros,
+ * kept sub-cell quadrature points. Any pointer may be null. Synchronises the
+ * stream; reports VMS_EOVERFLOW if a device-side capacity was exceeded. */
+int vms_sizes(vms_ctx *ctx, int64_t *n_nodes, int64_t *n_rows, int64_t *nnz, int64_t *n_subgp);
+
+/* Copy a derived quantity to HOST memory dst (see VMS_EXPORT_*). For
+ * VMS_EXPORT_SUBGP dst must hold n_subgp * (8 + 4 + 1 + 24) bytes, laid out
+ * as the four arrays one after the other. */
+int vms_export(vms_ctx *ctx, uint32_t what, void *dst);
+
+/* Matrix and vector assembly (Alg. 1 element loop, Alg. 2, Alg. 6):
+ * csr_vals (DEVICE, nnz entries, double for VMS_FP64 else float) receives the
+ * Jacobian, resid (DEVICE, n_rows doubles, nullable) the residual. Both are
+ * overwritten (zeroed first). OUT elements use the 2x2x2 Gauss points,
+ * INTERCEPTED elements their kept sub-cell points, IN elements nothing. */
+int vms_assemble(vms_ctx *ctx, const vms_fields *f, void *csr_vals, double *resid,
+                 uint32_t flags);
+
+/* Vector assembly only: resid (DEVICE, n_rows doubles) is overwritten. If
+ * norm2 (HOST) is non-null the call synchronises and stores ||resid||_2,
+ * reduced in FP64 on the device. */
+int vms_apply(vms_ctx *ctx, const vms_fields *f, double *resid, double *norm2);
+
+/* Exact in-out labels of n points against a surface (Alg. 5's question,
+ * answered exactly): px, py, pz DEVICE arrays of n doubles, labels DEVICE
+ * uint8 (1 IN or on the surface, 0 OUT). mode VMS_INOUT_EXACT, or
+ * VMS_INOUT_LEARNED with mlp a DEVICE pointer to a vms_mlp (points whose
+ * |prediction| >= margin take the network's sign, the rest the exact test).
+ * The surface's acceleration structure is built on the host at each call
+ * unless a context-free cache handle is used (see inout_prepare).
+ * stream is a hipStream_t. */
+int inout_classify(const vms_surface *surf, const double *px, const double *py, const double *pz,
+                   int64_t n, uint8_t *labels, uint32_t mode, const void *mlp, void *stream);
+
+/* Reusable in-out handle: the surface's acceleration structure built once
+ * (host pointers read during the call; device memory owned by the handle).
+ * inout_classify_prepared has the semantics of inout_classify without any
+ * allocation; the handle is bound to stream. */
+typedef struct inout_handle inout_handle;
+int inout_prepare(const vms_surface *surf, void *stream, inout_handle **out);
+int inout_classify_prepared(inout_handle *h, const double *px, const double *py, const double *pz,
+                            int64_t n, uint8_t *labels, uint32_t mode, const void *mlp);
+void inout_release(inout_handle *h);
+
+/* Host-only mesh derivation (no device involved): the node numbering,
+ * hanging constraints and CSR pattern that vms_create derives, for checks on
+ * machines without a GPU. markers (HOST, nullable) excludes IN elements
+ * (marker 1) from the pattern. vms_mesh_export accepts VMS_EXPORT_NODE_XYZ,
+ * _ROW_PTR, _COL_IDX and _MASTERS with the layouts of vms_export. */
+typedef struct vms_mesh vms_mesh;
+int vms_mesh_create(vms_mesh **out, const vms_octree *tree, const uint8_t *markers);
+int vms_mesh_sizes(vms_mesh *h, int64_t *n_nodes, int64_t *nnz, int64_t *n_hanging);
+int vms_mesh_export(vms_mesh *h, uint32_t what, void *dst);
+void vms_mesh_destroy(vms_mesh *h);
+
+/* Per-stage timing with HIP events recorded on the context stream (off by
+ * default). vms_last_timing synchronises on the last recorded event and
+ * writes HOST ms[4]: relabelling (sub-cell quadrature and in-out tests),
+ * zeroing and identity rows, OUT-element assembly kernel, INTERCEPTED-element
+ * assembly kernel, of the last vms_assemble / vms_apply. */
+int vms_set_timing(vms_ctx *ctx, int on);
+int vms_last_timing(vms_ctx *ctx, float *ms);
+
+/* Counters of a context (HOST out[6]): OUT elements, INTERCEPTED elements,
+ * points labelled by the last sub-cell quadrature, degenerate directions
+ * abandoned, hanging vertices, kept sub-cell points. */
+int vms_stats(vms_ctx *ctx, int64_t *out);
+
+/* Message of the last error on ctx (or of the last failed vms_create /
+ * inout_classify when ctx is null). Never null. */
+const char *vms_last_error(vms_ctx *ctx);
+
+/* Free the context's device memory. Accepts null. */
+void vms_destroy(vms_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VMS_H */

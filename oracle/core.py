@@ -220,11 +220,20 @@ def std_points(h):
     return xi, np.full(8, (h / 2.0) ** 3)
 
 
-def point_lists(tree, mk, sub, depth):
-    """Per element: 8 Gauss points for OUT, kept sub-cell points for INTERCEPTED, none for IN."""
+def point_lists(tree, mk, sub, depth, subset=None):
+    """Per element: 8 Gauss points for OUT, kept sub-cell points for INTERCEPTED, none for IN.
+
+    subset: optional element indices; the other elements get no points."""
     E = tree.n
     h = element_h(tree)
-    counts = np.where(mk == OUT, 8, 0).astype(np.int64)
+    keep = np.ones(E, bool)
+    if subset is not None:
+        keep = np.zeros(E, bool)
+        keep[np.asarray(subset, np.int64)] = True
+        if sub is not None and sub["el"].size:
+            sel = keep[sub["el"]]
+            sub = {k: (v[sel] if isinstance(v, np.ndarray) else v) for k, v in sub.items()}
+    counts = np.where((mk == OUT) & keep, 8, 0).astype(np.int64)
     if sub is not None and sub["el"].size:
         np.add.at(counts, sub["el"], 1)
     off = np.zeros(E + 1, np.int64)
@@ -232,7 +241,7 @@ def point_lists(tree, mk, sub, depth):
     xi = np.zeros((off[-1], 3))
     w = np.zeros(off[-1])
     sxi = np.array([[XI if (g >> k) & 1 else -XI for k in range(3)] for g in range(8)])
-    outs = np.nonzero(mk == OUT)[0]
+    outs = np.nonzero((mk == OUT) & keep)[0]
     for g in range(8):
         xi[off[outs] + g] = sxi[g]
         w[off[outs] + g] = (h[outs] / 2.0) ** 3
@@ -250,7 +259,7 @@ def point_lists(tree, mk, sub, depth):
 
 
 def assemble(tree, ms, fields, prm=None, mk=None, sub=None, depth=3, vals=True, resid=True,
-             el_range=None):
+             el_range=None, subset=None):
     """Global Jacobian values (CSR of ``ms``) and residual, FP64.
 
     Inactive nodes (no contribution from any non-IN element) get an identity
@@ -258,7 +267,7 @@ def assemble(tree, ms, fields, prm=None, mk=None, sub=None, depth=3, vals=True, 
     prm = prm or params()
     E = tree.n
     mk = np.zeros(E, np.uint8) if mk is None else mk
-    off, xi, w = point_lists(tree, mk, sub, depth)
+    off, xi, w = point_lists(tree, mk, sub, depth, subset)
     h = element_h(tree)
     Cm = _c(ms.C, np.float64)
     V = np.zeros(ms.nnz) if vals else None
@@ -272,7 +281,7 @@ def assemble(tree, ms, fields, prm=None, mk=None, sub=None, depth=3, vals=True, 
                            _p(ms.row_ptr), _p(ms.col_idx), _p(V), _p(R), b, e)
     if rc != 0:
         raise RuntimeError(f"pattern misses an entry of element {-rc - 1}")
-    if el_range is None and V is not None:
+    if el_range is None and subset is None and V is not None:
         inact = np.nonzero(~ms.node_active)[0]
         for n in inact:
             for c in range(4):

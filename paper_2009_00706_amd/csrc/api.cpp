@@ -1,0 +1,903 @@
+// C-ABI of libvms: context creation (host mesh derivation, device setup of
+// labels, markers and sub-cell quadrature), assembly launches, exports.
+#include "../../include/vms.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "geom.h"
+#include "kernels.h"
+#include "mesh.h"
+#include "mlp.h"
+
+using vmsk::SurfDev;
+
+namespace {
+
+std::mutex g_err_mu;
+std::string g_err = "no error";
+
+void set_global_err(const std::string &s) {
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    g_err = s;
+}
+
+struct DevBuf {
+    std::vector<void *> ptrs;
+    ~DevBuf() { release(); }
+    void release() {
+        for (void *p : ptrs) (void)hipFree(p);
+        ptrs.clear();
+    }
+    template <typename T>
+    hipError_t alloc(T **p, size_t n) {
+        *p = nullptr;
+        if (n == 0) n = 1;
+        hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+        if (e == hipSuccess) ptrs.push_back(*p);
+        return e;
+    }
+};
+
+// Surface on the device plus its host-side description.
+struct SurfaceHost {
+    SurfDev S{};
+    DevBuf buf;
+    std::vector<double> tv, tbox;  // host copies (background-triangle gathering)
+    double lo[3], hi[3];
+};
+
+int check_watertight(const vms_surface *s, std::string &err) {
+    const int64_t nt = s->n_tri;
+    std::vector<uint64_t> fwd;
+    fwd.reserve(3 * nt);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int k = 0; k < 3; ++k) {
+            int64_t a = s->tri[3 * t + k], b = s->tri[3 * t + (k + 1) % 3];
+            if (a < 0 || b < 0 || a >= s->n_vert || b >= s->n_vert || a == b) {
+                err = "triangle with an invalid vertex index";
+                return VMS_EINVAL;
+            }
+            fwd.push_back(((uint64_t)a << 32) | (uint64_t)b);
+        }
+    std::sort(fwd.begin(), fwd.end());
+    for (size_t i = 1; i < fwd.size(); ++i)
+        if (fwd[i] == fwd[i - 1]) { err = "surface not consistently oriented (repeated edge)"; return VMS_EMESH; }
+    for (uint64_t e : fwd) {
+        uint64_t r = ((e & 0xffffffffull) << 32) | (e >> 32);
+        if (!std::binary_search(fwd.begin(), fwd.end(), r)) {
+            err = "surface not watertight (edge without its opposite)";
+            return VMS_EMESH;
+        }
+    }
+    return VMS_OK;
+}
+
+// bin index, the same arithmetic as the device query
+inline int host_bin(double v, double v0, double inv, int n) {
+    volatile double d = v - v0;
+    volatile double t = d * inv;
+    int b = (int)std::floor(t);
+    return b < 0 ? 0 : (b >= n ? n - 1 : b);
+}
+
+int build_surface(const vms_surface *s, hipStream_t st, SurfaceHost &H, std::string &err) {
+    if (!s || s->n_tri <= 0 || s->n_vert <= 0 || !s->verts || !s->tri) {
+        err = "empty or null surface";
+        return VMS_EINVAL;
+    }
+    int rc = check_watertight(s, err);
+    if (rc) return rc;
+    const int64_t nt = s->n_tri;
+    H.tv.resize(9 * nt);
+    H.tbox.resize(6 * nt);
+    for (int k = 0; k < 3; ++k) { H.lo[k] = INFINITY; H.hi[k] = -INFINITY; }
+    for (int64_t v = 0; v < s->n_vert; ++v)
+        for (int k = 0; k < 3; ++k) {
+            double x = s->verts[3 * v + k];
+            if (!std::isfinite(x)) { err = "non-finite surface vertex"; return VMS_EINVAL; }
+            H.lo[k] = std::min(H.lo[k], x);
+            H.hi[k] = std::max(H.hi[k], x);
+        }
+    for (int64_t t = 0; t < nt; ++t) {
+        for (int c = 0; c < 3; ++c)
+            for (int k = 0; k < 3; ++k) H.tv[9 * t + 3 * c + k] = s->verts[3 * s->tri[3 * t + c] + k];
+        for (int k = 0; k < 3; ++k) {
+            double a = H.tv[9 * t + k], b = H.tv[9 * t + 3 + k], c = H.tv[9 * t + 6 + k];
+            H.tbox[6 * t + k] = std::min(a, std::min(b, c));
+            H.tbox[6 * t + 3 + k] = std::max(a, std::max(b, c));
+        }
+    }
+    // (y, z) bins for +x rays
+    int nb = (int)std::ceil(std::sqrt((double)nt));
+    nb = std::max(1, std::min(nb, 1024));
+    SurfDev &S = H.S;
+    S.n_tri = (int32_t)nt;
+    S.nby = S.nbz = nb;
+    for (int k = 0; k < 3; ++k) { S.lo[k] = H.lo[k]; S.hi[k] = H.hi[k]; }
+    S.y0 = H.lo[1];
+    S.z0 = H.lo[2];
+    double wy = H.hi[1] - H.lo[1], wz = H.hi[2] - H.lo[2];
+    S.iny = wy > 0 ? nb / wy : 0.0;
+    S.inz = wz > 0 ? nb / wz : 0.0;
+    std::vector<int32_t> cnt((size_t)nb * nb + 1, 0);
+    auto range = [&](int64_t t, int &y0, int &y1, int &z0, int &z1) {
+        y0 = host_bin(H.tbox[6 * t + 1], S.y0, S.iny, nb);
+        y1 = host_bin(H.tbox[6 * t + 4], S.y0, S.iny, nb);
+        z0 = host_bin(H.tbox[6 * t + 2], S.z0, S.inz, nb);
+        z1 = host_bin(H.tbox[6 * t + 5], S.z0, S.inz, nb);
+    };
+    for (int64_t t = 0; t < nt; ++t) {
+        int y0, y1, z0, z1;
+        range(t, y0, y1, z0, z1);
+        for (int z = z0; z <= z1; ++z)
+            for (int y = y0; y <= y1; ++y) cnt[(size_t)z * nb + y + 1]++;
+    }
+    for (size_t i = 1; i < cnt.size(); ++i) cnt[i] += cnt[i - 1];
+    std::vector<int32_t> ids(cnt.back());
+    std::vector<int32_t> fillp(cnt.begin(), cnt.end() - 1);
+    for (int64_t t = 0; t < nt; ++t) {
+        int y0, y1, z0, z1;
+        range(t, y0, y1, z0, z1);
+        for (int z = z0; z <= z1; ++z)
+            for (int y = y0; y <= y1; ++y) ids[fillp[(size_t)z * nb + y]++] = (int32_t)t;
+    }
+    double *dtv, *dtb;
+    int32_t *doff, *dids;
+    if (H.buf.alloc(&dtv, H.tv.size()) || H.buf.alloc(&dtb, H.tbox.size()) ||
+        H.buf.alloc(&doff, cnt.size()) || H.buf.alloc(&dids, ids.size())) {
+        err = "device allocation failed (surface)";
+        return VMS_ENOMEM;
+    }
+    if (hipMemcpyAsync(dtv, H.tv.data(), H.tv.size() * 8, hipMemcpyHostToDevice, st) ||
+        hipMemcpyAsync(dtb, H.tbox.data(), H.tbox.size() * 8, hipMemcpyHostToDevice, st) ||
+        hipMemcpyAsync(doff, cnt.data(), cnt.size() * 4, hipMemcpyHostToDevice, st) ||
+        (ids.size() && hipMemcpyAsync(dids, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, st)) ||
+        hipStreamSynchronize(st)) {
+        err = "device copy failed (surface)";
+        return VMS_EHIP;
+    }
+    S.tv = dtv;
+    S.tbox = dtb;
+    S.bin_off = doff;
+    S.bin_tri = dids;
+    return VMS_OK;
+}
+
+}  // namespace
+
+struct vms_ctx {
+    hipStream_t stream = nullptr;
+    std::string err = "no error";
+    vms_params prm{};
+    double origin[3] = {0, 0, 0};
+    double root_len = 1.0;
+    int max_level = 0;
+    vms::MeshHost mesh;
+    std::vector<int32_t> ax, ay, az;
+    std::vector<uint8_t> level, markers, corner_lab;
+    bool has_surf = false;
+    SurfaceHost surf;
+    DevBuf buf;
+    // element data
+    int32_t *d_masters = nullptr;
+    uint32_t *d_ccode = nullptr;
+    uint8_t *d_hang = nullptr, *d_level = nullptr;
+    int64_t *d_rowbase = nullptr;
+    int32_t *d_rowlen = nullptr;
+    uint16_t *d_kk = nullptr;
+    int64_t n_std = 0;
+    int32_t *d_std = nullptr;
+    // intercepted elements and their sub-cell points
+    int64_t n_sq = 0;
+    std::vector<int32_t> sq_el;
+    std::vector<int32_t> sq_cnt;
+    std::vector<int64_t> sq_off;
+    int32_t *d_sq_el = nullptr, *d_sq_ax = nullptr, *d_sq_ay = nullptr, *d_sq_az = nullptr;
+    uint8_t *d_sq_level = nullptr, *d_sq_clab = nullptr;
+    int64_t *d_bt_off = nullptr;
+    int32_t *d_bt_ids = nullptr;
+    int32_t *d_sq_cnt = nullptr;
+    int64_t *d_sq_off = nullptr;
+    uint32_t *d_entries = nullptr;
+    int64_t n_subgp = 0;
+    // identity rows of inactive nodes
+    int64_t n_ones = 0;
+    int64_t *d_ones = nullptr;
+    unsigned long long *d_counters = nullptr;  // 0: labelled points, 1: degenerate directions
+    unsigned int *d_flag = nullptr;            // device-side overflow flag
+    double *d_norm = nullptr;
+    // optional per-stage timing with events on the context stream
+    bool timing = false;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    uint64_t n_labelled = 0, n_degenerate = 0;
+};
+
+namespace {
+
+int fail(vms_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    set_global_err(msg);
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(ctx, VMS_EHIP, std::string("HIP error: ") + hipGetErrorString(e_) + \
+                                           " at " #expr);                                    \
+    } while (0)
+
+template <typename T>
+int upload(vms_ctx *c, T **dst, const std::vector<T> &src) {
+    if (c->buf.alloc(dst, src.size())) return fail(c, VMS_ENOMEM, "device allocation failed");
+    if (!src.empty())
+        HIPCHK(c, hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice,
+                                 c->stream));
+    return VMS_OK;
+}
+
+bool params_ok(const vms_params *p, std::string &why) {
+    const double v[6] = {p->rho, p->mu, p->dt, p->theta, p->c_t, p->c_i};
+    for (double x : v)
+        if (!std::isfinite(x)) { why = "non-finite parameter"; return false; }
+    if (p->rho <= 0 || p->dt <= 0 || p->mu < 0 || p->c_t <= 0 || p->c_i < 0 || p->theta < 0 ||
+        p->theta > 1) {
+        why = "parameter out of range (rho > 0, dt > 0, mu >= 0, c_t > 0, c_i >= 0, 0 <= theta <= 1)";
+        return false;
+    }
+    return true;
+}
+
+// background triangles of the listed elements: every triangle whose box meets
+// the closed element box (same coordinate formula as the device)
+void gather_bt(vms_ctx *c, std::vector<int64_t> &off, std::vector<int32_t> &ids) {
+    const SurfaceHost &H = c->surf;
+    const int64_t nt = H.S.n_tri;
+    const int nb = std::max(1, std::min(256, (int)std::ceil(std::cbrt((double)nt) * 2)));
+    double inv[3];
+    for (int k = 0; k < 3; ++k) {
+        double w = H.hi[k] - H.lo[k];
+        inv[k] = w > 0 ? nb / w : 0.0;
+    }
+    auto bin = [&](double v, int k) { return host_bin(v, H.lo[k], inv[k], nb); };
+    std::vector<int32_t> cnt((size_t)nb * nb * nb + 1, 0);
+    for (int pass = 0; pass < 2; ++pass) {
+        static thread_local std::vector<int32_t> fillp;
+        if (pass == 1) fillp.assign(cnt.begin(), cnt.end() - 1);
+        static thread_local std::vector<int32_t> cell_ids;
+        if (pass == 1) cell_ids.assign(cnt.back(), 0);
+        for (int64_t t = 0; t < nt; ++t) {
+            int r0[3], r1[3];
+            for (int k = 0; k < 3; ++k) { r0[k] = bin(H.tbox[6 * t + k], k); r1[k] = bin(H.tbox[6 * t + 3 + k], k); }
+            for (int z = r0[2]; z <= r1[2]; ++z)
+                for (int y = r0[1]; y <= r1[1]; ++y)
+                    for (int x = r0[0]; x <= r1[0]; ++x) {
+                        size_t cell = ((size_t)z * nb + y) * nb + x;
+                        if (pass == 0) cnt[cell + 1]++;
+                        else cell_ids[fillp[cell]++] = (int32_t)t;
+                    }
+        }
+        if (pass == 0) {
+            for (size_t i = 1; i < cnt.size(); ++i) cnt[i] += cnt[i - 1];
+            continue;
+        }
+        const int M = c->max_level;
+        const double sc = std::ldexp(1.0, -M);
+        off.assign(c->n_sq + 1, 0);
+        ids.clear();
+        std::vector<int32_t> cand;
+        for (int64_t i = 0; i < c->n_sq; ++i) {
+            const int e = c->sq_el[i];
+            const int64_t s = (int64_t)1 << (M - c->level[e]);
+            const int64_t A[3] = {c->ax[e], c->ay[e], c->az[e]};
+            double lo[3], hi[3];
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = vmsd::point_coord(c->origin[k], c->root_len, sc, A[k], 0, 0.0);
+                hi[k] = vmsd::point_coord(c->origin[k], c->root_len, sc, A[k] + s, 0, 0.0);
+            }
+            int r0[3], r1[3];
+            bool outside = false;
+            for (int k = 0; k < 3; ++k) {
+                if (hi[k] < H.lo[k] || lo[k] > H.hi[k]) outside = true;
+                r0[k] = bin(lo[k], k);
+                r1[k] = bin(hi[k], k);
+            }
+            cand.clear();
+            if (!outside)
+                for (int z = r0[2]; z <= r1[2]; ++z)
+                    for (int y = r0[1]; y <= r1[1]; ++y)
+                        for (int x = r0[0]; x <= r1[0]; ++x) {
+                            size_t cell = ((size_t)z * nb + y) * nb + x;
+                            for (int32_t j = cnt[cell]; j < cnt[cell + 1]; ++j) cand.push_back(cell_ids[j]);
+                        }
+            std::sort(cand.begin(), cand.end());
+            cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+            for (int32_t t : cand) {
+                bool meet = true;
+                for (int k = 0; k < 3 && meet; ++k)
+                    if (H.tbox[6 * t + 3 + k] < lo[k] || H.tbox[6 * t + k] > hi[k]) meet = false;
+                if (meet) ids.push_back(t);
+            }
+            off[i + 1] = (int64_t)ids.size();
+        }
+    }
+}
+
+// sub-cell quadrature on the device. At creation: count pass, offsets on the
+// host, fill pass. On relabelling: the fill pass alone, which recomputes every
+// label and verifies each element's point count on the device (a mismatch sets
+// the overflow flag, reported by vms_sizes); no host synchronisation.
+int run_subquad(vms_ctx *c, bool first) {
+    if (c->n_sq == 0) return VMS_OK;
+    vmsk::GeoArgs g{};
+    for (int k = 0; k < 3; ++k) g.origin[k] = c->origin[k];
+    g.root_len = c->root_len;
+    g.max_level = c->max_level;
+    g.depth = c->prm.quad_depth;
+    vmsk::SubqArgs a{};
+    a.n = c->n_sq;
+    a.el = c->d_sq_el;
+    a.ax = c->d_sq_ax; a.ay = c->d_sq_ay; a.az = c->d_sq_az;
+    a.level = c->d_sq_level;
+    a.corner_lab = c->d_sq_clab;
+    a.bt_off = c->d_bt_off;
+    a.bt_ids = c->d_bt_ids;
+    a.cnt = c->d_sq_cnt;
+    a.nlabel = c->d_counters;
+    a.ndeg = c->d_counters + 1;
+    a.flag = c->d_flag;
+    if (first) {
+        HIPCHK(c, hipMemsetAsync(c->d_counters, 0, 2 * sizeof(unsigned long long), c->stream));
+        vmsk::launch_subquad(c->stream, c->surf.S, g, a, 0);
+        HIPCHK(c, hipGetLastError());
+        std::vector<int32_t> cnt(c->n_sq);
+        HIPCHK(c, hipMemcpyAsync(cnt.data(), c->d_sq_cnt, c->n_sq * 4, hipMemcpyDeviceToHost, c->stream));
+        unsigned long long ctr[2];
+        HIPCHK(c, hipMemcpyAsync(ctr, c->d_counters, sizeof ctr, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->n_labelled = ctr[0];
+        c->n_degenerate = ctr[1];
+        std::vector<int64_t> off(c->n_sq + 1, 0);
+        for (int64_t i = 0; i < c->n_sq; ++i) off[i + 1] = off[i] + cnt[i];
+        c->sq_cnt = cnt;
+        c->sq_off = off;
+        c->n_subgp = off.back();
+        if (upload(c, &c->d_sq_off, off)) return VMS_ENOMEM;
+        if (c->buf.alloc(&c->d_entries, (size_t)std::max<int64_t>(1, c->n_subgp)))
+            return fail(c, VMS_ENOMEM, "device allocation failed (sub-cell points)");
+    }
+    a.off = c->d_sq_off;
+    a.entries = c->d_entries;
+    vmsk::launch_subquad(c->stream, c->surf.S, g, a, 1);
+    HIPCHK(c, hipGetLastError());
+    return VMS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *vms_last_error(vms_ctx *ctx) {
+    if (ctx) return ctx->err.c_str();
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    return g_err.c_str();
+}
+
+void vms_destroy(vms_ctx *ctx) {
+    if (!ctx) return;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (hipEvent_t &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
+               const vms_params *prm, void *stream) {
+    if (!out) return fail(nullptr, VMS_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (!tree || !prm || !tree->ax || !tree->ay || !tree->az || !tree->level || tree->n_oct <= 0)
+        return fail(nullptr, VMS_EINVAL, "null or empty octree");
+    if (tree->max_level < 0 || tree->max_level > 20)
+        return fail(nullptr, VMS_EUNSUPPORTED, "max_level must be in [0, 20]");
+    if (tree->n_oct >= ((int64_t)1 << 31)) return fail(nullptr, VMS_EUNSUPPORTED, "more than 2^31 octants");
+    std::string why;
+    if (!params_ok(prm, why)) return fail(nullptr, VMS_EINVAL, why);
+    if (prm->quad_depth < 0 || prm->quad_depth > 3)
+        return fail(nullptr, VMS_EUNSUPPORTED, "quad_depth must be in [0, 3]");
+    if (prm->precision > VMS_MIXED_FP16) return fail(nullptr, VMS_EUNSUPPORTED, "unknown precision");
+    if (prm->precision != VMS_FP64) return fail(nullptr, VMS_EUNSUPPORTED, "mixed precision not built");
+    if (!std::isfinite(tree->root_len) || tree->root_len <= 0)
+        return fail(nullptr, VMS_EINVAL, "root_len must be positive");
+
+    vms_ctx *c = new vms_ctx();
+    c->stream = (hipStream_t)stream;
+    c->prm = *prm;
+    for (int k = 0; k < 3; ++k) c->origin[k] = tree->origin[k];
+    c->root_len = tree->root_len;
+    c->max_level = tree->max_level;
+    const int64_t E = tree->n_oct;
+    c->ax.assign(tree->ax, tree->ax + E);
+    c->ay.assign(tree->ay, tree->ay + E);
+    c->az.assign(tree->az, tree->az + E);
+    c->level.assign(tree->level, tree->level + E);
+    auto bail = [&](int code) {
+        set_global_err(c->err);
+        delete c;
+        return code;
+    };
+
+    std::string err;
+    int rc;
+    if (surf) {  // host-side validation first: no device work for a bad surface
+        if (surf->n_tri <= 0 || surf->n_vert <= 0 || !surf->verts || !surf->tri) {
+            c->err = "empty or null surface";
+            return bail(VMS_EINVAL);
+        }
+        rc = check_watertight(surf, err);
+        if (rc) { c->err = err; return bail(rc); }
+    }
+    vms::TreeIn ti{E, c->ax.data(), c->ay.data(), c->az.data(), c->level.data(), tree->max_level};
+    rc = vms::derive_mesh(ti, c->mesh, err);
+    if (rc) { c->err = err; return bail(rc == -2 ? VMS_EMESH : VMS_EINVAL); }
+    vms::MeshHost &m = c->mesh;
+    if (c->buf.alloc(&c->d_counters, 2) || c->buf.alloc(&c->d_norm, 1) ||
+        c->buf.alloc(&c->d_flag, 1) || hipMemsetAsync(c->d_flag, 0, 4, c->stream) != hipSuccess) {
+        c->err = "device allocation failed";
+        return bail(VMS_ENOMEM);
+    }
+
+    // ---- markers (Alg. 4) from exact corner labels
+    c->markers.assign(E, 0);
+    c->corner_lab.assign((size_t)E * 8, 0);
+    if (surf) {
+        rc = build_surface(surf, c->stream, c->surf, err);
+        if (rc) { c->err = err; return bail(rc); }
+        c->has_surf = true;
+        const int64_t NV = (int64_t)m.vert_key.size();
+        std::vector<int32_t> ix(NV), iy(NV), iz(NV);
+        for (int64_t v = 0; v < NV; ++v) {
+            int64_t x, y, z;
+            vms::unmorton3(m.vert_key[v], x, y, z);
+            ix[v] = (int32_t)x; iy[v] = (int32_t)y; iz[v] = (int32_t)z;
+        }
+        DevBuf tmp;
+        int32_t *dix, *diy, *diz;
+        uint8_t *dlab;
+        if (tmp.alloc(&dix, NV) || tmp.alloc(&diy, NV) || tmp.alloc(&diz, NV) || tmp.alloc(&dlab, NV)) {
+            c->err = "device allocation failed (vertex labels)";
+            return bail(VMS_ENOMEM);
+        }
+        std::vector<uint8_t> vlab(NV);
+        vmsk::GeoArgs g{};
+        for (int k = 0; k < 3; ++k) g.origin[k] = c->origin[k];
+        g.root_len = c->root_len;
+        g.max_level = c->max_level;
+        g.depth = prm->quad_depth;
+        if (hipMemcpyAsync(dix, ix.data(), NV * 4, hipMemcpyHostToDevice, c->stream) ||
+            hipMemcpyAsync(diy, iy.data(), NV * 4, hipMemcpyHostToDevice, c->stream) ||
+            hipMemcpyAsync(diz, iz.data(), NV * 4, hipMemcpyHostToDevice, c->stream) ||
+            hipMemsetAsync(c->d_counters, 0, 16, c->stream)) {
+            c->err = "device copy failed (vertex labels)";
+            return bail(VMS_EHIP);
+        }
+        vmsk::launch_vertex_labels(c->stream, c->surf.S, g, NV, dix, diy, diz, dlab, c->d_counters + 1);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(vlab.data(), dlab, NV, hipMemcpyDeviceToHost, c->stream) ||
+            hipStreamSynchronize(c->stream)) {
+            c->err = "vertex label kernel failed";
+            return bail(VMS_EHIP);
+        }
+        for (int64_t e = 0; e < E; ++e) {
+            int nin = 0;
+            for (int a = 0; a < 8; ++a) {
+                uint8_t l = vlab[m.elem_vert[8 * e + a]];
+                c->corner_lab[8 * e + a] = l;
+                nin += l;
+            }
+            c->markers[e] = nin == 8 ? 1 : (nin == 0 ? 0 : 2);
+        }
+    }
+
+    // ---- intercepted elements: background triangles, sub-cell quadrature
+    for (int64_t e = 0; e < E; ++e)
+        if (c->markers[e] == 2) c->sq_el.push_back((int32_t)e);
+    c->n_sq = (int64_t)c->sq_el.size();
+    if (c->n_sq) {
+        std::vector<int64_t> bt_off;
+        std::vector<int32_t> bt_ids;
+        gather_bt(c, bt_off, bt_ids);
+        std::vector<int32_t> sax(c->n_sq), say(c->n_sq), saz(c->n_sq);
+        std::vector<uint8_t> slev(c->n_sq), sclab(8 * c->n_sq);
+        for (int64_t i = 0; i < c->n_sq; ++i) {
+            int e = c->sq_el[i];
+            sax[i] = c->ax[e]; say[i] = c->ay[e]; saz[i] = c->az[e]; slev[i] = c->level[e];
+            for (int a = 0; a < 8; ++a) sclab[8 * i + a] = c->corner_lab[8 * e + a];
+        }
+        if (upload(c, &c->d_sq_el, c->sq_el) || upload(c, &c->d_sq_ax, sax) ||
+            upload(c, &c->d_sq_ay, say) || upload(c, &c->d_sq_az, saz) ||
+            upload(c, &c->d_sq_level, slev) || upload(c, &c->d_sq_clab, sclab) ||
+            upload(c, &c->d_bt_off, bt_off) || upload(c, &c->d_bt_ids, bt_ids) ||
+            c->buf.alloc(&c->d_sq_cnt, c->n_sq))
+            return bail(VMS_ENOMEM);
+        rc = run_subquad(c, true);
+        if (rc) return bail(rc);
+    }
+
+    // ---- CSR pattern over non-IN elements
+    std::vector<uint8_t> active(E);
+    for (int64_t e = 0; e < E; ++e) active[e] = c->markers[e] != 1;
+    rc = vms::build_pattern(m, active, err);
+    if (rc) { c->err = err; return bail(rc == -6 ? VMS_EUNSUPPORTED : VMS_EINVAL); }
+
+    // ---- device element data and work lists
+    std::vector<int32_t> stdl, cutl;
+    for (int64_t e = 0; e < E; ++e)
+        if (c->markers[e] == 0) stdl.push_back((int32_t)e);
+    c->n_std = (int64_t)stdl.size();
+    std::vector<int64_t> ones;
+    for (int64_t n = 0; n < m.n_nodes; ++n) {
+        if (m.node_active[n]) continue;
+        int64_t deg = m.nrow_ptr[n + 1] - m.nrow_ptr[n];
+        for (int cc = 0; cc < 4; ++cc) ones.push_back(m.row_ptr[4 * n + cc] + 4 * (int64_t)m.diag_pos[n] + cc);
+        (void)deg;
+    }
+    c->n_ones = (int64_t)ones.size();
+    if (upload(c, &c->d_masters, m.masters) || upload(c, &c->d_ccode, m.ccode) ||
+        upload(c, &c->d_hang, m.has_hang) || upload(c, &c->d_level, c->level) ||
+        upload(c, &c->d_rowbase, m.el_rowbase) || upload(c, &c->d_rowlen, m.el_rowlen) ||
+        upload(c, &c->d_kk, m.el_kk) || upload(c, &c->d_std, stdl) || upload(c, &c->d_ones, ones))
+        return bail(VMS_ENOMEM);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+        c->err = "device synchronisation failed at create";
+        return bail(VMS_EHIP);
+    }
+    *out = c;
+    return VMS_OK;
+}
+
+int vms_sizes(vms_ctx *c, int64_t *n_nodes, int64_t *n_rows, int64_t *nnz, int64_t *n_subgp) {
+    if (!c) return fail(nullptr, VMS_EINVAL, "null context");
+    unsigned int flag = 0;
+    HIPCHK(c, hipMemcpyAsync(&flag, c->d_flag, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (flag) return fail(c, VMS_EOVERFLOW, "relabelling changed the sub-cell point count of an element");
+    if (n_nodes) *n_nodes = c->mesh.n_nodes;
+    if (n_rows) *n_rows = 4 * c->mesh.n_nodes;
+    if (nnz) *nnz = c->mesh.nnz;
+    if (n_subgp) *n_subgp = c->n_subgp;
+    return VMS_OK;
+}
+
+int vms_export(vms_ctx *c, uint32_t what, void *dst) {
+    if (!c || !dst) return fail(c, VMS_EINVAL, "null context or destination");
+    const vms::MeshHost &m = c->mesh;
+    const int64_t E = m.n_el;
+    switch (what) {
+        case VMS_EXPORT_NODE_XYZ: {
+            int32_t *d = (int32_t *)dst;
+            for (int64_t n = 0; n < m.n_nodes; ++n) {
+                int64_t x, y, z;
+                vms::unmorton3(m.node_key[n], x, y, z);
+                d[n] = (int32_t)x; d[m.n_nodes + n] = (int32_t)y; d[2 * m.n_nodes + n] = (int32_t)z;
+            }
+            return VMS_OK;
+        }
+        case VMS_EXPORT_ROW_PTR:
+            std::memcpy(dst, m.row_ptr.data(), m.row_ptr.size() * 8);
+            return VMS_OK;
+        case VMS_EXPORT_COL_IDX:
+            std::memcpy(dst, m.col_idx.data(), m.col_idx.size() * 4);
+            return VMS_OK;
+        case VMS_EXPORT_MARKERS:
+            std::memcpy(dst, c->markers.data(), E);
+            return VMS_OK;
+        case VMS_EXPORT_VERTEX_LAB:
+            std::memcpy(dst, c->corner_lab.data(), 8 * E);
+            return VMS_OK;
+        case VMS_EXPORT_MASTERS:
+            std::memcpy(dst, m.masters.data(), 8 * E * 4);
+            return VMS_OK;
+        case VMS_EXPORT_SUBGP: {
+            const int64_t n = c->n_subgp;
+            std::vector<uint32_t> ent(n);
+            if (n) {
+                HIPCHK(c, hipMemcpyAsync(ent.data(), c->d_entries, n * 4, hipMemcpyDeviceToHost, c->stream));
+                HIPCHK(c, hipStreamSynchronize(c->stream));
+            }
+            int64_t *o_el = (int64_t *)dst;
+            int32_t *o_key = (int32_t *)((char *)dst + 8 * n);
+            uint8_t *o_lvl = (uint8_t *)((char *)dst + 12 * n);
+            double *o_xyz = (double *)((char *)dst + 13 * n);
+            const int D = c->prm.quad_depth, M = c->max_level;
+            const double scF = std::ldexp(1.0, -(M + D));
+            for (int64_t i = 0; i < c->n_sq; ++i) {
+                const int e = c->sq_el[i];
+                const int64_t SE = (int64_t)1 << (M - c->level[e] + D);
+                const int64_t A0[3] = {(int64_t)c->ax[e] << D, (int64_t)c->ay[e] << D, (int64_t)c->az[e] << D};
+                for (int64_t p = c->sq_off[i]; p < c->sq_off[i + 1]; ++p) {
+                    uint32_t en = ent[p];
+                    int l = en & 3;
+                    uint32_t key = en >> 2;
+                    int gp = (key >> (3 * (D - l))) & 7;
+                    int64_t A[3] = {A0[0], A0[1], A0[2]};
+                    for (int k = 1; k <= l; ++k) {
+                        uint32_t dg = (key >> (3 * (D - k + 1))) & 7u;
+                        for (int ax = 0; ax < 3; ++ax)
+                            if ((dg >> ax) & 1u) A[ax] += SE >> k;
+                    }
+                    o_el[p] = e;
+                    o_key[p] = (int32_t)key;
+                    o_lvl[p] = (uint8_t)l;
+                    double xyz[3];
+                    for (int ax = 0; ax < 3; ++ax)
+                        xyz[ax] = vmsd::point_coord(c->origin[ax], c->root_len, scF, A[ax], SE >> l,
+                                                    ((gp >> ax) & 1) ? VMS_GP : VMS_GM);
+                    std::memcpy(o_xyz + 3 * p, xyz, sizeof xyz);
+                }
+            }
+            return VMS_OK;
+        }
+        default:
+            return fail(c, VMS_EINVAL, "unknown export selector");
+    }
+}
+
+static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *resid, uint32_t flags,
+                         bool mat) {
+    if (!c || !f) return fail(c, VMS_EINVAL, "null context or fields");
+    if (mat && !vals) return fail(c, VMS_EINVAL, "null csr_vals");
+    if (!mat && !resid) return fail(c, VMS_EINVAL, "null resid");
+    const double *fp[7] = {f->ux, f->uy, f->uz, f->p, f->ux0, f->uy0, f->uz0};
+    for (const double *p : fp)
+        if (!p) return fail(c, VMS_EINVAL, "null field pointer");
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+    if (flags & VMS_RELABEL) {
+        if (c->has_surf) {
+            int rc = run_subquad(c, false);
+            if (rc) return rc;
+        }
+    }
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+    const bool fp64 = c->prm.precision == VMS_FP64;
+    const int64_t nrows = 4 * c->mesh.n_nodes;
+    if (mat) {
+        if (fp64) {
+            vmsk::launch_fill_f64(c->stream, (double *)vals, c->mesh.nnz, 0.0);
+            vmsk::launch_set_ones_f64(c->stream, (double *)vals, c->d_ones, c->n_ones);
+        } else {
+            vmsk::launch_fill_f32(c->stream, (float *)vals, c->mesh.nnz, 0.0f);
+            vmsk::launch_set_ones_f32(c->stream, (float *)vals, c->d_ones, c->n_ones);
+        }
+    }
+    if (resid) vmsk::launch_fill_f64(c->stream, resid, nrows, 0.0);
+    vmsk::AsmArgs a{};
+    a.masters = c->d_masters;
+    a.ccode = c->d_ccode;
+    a.has_hang = c->d_hang;
+    a.level = c->d_level;
+    a.rowbase = c->d_rowbase;
+    a.rowlen = c->d_rowlen;
+    a.kk = c->d_kk;
+    a.depth = c->prm.quad_depth;
+    for (int k = 0; k < 7; ++k) a.f[k] = fp[k];
+    a.rho = c->prm.rho; a.mu = c->prm.mu; a.dt = c->prm.dt; a.theta = c->prm.theta;
+    a.c_t = c->prm.c_t; a.c_i = c->prm.c_i; a.root_len = c->root_len;
+    a.vals = vals;
+    a.resid = resid;
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
+    // OUT elements: 2x2x2 Gauss points
+    a.n_items = c->n_std;
+    a.items = c->d_std;
+    if (fp64) vmsk::launch_assemble_f64(c->stream, a, false, mat);
+    else vmsk::launch_assemble_mixed(c->stream, a, false, mat, c->prm.precision == VMS_MIXED_FP16);
+    HIPCHK(c, hipGetLastError());
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
+    // INTERCEPTED elements: kept sub-cell points
+    if (c->n_sq) {
+        a.n_items = c->n_sq;
+        a.items = c->d_sq_el;
+        a.pt_off = c->d_sq_off;
+        a.pt_cnt = c->d_sq_cnt;
+        a.entries = c->d_entries;
+        if (fp64) vmsk::launch_assemble_f64(c->stream, a, true, mat);
+        else vmsk::launch_assemble_mixed(c->stream, a, true, mat, c->prm.precision == VMS_MIXED_FP16);
+        HIPCHK(c, hipGetLastError());
+    }
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[4], c->stream));
+    return VMS_OK;
+}
+
+int vms_set_timing(vms_ctx *c, int on) {
+    if (!c) return fail(nullptr, VMS_EINVAL, "null context");
+    if (on)
+        for (hipEvent_t &e : c->ev)
+            if (!e) HIPCHK(c, hipEventCreate(&e));
+    c->timing = on != 0;
+    return VMS_OK;
+}
+
+int vms_last_timing(vms_ctx *c, float *ms) {
+    if (!c || !ms) return fail(c, VMS_EINVAL, "null argument");
+    if (!c->timing) return fail(c, VMS_EINVAL, "timing is off");
+    HIPCHK(c, hipEventSynchronize(c->ev[4]));
+    for (int k = 0; k < 4; ++k) HIPCHK(c, hipEventElapsedTime(&ms[k], c->ev[k], c->ev[k + 1]));
+    return VMS_OK;
+}
+
+int vms_assemble(vms_ctx *c, const vms_fields *f, void *csr_vals, double *resid, uint32_t flags) {
+    return assemble_impl(c, f, csr_vals, resid, flags, true);
+}
+
+int vms_apply(vms_ctx *c, const vms_fields *f, double *resid, double *norm2) {
+    int rc = assemble_impl(c, f, nullptr, resid, 0, false);
+    if (rc) return rc;
+    if (norm2) {
+        HIPCHK(c, hipMemsetAsync(c->d_norm, 0, sizeof(double), c->stream));
+        vmsk::launch_norm2(c->stream, resid, 4 * c->mesh.n_nodes, c->d_norm);
+        double s = 0;
+        HIPCHK(c, hipMemcpyAsync(&s, c->d_norm, sizeof s, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        *norm2 = std::sqrt(s);
+    }
+    return VMS_OK;
+}
+
+int vms_stats(vms_ctx *c, int64_t *out) {
+    if (!c || !out) return fail(c, VMS_EINVAL, "null argument");
+    out[0] = c->n_std;
+    out[1] = c->n_sq;
+    out[2] = (int64_t)c->n_labelled;
+    out[3] = (int64_t)c->n_degenerate;
+    out[4] = c->mesh.n_hanging;
+    out[5] = c->n_subgp;
+    return VMS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// in-out classification of arbitrary points
+// ---------------------------------------------------------------------------
+
+struct inout_handle {
+    SurfaceHost surf;
+    hipStream_t stream;
+    unsigned long long *d_ndeg = nullptr;
+    DevBuf buf;
+    vmsm::Filter filter;
+};
+
+int inout_prepare(const vms_surface *s, void *stream, inout_handle **out) {
+    if (!out) return fail(nullptr, VMS_EINVAL, "null output pointer");
+    *out = nullptr;
+    inout_handle *h = new inout_handle();
+    h->stream = (hipStream_t)stream;
+    std::string err;
+    int rc = build_surface(s, h->stream, h->surf, err);
+    if (rc) { set_global_err(err); delete h; return rc; }
+    if (h->buf.alloc(&h->d_ndeg, 1)) { set_global_err("device allocation failed"); delete h; return VMS_ENOMEM; }
+    *out = h;
+    return VMS_OK;
+}
+
+void inout_release(inout_handle *h) {
+    if (!h) return;
+    (void)hipStreamSynchronize(h->stream);
+    delete h;
+}
+
+int inout_classify_prepared(inout_handle *h, const double *px, const double *py, const double *pz,
+                            int64_t n, uint8_t *labels, uint32_t mode, const void *mlp) {
+    if (!h || (n > 0 && (!px || !py || !pz || !labels)) || n < 0)
+        return fail(nullptr, VMS_EINVAL, "null argument or negative size");
+    if (mode == VMS_INOUT_EXACT) {
+        vmsk::launch_point_labels(h->stream, h->surf.S, n, px, py, pz, labels, nullptr);
+    } else if (mode == VMS_INOUT_LEARNED) {
+        if (!mlp) return fail(nullptr, VMS_EINVAL, "learned mode needs a network");
+        int rc = vmsm::classify_learned(h->stream, h->filter, (const vmsm::MlpDev *)mlp, h->surf.S, px,
+                                        py, pz, n, labels);
+        if (rc) return fail(nullptr, rc, "learned classification failed");
+    } else {
+        return fail(nullptr, VMS_EUNSUPPORTED, "unknown in-out mode");
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(nullptr, VMS_EHIP, hipGetErrorString(e));
+    return VMS_OK;
+}
+
+int inout_classify(const vms_surface *surf, const double *px, const double *py, const double *pz,
+                   int64_t n, uint8_t *labels, uint32_t mode, const void *mlp, void *stream) {
+    inout_handle *h = nullptr;
+    int rc = inout_prepare(surf, stream, &h);
+    if (rc) return rc;
+    rc = inout_classify_prepared(h, px, py, pz, n, labels, mode, mlp);
+    if (rc == VMS_OK && hipStreamSynchronize(h->stream) != hipSuccess) rc = VMS_EHIP;
+    inout_release(h);
+    return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// host-only mesh derivation (no device involved)
+// ---------------------------------------------------------------------------
+
+struct vms_mesh {
+    vms::MeshHost m;
+    std::vector<int32_t> ax, ay, az;
+    std::vector<uint8_t> level;
+};
+
+extern "C" {
+
+int vms_mesh_create(vms_mesh **out, const vms_octree *tree, const uint8_t *markers) {
+    if (!out) return fail(nullptr, VMS_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (!tree || !tree->ax || !tree->ay || !tree->az || !tree->level || tree->n_oct <= 0)
+        return fail(nullptr, VMS_EINVAL, "null or empty octree");
+    if (tree->max_level < 0 || tree->max_level > 20)
+        return fail(nullptr, VMS_EUNSUPPORTED, "max_level must be in [0, 20]");
+    vms_mesh *h = new vms_mesh();
+    const int64_t E = tree->n_oct;
+    h->ax.assign(tree->ax, tree->ax + E);
+    h->ay.assign(tree->ay, tree->ay + E);
+    h->az.assign(tree->az, tree->az + E);
+    h->level.assign(tree->level, tree->level + E);
+    vms::TreeIn ti{E, h->ax.data(), h->ay.data(), h->az.data(), h->level.data(), tree->max_level};
+    std::string err;
+    int rc = vms::derive_mesh(ti, h->m, err);
+    if (rc == 0) {
+        std::vector<uint8_t> active(E, 1);
+        if (markers)
+            for (int64_t e = 0; e < E; ++e) active[e] = markers[e] != 1;
+        rc = vms::build_pattern(h->m, active, err);
+        if (rc) rc = rc == -6 ? VMS_EUNSUPPORTED : VMS_EINVAL;
+    } else {
+        rc = rc == -2 ? VMS_EMESH : VMS_EINVAL;
+    }
+    if (rc) {
+        set_global_err(err);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return VMS_OK;
+}
+
+int vms_mesh_sizes(vms_mesh *h, int64_t *n_nodes, int64_t *nnz, int64_t *n_hanging) {
+    if (!h) return fail(nullptr, VMS_EINVAL, "null mesh");
+    if (n_nodes) *n_nodes = h->m.n_nodes;
+    if (nnz) *nnz = h->m.nnz;
+    if (n_hanging) *n_hanging = h->m.n_hanging;
+    return VMS_OK;
+}
+
+int vms_mesh_export(vms_mesh *h, uint32_t what, void *dst) {
+    if (!h || !dst) return fail(nullptr, VMS_EINVAL, "null mesh or destination");
+    const vms::MeshHost &m = h->m;
+    switch (what) {
+        case VMS_EXPORT_NODE_XYZ: {
+            int32_t *d = (int32_t *)dst;
+            for (int64_t n = 0; n < m.n_nodes; ++n) {
+                int64_t x, y, z;
+                vms::unmorton3(m.node_key[n], x, y, z);
+                d[n] = (int32_t)x; d[m.n_nodes + n] = (int32_t)y; d[2 * m.n_nodes + n] = (int32_t)z;
+            }
+            return VMS_OK;
+        }
+        case VMS_EXPORT_ROW_PTR: std::memcpy(dst, m.row_ptr.data(), m.row_ptr.size() * 8); return VMS_OK;
+        case VMS_EXPORT_COL_IDX: std::memcpy(dst, m.col_idx.data(), m.col_idx.size() * 4); return VMS_OK;
+        case VMS_EXPORT_MASTERS: std::memcpy(dst, m.masters.data(), m.masters.size() * 4); return VMS_OK;
+        default: return fail(nullptr, VMS_EINVAL, "unsupported export selector for a host mesh");
+    }
+}
+
+void vms_mesh_destroy(vms_mesh *h) { delete h; }
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Internal interface between the host API of libvms and its HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vmsk {
+
+// Surface on the device. Triangles are packed as 9 doubles (a, b, c) plus an
+// axis-aligned box (6 doubles: min xyz, max xyz). Rays along +x are served by
+// a 2D grid of bins over (y, z); bin(v) = clamp(floor((v - v0) * inv), 0, n-1)
+// is evaluated identically when bins are filled (host) and queried (device).
+struct SurfDev {
+    int32_t n_tri;
+    int32_t nby, nbz;
+    int32_t pad;
+    const double *tv;    // [n_tri][9]
+    const double *tbox;  // [n_tri][6]
+    double lo[3], hi[3];
+    double y0, z0, iny, inz;
+    const int32_t *bin_off;  // [nby*nbz + 1]
+    const int32_t *bin_tri;
+};
+
+struct GeoArgs {
+    double origin[3];
+    double root_len;
+    int32_t max_level;
+    int32_t depth;
+};
+
+// Exact labels of points given by integer coordinates at max-level resolution.
+void launch_vertex_labels(hipStream_t s, const SurfDev &S, const GeoArgs &g, int64_t n,
+                          const int32_t *ix, const int32_t *iy, const int32_t *iz, uint8_t *lab,
+                          unsigned long long *ndeg);
+// Exact labels of arbitrary points.
+void launch_point_labels(hipStream_t s, const SurfDev &S, int64_t n, const double *px,
+                         const double *py, const double *pz, uint8_t *lab,
+                         unsigned long long *ndeg);
+// Exact labels of the points whose index is listed (learned-filter fallback).
+void launch_point_labels_list(hipStream_t s, const SurfDev &S, const int64_t *idx,
+                              const unsigned long long *count, int64_t cap, const double *px,
+                              const double *py, const double *pz, uint8_t *lab,
+                              unsigned long long *ndeg);
+
+// Adaptive sub-cell quadrature of INTERCEPTED elements. pass 0 counts kept
+// points per element into cnt; pass 1 writes the sorted entries
+// (key << 2 | level) at off[i]. Per element i of the list: element id,
+// anchor/level, corner labels, and background triangles bt_ids[bt_off[i] ..).
+struct SubqArgs {
+    int64_t n;
+    const int32_t *el;
+    const int32_t *ax, *ay, *az;
+    const uint8_t *level;
+    const uint8_t *corner_lab;  // [n][8]
+    const int64_t *bt_off;
+    const int32_t *bt_ids;
+    int32_t *cnt;
+    const int64_t *off;
+    uint32_t *entries;
+    unsigned long long *nlabel;
+    unsigned long long *ndeg;
+    unsigned int *flag;  // bit 0: a relabelled element changed its point count
+};
+void launch_subquad(hipStream_t s, const SurfDev &S, const GeoArgs &g, const SubqArgs &a, int pass);
+
+// Assembly.
+struct AsmArgs {
+    // element data (indexed by element id)
+    const int32_t *masters;   // [E][8]
+    const uint32_t *ccode;    // [E][4]
+    const uint8_t *has_hang;  // [E]
+    const uint8_t *level;     // [E]
+    const int64_t *rowbase;   // [E][8]
+    const int32_t *rowlen;    // [E][8]
+    const uint16_t *kk;       // [E][64]
+    // work list
+    int64_t n_items;
+    const int32_t *items;     // element ids
+    const int64_t *pt_off;    // SUB: first entry of the item's points
+    const int32_t *pt_cnt;    // SUB: number of points
+    const uint32_t *entries;  // SUB: key << 2 | level
+    int32_t depth;
+    // fields
+    const double *f[7];       // ux uy uz p ux0 uy0 uz0
+    // parameters
+    double rho, mu, dt, theta, c_t, c_i, root_len;
+    // outputs
+    void *vals;
+    double *resid;
+};
+void launch_assemble_f64(hipStream_t s, const AsmArgs &a, bool sub, bool mat);
+void launch_assemble_mixed(hipStream_t s, const AsmArgs &a, bool sub, bool mat, int fp16);
+
+void launch_fill_f64(hipStream_t s, double *p, int64_t n, double v);
+void launch_fill_f32(hipStream_t s, float *p, int64_t n, float v);
+void launch_set_ones_f64(hipStream_t s, double *vals, const int64_t *idx, int64_t n);
+void launch_set_ones_f32(hipStream_t s, float *vals, const int64_t *idx, int64_t n);
+// sum of squares, FP64, into out[0] (zeroed by the caller)
+void launch_norm2(hipStream_t s, const double *v, int64_t n, double *out);
+
+}  // namespace vmsk

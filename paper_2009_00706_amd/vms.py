@@ -1,0 +1,342 @@
+"""ctypes binding of libvms (argument marshalling only).
+
+Every entry point of ``include/vms.h`` has a function of the same name here.
+Device buffers are torch tensors on a ROCm device (PyTorch provides device
+memory and the stream); all computation runs in the HIP library. Loading
+fails loudly if ``libvms.so`` has not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvms.so")
+
+VMS_OK, VMS_EINVAL, VMS_EMESH, VMS_EHIP, VMS_ENOMEM, VMS_EOVERFLOW, VMS_EUNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6)
+VMS_FP64, VMS_MIXED_BF16, VMS_MIXED_FP16 = 0, 1, 2
+VMS_INOUT_EXACT, VMS_INOUT_LEARNED = 0, 1
+VMS_RELABEL = 1
+(VMS_EXPORT_NODE_XYZ, VMS_EXPORT_ROW_PTR, VMS_EXPORT_COL_IDX, VMS_EXPORT_MARKERS,
+ VMS_EXPORT_VERTEX_LAB, VMS_EXPORT_SUBGP, VMS_EXPORT_MASTERS) = range(1, 8)
+
+EXPORTED = ["vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply", "inout_classify",
+            "inout_prepare", "inout_classify_prepared", "inout_release", "vms_stats",
+            "vms_mesh_create", "vms_mesh_sizes", "vms_mesh_export", "vms_mesh_destroy",
+            "vms_set_timing", "vms_last_timing",
+            "vms_last_error", "vms_destroy"]
+
+
+class VmsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libvms error {code}: {msg}")
+        self.code = code
+
+
+class Octree(C.Structure):
+    _fields_ = [("n_oct", C.c_int64), ("ax", C.c_void_p), ("ay", C.c_void_p), ("az", C.c_void_p),
+                ("level", C.c_void_p), ("max_level", C.c_int32), ("pad", C.c_int32),
+                ("origin", C.c_double * 3), ("root_len", C.c_double)]
+
+
+class Surface(C.Structure):
+    _fields_ = [("n_vert", C.c_int32), ("n_tri", C.c_int32), ("verts", C.c_void_p),
+                ("tri", C.c_void_p)]
+
+
+class Params(C.Structure):
+    _fields_ = [("rho", C.c_double), ("mu", C.c_double), ("dt", C.c_double),
+                ("theta", C.c_double), ("c_t", C.c_double), ("c_i", C.c_double),
+                ("quad_depth", C.c_int32), ("precision", C.c_uint32)]
+
+
+class Fields(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("ux", "uy", "uz", "p", "ux0", "uy0", "uz0")]
+
+
+_lib = None
+
+
+def lib():
+    """Load libvms.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2009_00706_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        p, i64, i32, u32 = C.c_void_p, C.c_int64, C.c_int32, C.c_uint32
+        L.vms_create.argtypes = [C.POINTER(p), C.POINTER(Octree), C.POINTER(Surface),
+                                 C.POINTER(Params), p]
+        L.vms_sizes.argtypes = [p, p, p, p, p]
+        L.vms_export.argtypes = [p, u32, p]
+        L.vms_assemble.argtypes = [p, C.POINTER(Fields), p, p, u32]
+        L.vms_apply.argtypes = [p, C.POINTER(Fields), p, p]
+        L.inout_classify.argtypes = [C.POINTER(Surface), p, p, p, i64, p, u32, p, p]
+        L.inout_prepare.argtypes = [C.POINTER(Surface), p, C.POINTER(p)]
+        L.inout_classify_prepared.argtypes = [p, p, p, p, i64, p, u32, p]
+        L.inout_release.argtypes = [p]
+        L.inout_release.restype = None
+        L.vms_stats.argtypes = [p, p]
+        L.vms_mesh_create.argtypes = [C.POINTER(p), C.POINTER(Octree), p]
+        L.vms_mesh_sizes.argtypes = [p, p, p, p]
+        L.vms_mesh_export.argtypes = [p, u32, p]
+        L.vms_mesh_destroy.argtypes = [p]
+        L.vms_mesh_destroy.restype = None
+        L.vms_set_timing.argtypes = [p, C.c_int]
+        L.vms_last_timing.argtypes = [p, p]
+        L.vms_last_error.argtypes = [p]
+        L.vms_last_error.restype = C.c_char_p
+        L.vms_destroy.argtypes = [p]
+        L.vms_destroy.restype = None
+        for n in ("vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply",
+                  "inout_classify", "inout_prepare", "inout_classify_prepared", "vms_stats",
+                  "vms_mesh_create", "vms_mesh_sizes", "vms_mesh_export", "vms_set_timing",
+                  "vms_last_timing"):
+            getattr(L, n).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc, ctx=None):
+    if rc != VMS_OK:
+        raise VmsError(rc, lib().vms_last_error(ctx).decode())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _np(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def make_surface(verts, tris):
+    v = _np(verts, np.float64).reshape(-1, 3)
+    t = _np(tris, np.int32).reshape(-1, 3)
+    s = Surface(v.shape[0], t.shape[0], v.ctypes.data, t.ctypes.data)
+    s._keep = (v, t)
+    return s
+
+
+def make_params(rho=1.0, mu=0.01, dt=0.01, theta=0.5, c_t=4.0, c_i=36.0, quad_depth=3,
+                precision=VMS_FP64):
+    return Params(rho, mu, dt, theta, c_t, c_i, quad_depth, precision)
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names as the C-ABI)
+# ---------------------------------------------------------------------------
+
+
+def vms_create(tree, surf=None, params=None, stream=None):
+    """tree: object with ax, ay, az, level, max_level, origin, root_len (host arrays);
+    surf: object with verts (n,3), tris (m,3) or None. Returns the context handle."""
+    o = _octree(tree)
+    s = make_surface(surf.verts, surf.tris) if surf is not None else None
+    prm = params if params is not None else make_params()
+    h = C.c_void_p()
+    rc = lib().vms_create(C.byref(h), C.byref(o), C.byref(s) if s is not None else None,
+                          C.byref(prm), _stream(stream))
+    _check(rc, None)
+    return h
+
+
+def _octree(tree):
+    ax, ay, az = (_np(a, np.int32) for a in (tree.ax, tree.ay, tree.az))
+    lv = _np(tree.level, np.uint8)
+    o = Octree(ax.shape[0], ax.ctypes.data, ay.ctypes.data, az.ctypes.data, lv.ctypes.data,
+               int(tree.max_level), 0, (C.c_double * 3)(*tree.origin), float(tree.root_len))
+    o._keep = (ax, ay, az, lv)
+    return o
+
+
+def vms_mesh_create(tree, markers=None):
+    o = _octree(tree)
+    mk = _np(markers, np.uint8) if markers is not None else None
+    h = C.c_void_p()
+    _check(lib().vms_mesh_create(C.byref(h), C.byref(o), mk.ctypes.data if mk is not None else None),
+           None)
+    return h
+
+
+def vms_mesh_sizes(h):
+    v = (C.c_int64 * 3)()
+    _check(lib().vms_mesh_sizes(h, C.byref(v, 0), C.byref(v, 8), C.byref(v, 16)), None)
+    return {"n_nodes": v[0], "nnz": v[1], "n_hanging": v[2]}
+
+
+def vms_mesh_export(h, what, n_oct=None):
+    sz = vms_mesh_sizes(h)
+    shapes = {VMS_EXPORT_NODE_XYZ: ((3, sz["n_nodes"]), np.int32),
+              VMS_EXPORT_ROW_PTR: ((4 * sz["n_nodes"] + 1,), np.int64),
+              VMS_EXPORT_COL_IDX: ((sz["nnz"],), np.int32),
+              VMS_EXPORT_MASTERS: ((n_oct, 8), np.int32)}
+    shp, dt = shapes[what]
+    out = np.zeros(shp, dt)
+    _check(lib().vms_mesh_export(h, what, out.ctypes.data), None)
+    return out
+
+
+def vms_mesh_destroy(h):
+    lib().vms_mesh_destroy(h)
+
+
+def vms_sizes(ctx):
+    v = (C.c_int64 * 4)()
+    _check(lib().vms_sizes(ctx, C.byref(v, 0), C.byref(v, 8), C.byref(v, 16), C.byref(v, 24)), ctx)
+    return {"n_nodes": v[0], "n_rows": v[1], "nnz": v[2], "n_subgp": v[3]}
+
+
+def vms_stats(ctx):
+    v = (C.c_int64 * 6)()
+    _check(lib().vms_stats(ctx, v), ctx)
+    return {"n_out": v[0], "n_intercepted": v[1], "n_labelled": v[2], "n_degenerate": v[3],
+            "n_hanging": v[4], "n_subgp": v[5]}
+
+
+def vms_export(ctx, what, n_oct=None):
+    sz = vms_sizes(ctx)
+    if what == VMS_EXPORT_NODE_XYZ:
+        out = np.zeros((3, sz["n_nodes"]), np.int32)
+    elif what == VMS_EXPORT_ROW_PTR:
+        out = np.zeros(sz["n_rows"] + 1, np.int64)
+    elif what == VMS_EXPORT_COL_IDX:
+        out = np.zeros(sz["nnz"], np.int32)
+    elif what == VMS_EXPORT_MARKERS:
+        out = np.zeros(n_oct, np.uint8)
+    elif what == VMS_EXPORT_VERTEX_LAB:
+        out = np.zeros((n_oct, 8), np.uint8)
+    elif what == VMS_EXPORT_MASTERS:
+        out = np.zeros((n_oct, 8), np.int32)
+    elif what == VMS_EXPORT_SUBGP:
+        n = sz["n_subgp"]
+        raw = np.zeros(n * 37 + 8, np.uint8)
+        _check(lib().vms_export(ctx, what, raw.ctypes.data), ctx)
+        return {"el": raw[:8 * n].view(np.int64).copy(),
+                "key": raw[8 * n:12 * n].view(np.int32).copy(),
+                "lvl": raw[12 * n:13 * n].copy(),
+                "xyz": raw[13 * n:37 * n].view(np.float64).reshape(n, 3).copy()}
+    else:
+        raise ValueError(what)
+    _check(lib().vms_export(ctx, what, out.ctypes.data), ctx)
+    return out
+
+
+def _fields(f):
+    return Fields(*[f[k].data_ptr() for k in ("ux", "uy", "uz", "p", "ux0", "uy0", "uz0")])
+
+
+def vms_assemble(ctx, fields, csr_vals, resid=None, flags=0):
+    """fields: dict of 7 float64 device tensors; csr_vals: device tensor (nnz)."""
+    fs = _fields(fields)
+    _check(lib().vms_assemble(ctx, C.byref(fs), _ptr(csr_vals), _ptr(resid), flags), ctx)
+
+
+def vms_apply(ctx, fields, resid, want_norm=False):
+    fs = _fields(fields)
+    nrm = C.c_double(0.0)
+    _check(lib().vms_apply(ctx, C.byref(fs), _ptr(resid), C.byref(nrm) if want_norm else None), ctx)
+    return nrm.value if want_norm else None
+
+
+def inout_classify(surf, px, py, pz, labels, mode=VMS_INOUT_EXACT, mlp=None, stream=None):
+    s = make_surface(surf.verts, surf.tris)
+    rc = lib().inout_classify(C.byref(s), _ptr(px), _ptr(py), _ptr(pz), px.numel(), _ptr(labels),
+                              mode, C.c_void_p(mlp) if mlp else None, _stream(stream))
+    _check(rc, None)
+
+
+def inout_prepare(surf, stream=None):
+    s = make_surface(surf.verts, surf.tris)
+    h = C.c_void_p()
+    _check(lib().inout_prepare(C.byref(s), _stream(stream), C.byref(h)), None)
+    return h
+
+
+def inout_classify_prepared(h, px, py, pz, labels, mode=VMS_INOUT_EXACT, mlp=None):
+    rc = lib().inout_classify_prepared(h, _ptr(px), _ptr(py), _ptr(pz), px.numel(), _ptr(labels),
+                                       mode, C.c_void_p(mlp) if mlp else None)
+    _check(rc, None)
+
+
+def inout_release(h):
+    lib().inout_release(h)
+
+
+def vms_set_timing(ctx, on=True):
+    _check(lib().vms_set_timing(ctx, 1 if on else 0), ctx)
+
+
+def vms_last_timing(ctx):
+    """ms of the last call: relabel, zero/identity, OUT-element kernel, INTERCEPTED kernel."""
+    v = (C.c_float * 4)()
+    _check(lib().vms_last_timing(ctx, v), ctx)
+    return list(v)
+
+
+def vms_last_error(ctx=None):
+    return lib().vms_last_error(ctx).decode()
+
+
+def vms_destroy(ctx):
+    lib().vms_destroy(ctx)
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper used by tests and the benchmark
+# ---------------------------------------------------------------------------
+
+
+class Assembler:
+    """One context plus its device outputs; fields are given as host arrays."""
+
+    def __init__(self, tree, surf=None, params=None, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.params = params if params is not None else make_params()
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            self.ctx = vms_create(tree, surf, self.params, self.stream.cuda_stream)
+        self.sizes = vms_sizes(self.ctx)
+        self.n_oct = tree.ax.shape[0]
+        fp64 = self.params.precision == VMS_FP64
+        self.vals = torch.zeros(self.sizes["nnz"], dtype=torch.float64 if fp64 else torch.float32,
+                                device=self.device)
+        self.resid = torch.zeros(self.sizes["n_rows"], dtype=torch.float64, device=self.device)
+        self.fields = None
+
+    def set_fields(self, f):
+        t = self.torch
+        self.fields = {k: t.as_tensor(np.ascontiguousarray(f[k], np.float64), device=self.device)
+                       for k in ("ux", "uy", "uz", "p", "ux0", "uy0", "uz0")}
+
+    def assemble(self, flags=0, resid=True):
+        vms_assemble(self.ctx, self.fields, self.vals, self.resid if resid else None, flags)
+
+    def apply(self, want_norm=False):
+        return vms_apply(self.ctx, self.fields, self.resid, want_norm)
+
+    def export(self, what):
+        return vms_export(self.ctx, what, self.n_oct)
+
+    def close(self):
+        if self.ctx:
+            vms_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,123 @@
+"""CPU-only checks of libvms: the C-ABI loads and exports every declared symbol,
+the host mesh derivation matches the CPU reference bit for bit, and error codes
+that the host can force come back as documented (no device call is made)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2009_00706_amd import inputs as I
+from paper_2009_00706_amd import vms
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "vms.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?\s*(\w+)\s*\(", src, re.M)))
+
+
+def test_all_declared_symbols_exported():
+    names = declared_functions()
+    assert len(names) >= 15
+    L = vms.lib()
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in vms.EXPORTED, n
+
+
+def _parity(oracle, t, markers=None):
+    h = vms.vms_mesh_create(t, markers)
+    try:
+        sz = vms.vms_mesh_sizes(h)
+        act = None if markers is None else markers != 1
+        ms = oracle.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level, active=act)
+        assert sz["n_nodes"] == ms.n_nodes and sz["nnz"] == ms.nnz and sz["n_hanging"] == ms.n_hanging
+        assert np.array_equal(vms.vms_mesh_export(h, vms.VMS_EXPORT_NODE_XYZ).T, ms.node_xyz_int)
+        assert np.array_equal(vms.vms_mesh_export(h, vms.VMS_EXPORT_ROW_PTR), ms.row_ptr)
+        assert np.array_equal(vms.vms_mesh_export(h, vms.VMS_EXPORT_COL_IDX), ms.col_idx)
+        m = vms.vms_mesh_export(h, vms.VMS_EXPORT_MASTERS, t.n)
+        big = np.iinfo(np.int32).max
+        assert np.array_equal(np.sort(np.where(m < 0, big, m), 1),
+                              np.sort(np.where(ms.masters < 0, big, ms.masters), 1))
+        return ms
+    finally:
+        vms.vms_mesh_destroy(h)
+
+
+def test_index_parity_uniform(oracle):
+    ms = _parity(oracle, I.uniform_octree(4))
+    assert ms.nnz == 1882384
+
+
+def test_index_parity_hanging(oracle):
+    c = (0.5 + I.BODY_OFFSET[0], 0.5, 0.5)
+    ms = _parity(oracle, I.sphere_refined_octree(c, 0.3, 2, 5, 1.5))
+    assert ms.n_hanging > 1000
+
+
+def test_index_parity_with_in_elements(oracle):
+    t = I.uniform_octree(3)
+    rng = np.random.default_rng(0)
+    mk = rng.choice([0, 1, 2], t.n, p=[0.6, 0.3, 0.1]).astype(np.uint8)
+    _parity(oracle, t, mk)
+
+
+def test_index_parity_sphere_workload(oracle):
+    tree, _ = I.sphere_workload()
+    _parity(oracle, tree)
+
+
+def test_unbalanced_tree_rejected():
+    t = I.uniform_octree(2, max_level=4)
+    # replace one leaf by its 64 level-4 descendants: level 2 next to level 4
+    keep = np.arange(1, t.n)
+    s = 1
+    sub = np.array([(x, y, z) for z in range(4) for y in range(4) for x in range(4)]) * s
+    ax = np.concatenate([t.ax[keep], sub[:, 0]]).astype(np.int32)
+    ay = np.concatenate([t.ay[keep], sub[:, 1]]).astype(np.int32)
+    az = np.concatenate([t.az[keep], sub[:, 2]]).astype(np.int32)
+    lv = np.concatenate([t.level[keep], np.full(64, 4)]).astype(np.uint8)
+    bad = I.Octree(ax, ay, az, lv, 4)
+    with pytest.raises(vms.VmsError) as ei:
+        vms.vms_mesh_create(bad)
+    assert ei.value.code == vms.VMS_EMESH
+    with pytest.raises(vms.VmsError) as ei:
+        vms.vms_create(bad, None, vms.make_params(), stream=0)
+    assert ei.value.code == vms.VMS_EMESH
+
+
+def test_bad_parameters_rejected():
+    t = I.uniform_octree(2)
+    for kw in ({"dt": 0.0}, {"dt": -1.0}, {"rho": float("nan")}, {"mu": -0.1}, {"theta": 1.5}):
+        with pytest.raises(vms.VmsError) as ei:
+            vms.vms_create(t, None, vms.make_params(**kw), stream=0)
+        assert ei.value.code == vms.VMS_EINVAL, kw
+    with pytest.raises(vms.VmsError) as ei:
+        vms.vms_create(t, None, vms.make_params(quad_depth=4), stream=0)
+    assert ei.value.code == vms.VMS_EUNSUPPORTED
+
+
+def test_non_watertight_surface_rejected():
+    t = I.uniform_octree(2)
+    s = I.icosphere(1, 0.2, (0.5, 0.5, 0.5))
+    s.tris = s.tris[1:]
+    with pytest.raises(vms.VmsError) as ei:
+        vms.vms_create(t, s, vms.make_params(), stream=0)
+    assert ei.value.code == vms.VMS_EMESH
+    s2 = I.icosphere(1, 0.2, (0.5, 0.5, 0.5))
+    s2.tris[0] = s2.tris[0, [0, 2, 1]]  # one flipped triangle
+    with pytest.raises(vms.VmsError) as ei:
+        vms.vms_create(t, s2, vms.make_params(), stream=0)
+    assert ei.value.code == vms.VMS_EMESH
+
+
+def test_misaligned_leaf_rejected():
+    t = I.uniform_octree(2, max_level=3)
+    ax = t.ax.copy()
+    ax[0] += 1
+    with pytest.raises(vms.VmsError) as ei:
+        vms.vms_mesh_create(I.Octree(ax, t.ay, t.az, t.level, 3))
+    assert ei.value.code == vms.VMS_EINVAL
