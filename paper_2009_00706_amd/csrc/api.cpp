@@ -207,6 +207,10 @@ struct vms_ctx {
     int64_t *d_sq_off = nullptr;
     uint32_t *d_entries = nullptr;
     int64_t n_subgp = 0;
+    // assembly work items over the sub-cell points: at most ITEM_PTS points each
+    int64_t n_sub_items = 0;
+    int32_t *d_sub_el = nullptr, *d_sub_cnt = nullptr;
+    int64_t *d_sub_off = nullptr;
     // identity rows of inactive nodes
     int64_t n_ones = 0;
     int64_t *d_ones = nullptr;
@@ -413,7 +417,6 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
     if (prm->quad_depth < 0 || prm->quad_depth > 3)
         return fail(nullptr, VMS_EUNSUPPORTED, "quad_depth must be in [0, 3]");
     if (prm->precision > VMS_MIXED_FP16) return fail(nullptr, VMS_EUNSUPPORTED, "unknown precision");
-    if (prm->precision != VMS_FP64) return fail(nullptr, VMS_EUNSUPPORTED, "mixed precision not built");
     if (!std::isfinite(tree->root_len) || tree->root_len <= 0)
         return fail(nullptr, VMS_EINVAL, "root_len must be positive");
 
@@ -529,6 +532,21 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
             return bail(VMS_ENOMEM);
         rc = run_subquad(c, true);
         if (rc) return bail(rc);
+        // split every element's point list into work items of at most ITEM_PTS
+        // points (partial element matrices are summed by the atomic scatter)
+        const int ITEM_PTS = 64;
+        std::vector<int32_t> iel, icnt;
+        std::vector<int64_t> ioff;
+        for (int64_t i = 0; i < c->n_sq; ++i)
+            for (int64_t p = 0; p < c->sq_cnt[i]; p += ITEM_PTS) {
+                iel.push_back(c->sq_el[i]);
+                ioff.push_back(c->sq_off[i] + p);
+                icnt.push_back((int32_t)std::min<int64_t>(ITEM_PTS, c->sq_cnt[i] - p));
+            }
+        c->n_sub_items = (int64_t)iel.size();
+        if (upload(c, &c->d_sub_el, iel) || upload(c, &c->d_sub_off, ioff) ||
+            upload(c, &c->d_sub_cnt, icnt))
+            return bail(VMS_ENOMEM);
     }
 
     // ---- CSR pattern over non-IN elements
@@ -701,11 +719,11 @@ static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *re
     HIPCHK(c, hipGetLastError());
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
     // INTERCEPTED elements: kept sub-cell points
-    if (c->n_sq) {
-        a.n_items = c->n_sq;
-        a.items = c->d_sq_el;
-        a.pt_off = c->d_sq_off;
-        a.pt_cnt = c->d_sq_cnt;
+    if (c->n_sub_items) {
+        a.n_items = c->n_sub_items;
+        a.items = c->d_sub_el;
+        a.pt_off = c->d_sub_off;
+        a.pt_cnt = c->d_sub_cnt;
         a.entries = c->d_entries;
         if (fp64) vmsk::launch_assemble_f64(c->stream, a, true, mat);
         else vmsk::launch_assemble_mixed(c->stream, a, true, mat, c->prm.precision == VMS_MIXED_FP16);

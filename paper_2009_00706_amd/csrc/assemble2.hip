@@ -1,0 +1,549 @@
+// VMS element assembly of libvms (gfx950): two-stage contraction with MFMA.
+//
+// Residual and Jacobian of the VMS weak form, eq. (vms), with the fine
+// scales u' = -tau_M r_M (eq. uprime, f = 0, the viscous part of div sigma
+// dropped for trilinear fields) and p' = -rho tau_C div u (eq. pprime),
+// Crank-Nicolson in theta form (u_theta = theta u + (1-theta) u_prev), tau's
+// frozen at the current state.
+//
+// At each quadrature point q (weight W) the element matrix gains
+//   K[(a,i),(b,j)] += sum_{k,l} B[k][a] (W D^{ij}[k][l]) B[l][b],
+// B = [N; dN/dx; dN/dy; dN/dz] of the constrained basis (B C, C the
+// hanging-node operator M_e of Alg. 3) and D^{ij} the 4x4 coefficient block
+// of the linearised integrand for test component i and trial component j:
+//   D^{ij}[0][0] multiplies N_a N_b,  D^{ij}[0][1+l] N_a d_l N_b,
+//   D^{ij}[1+k][0] d_k N_a N_b,       D^{ij}[1+k][1+l] d_k N_a d_l N_b.
+// This is the precomputed-operator form of Alg. 6 / App. A (basis values and
+// gradients tabulated at Gauss points; the element matrix is a contraction
+// over points), split in two stages:
+//   stage 1 (VALU):  F_q[(i,k)][(b,j)] = sum_l W D^{ij}[k][l] B[l][b]
+//   stage 2 (MFMA):  K[a][(b,j,i)]     = sum_{q,k} B_q[k][a] F_q[(i,k)][(b,j)]
+// Stage 2 is a GEMM with the 8 basis rows a as M (padded to 16), the
+// contraction over (point, derivative) and the 128 columns (b, j, i) as N in
+// eight 16-column tiles t = (i, b-half) with columns (b mod 4, j), j fastest.
+//
+// Precision forms: FP64 uses v_mfma_f64_16x16x4 (one point per k-step).
+// MIXED_BF16 splits both operands into three bf16 terms and MIXED_FP16 into
+// two fp16 terms (with power-of-two scaling), accumulating in FP32 with
+// v_mfma_f32_16x16x32 (eight points per k-step); everything before the
+// contraction runs in FP32 and the result is written as FP32.
+//
+// One 64-lane workgroup per element, points in chunks of 8.
+#include "geom.h"
+#include "kernels.h"
+
+namespace vmsk {
+using namespace vmsd;
+
+#ifndef VMS_CP64
+#define VMS_CP64 8
+#endif
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+
+
+// per-point quantities in LDS: stabilisation parameters, interpolated state and
+// the factors that make every D entry a short sum (see dblock)
+enum {
+    QW = 0, QTM, QTC, QTB,
+    QUT = 4, QUP = 7, QA = 10, QG = 19, QGA = 28,  // u_theta, u', A = I/dt + theta grad u, grad u, grad u A
+    QY = 37, QX = 40, QCP = 43, QV0 = 46, QW0 = 49, QS9 = 52, QZ9 = 61,
+    QYM = 70, QCM = 73, QXM = 76,
+    QRC = 79,  // 16 residual coefficients r^i[k] (weight folded in)
+    NQ2 = 95
+};
+
+__device__ inline const double *field_in(const AsmArgs &a, int f) {
+    switch (f) {
+        case 0: return a.f[0];
+        case 1: return a.f[1];
+        case 2: return a.f[2];
+        case 3: return a.f[3];
+        case 4: return a.f[4];
+        case 5: return a.f[5];
+        default: return a.f[6];
+    }
+}
+
+template <typename T> __device__ inline T rsq(T x);
+template <> __device__ inline double rsq<double>(double x) { return rsqrt(x); }
+template <> __device__ inline float rsq<float>(float x) { return __frsqrt_rn(x); }
+
+// reference coordinates (double) and weight of point pt of the item
+template <bool SUB>
+__device__ inline void point_xw(const AsmArgs &a, int64_t item, int pt, double h, double xi[3],
+                                double &w) {
+    if (!SUB) {
+        for (int k = 0; k < 3; ++k) xi[k] = ((pt >> k) & 1) ? VMS_XI : -VMS_XI;
+        const double hh = 0.5 * h;
+        w = hh * hh * hh;
+        return;
+    }
+    const uint32_t en = a.entries[a.pt_off[item] + pt];
+    const int l = (int)(en & 3u), D = a.depth;
+    const uint32_t key = en >> 2;
+    const int gp = (int)((key >> (3 * (D - l))) & 7u);
+    const double sl = ldexp(1.0, -l);
+    for (int ax = 0; ax < 3; ++ax) {
+        double f = 0.0;
+        for (int k = 1; k <= l; ++k)
+            if ((key >> (3 * (D - k + 1) + ax)) & 1u) f += ldexp(1.0, -k);
+        f = __dadd_rn(f, sl * (((gp >> ax) & 1) ? VMS_GP : VMS_GM));
+        xi[ax] = __dsub_rn(2.0 * f, 1.0);
+    }
+    const double hs = h * ldexp(1.0, -(l + 1));
+    w = hs * hs * hs;
+}
+
+// D^{ij} (4x4) at one point, times W, from the per-point factors:
+//   momentum/velocity: D00 = rho A_ij - tau rho (grad u A)_ij
+//     D0l = d_ij theta(rho u_l + u'_l) - theta tau rho g_ij u_l
+//     Dk0 = A_ij Y_k + A_kj c_i - theta d_kj u'_i + (grad u A)_ij X_k
+//     Dkl = mu theta (d_ij d_kl + d_kj d_il) + rho tau_C theta d_ki d_lj + d_ij S_kl
+//           + theta d_kj c_i u_l + g_ij Z_kl
+//   with Y = tau(rho u + u'), X = -taubar tau rho u', c = tau u' - taubar tau rho s,
+//   S_kl = theta(tau rho u_k u_l + tau u'_k u_l + taubar u'_k u'_l),
+//   Z_kl = -taubar tau rho theta u'_k u_l, s = (u'.grad) u;
+//   momentum/pressure: D0l = -tau g_il, Dk0 = -d_ki,
+//     Dkl = d_li Ym_k + d_kl cm_i + Xm_k g_il, Ym = tau u + tau/rho u',
+//     cm = tau/rho u' - taubar tau s, Xm = -taubar tau u';
+//   continuity/velocity: D0l = theta d_lj, Dk0 = tau A_kj, Dkl = tau theta d_kj u_l;
+//   continuity/pressure: Dkl = tau/rho d_kl.
+template <typename T>
+__device__ inline void dblock(const T *Q, int i, int j, T rho, T mu, T th, T D[4][4]) {
+    const T W = Q[QW], tauM = Q[QTM];
+    if (i < 3 && j < 3) {
+        const T dij = (i == j) ? T(1) : T(0);
+        const T Aij = Q[QA + 3 * i + j], gij = Q[QG + 3 * i + j], GAij = Q[QGA + 3 * i + j];
+        const T cpi = Q[QCP + i], upi = Q[QUP + i];
+        const T mth = mu * th, rtc = rho * Q[QTC] * th;
+        D[0][0] = rho * Aij - tauM * rho * GAij;
+        for (int l = 0; l < 3; ++l) D[0][1 + l] = dij * Q[QV0 + l] + gij * Q[QW0 + l];
+        for (int k = 0; k < 3; ++k) {
+            const T Akj = Q[QA + 3 * k + j];
+            D[1 + k][0] = Aij * Q[QY + k] + Akj * cpi + GAij * Q[QX + k] - ((k == j) ? th * upi : T(0));
+            for (int l = 0; l < 3; ++l) {
+                T v = dij * Q[QS9 + 3 * k + l] + gij * Q[QZ9 + 3 * k + l];
+                if (k == j) v += th * cpi * Q[QUT + l];
+                if (i == j && k == l) v += mth;
+                if (k == j && i == l) v += mth;
+                if (k == i && l == j) v += rtc;
+                D[1 + k][1 + l] = v;
+            }
+        }
+    } else if (i < 3) {  // momentum test, pressure trial
+        const T cmi = Q[QCM + i];
+        D[0][0] = T(0);
+        for (int l = 0; l < 3; ++l) D[0][1 + l] = -tauM * Q[QG + 3 * i + l];
+        for (int k = 0; k < 3; ++k) {
+            D[1 + k][0] = (k == i) ? T(-1) : T(0);
+            for (int l = 0; l < 3; ++l) {
+                T v = Q[QXM + k] * Q[QG + 3 * i + l];
+                if (l == i) v += Q[QYM + k];
+                if (k == l) v += cmi;
+                D[1 + k][1 + l] = v;
+            }
+        }
+    } else if (j < 3) {  // continuity test, velocity trial
+        D[0][0] = T(0);
+        for (int l = 0; l < 3; ++l) D[0][1 + l] = (l == j) ? th : T(0);
+        for (int k = 0; k < 3; ++k) {
+            D[1 + k][0] = tauM * Q[QA + 3 * k + j];
+            for (int l = 0; l < 3; ++l) D[1 + k][1 + l] = (k == j) ? tauM * th * Q[QUT + l] : T(0);
+        }
+    } else {  // continuity test, pressure trial
+        const T v = tauM / rho;
+        for (int k = 0; k < 4; ++k)
+            for (int l = 0; l < 4; ++l) D[k][l] = (k == l && k > 0) ? v : T(0);
+    }
+    for (int k = 0; k < 4; ++k)
+        for (int l = 0; l < 4; ++l) D[k][l] *= W;
+}
+
+// split x into three bf16 terms with x ~= h + m + l
+__device__ inline void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l) {
+    h = (__bf16)x;
+    const float r1 = x - (float)h;
+    m = (__bf16)r1;
+    l = (__bf16)(r1 - (float)m);
+}
+__device__ inline void split2h(float x, _Float16 &h, _Float16 &l) {
+    h = (_Float16)x;
+    l = (_Float16)(x - (float)h);
+}
+
+// CP points per chunk (FP64: 4, mixed: 8 = one MFMA k-step of 32)
+template <typename T, int MODE, bool SUB, bool MAT, int CP>
+__global__ __launch_bounds__(64) void k_asm2(AsmArgs a) {
+    __shared__ T sU[7][8];
+    __shared__ T sC[8][8];
+    __shared__ T sB[CP][4][8];
+    __shared__ T sI[CP][7][4];
+    __shared__ T sQ[CP][NQ2];
+    __shared__ T sD[CP][4][4][4][4];  // [p][i][j][k][l], weight folded in
+    __shared__ T sSc[CP];             // fp16 form: per-point power-of-two balance
+    __shared__ int sM[8];
+    const int lane = threadIdx.x;
+    const int64_t item = blockIdx.x;
+    const int e = a.items[item];
+    const bool hang = a.has_hang[e] != 0;
+    const double hd = ldexp(a.root_len, -(int)a.level[e]);
+    const double two_over_h = 2.0 / hd;
+    const T h = (T)hd;
+    if (lane < 8) sM[lane] = a.masters[8 * (int64_t)e + lane];
+    {
+        const int v = lane >> 3, s = lane & 7, bit = 2 * (v * 8 + s);
+        const uint32_t code = (a.ccode[4 * (int64_t)e + (bit >> 5)] >> (bit & 31)) & 3u;
+        sC[v][s] = code == 3u ? T(1) : (code == 2u ? T(0.5) : (code == 1u ? T(0.25) : T(0)));
+    }
+    __syncthreads();
+    if (lane < 56) {
+        const int f = lane >> 3, s = lane & 7, m = sM[s];
+        sU[f][s] = m >= 0 ? (T)field_in(a, f)[m] : T(0);
+    }
+    const int npts = SUB ? a.pt_cnt[item] : 8;
+    const T rho = (T)a.rho, mu = (T)a.mu, th = (T)a.theta;
+    const T idt = (T)(1.0 / a.dt), irho = (T)(1.0 / a.rho);
+    // G = (2/h)^2 I: u.G.u = gG |u|^2; tau_M^-2 = c_t/dt^2 + gG |u|^2 + c_i nu^2 G:G;
+    // tau_C = 1/(tau_M tr G) = (h^2/12)/tau_M
+    const double gGd = 4.0 / (hd * hd), nud = a.mu / a.rho;
+    const T gG = (T)gGd;
+    const T tau0 = (T)(a.c_t / (a.dt * a.dt) + a.c_i * nud * nud * 3.0 * gGd * gGd);
+    const T h2_12 = (T)(hd * hd / 12.0);
+    // fp16 form: basis rows scaled by h/2 (values and scaled gradients in [-1, 1])
+    const T bscale = MODE == 2 ? (T)(0.5 * hd) : T(1);
+
+    // stage-2 accumulators and residual
+    v4d accd[8];
+    v4f accf[8];
+    for (int t = 0; t < 8; ++t) {
+        accd[t] = v4d{0, 0, 0, 0};
+        accf[t] = v4f{0, 0, 0, 0};
+    }
+    T R = T(0);  // lanes < 32: residual of (a = lane & 7, i = lane >> 3)
+
+    for (int base = 0; base < npts; base += CP) {
+        const int np = min(CP, npts - base);
+        // ---- phase 1: constrained basis at the chunk's points (lane = (p, s))
+        for (int idx = lane; idx < CP * 8; idx += 64) {
+            const int p = idx >> 3, s = idx & 7;
+            T b[4] = {T(0), T(0), T(0), T(0)};
+            double w = 0.0;
+            if (p < np) {
+                double xi[3];
+                point_xw<SUB>(a, item, base + p, hd, xi, w);
+                for (int v = 0; v < 8; ++v) {
+                    const T c = hang ? sC[v][s] : (v == s ? T(1) : T(0));
+                    if (c == T(0)) continue;
+                    double f[3], g[3];
+                    for (int k = 0; k < 3; ++k) {
+                        const double sg = ((v >> k) & 1) ? 1.0 : -1.0;
+                        f[k] = 0.5 * (1.0 + sg * xi[k]);
+                        g[k] = 0.5 * sg * two_over_h;
+                    }
+                    b[0] += c * (T)(f[0] * f[1] * f[2]);
+                    b[1] += c * (T)(g[0] * f[1] * f[2]);
+                    b[2] += c * (T)(f[0] * g[1] * f[2]);
+                    b[3] += c * (T)(f[0] * f[1] * g[2]);
+                }
+            }
+            for (int k = 0; k < 4; ++k) sB[p][k][s] = b[k];
+            if (s == 0) {
+                sQ[p][QW] = (T)w;
+                sSc[p] = T(1);
+            }
+        }
+        __syncthreads();
+        // ---- phase 2: interpolation of the 7 nodal fields (lane = (p, field))
+        for (int idx = lane; idx < CP * 8; idx += 64) {
+            const int p = idx >> 3, f = idx & 7;
+            if (p < np && f < 7) {
+                T v[4] = {T(0), T(0), T(0), T(0)};
+                for (int s = 0; s < 8; ++s) {
+                    const T u = sU[f][s];
+                    for (int k = 0; k < 4; ++k) v[k] += sB[p][k][s] * u;
+                }
+                for (int k = 0; k < 4; ++k) sI[p][f][k] = v[k];
+            }
+        }
+        __syncthreads();
+        // ---- phase 3: point quantities (lane = p)
+        if (lane < np) {
+            const int p = lane;
+            T ut[3], at[3], gu[3][3], gp[3];
+            for (int c = 0; c < 3; ++c) {
+                ut[c] = th * sI[p][c][0] + (T(1) - th) * sI[p][4 + c][0];
+                at[c] = (sI[p][c][0] - sI[p][4 + c][0]) * idt;
+                for (int m = 0; m < 3; ++m) gu[c][m] = th * sI[p][c][1 + m] + (T(1) - th) * sI[p][4 + c][1 + m];
+                gp[c] = sI[p][3][1 + c];
+            }
+            const T pr = sI[p][3][0];
+            T conv[3], rM[3];
+            for (int c = 0; c < 3; ++c) {
+                conv[c] = ut[0] * gu[c][0] + ut[1] * gu[c][1] + ut[2] * gu[c][2];
+                rM[c] = rho * (at[c] + conv[c]) + gp[c];
+            }
+            const T div = gu[0][0] + gu[1][1] + gu[2][2];
+            const T uGu = gG * (ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
+            const T tauM = rsq<T>(tau0 + uGu);
+            const T tauC = h2_12 / tauM;
+            T up[3];
+            for (int c = 0; c < 3; ++c) up[c] = -tauM * rM[c];
+            const T pp = -rho * tauC * div;
+            const T upg = gG * (up[0] * up[0] + up[1] * up[1] + up[2] * up[2]);
+            const T tb = upg > T(0) ? rsq<T>(upg) : T(0);
+            T *q = sQ[p];
+            const T W = q[QW];
+            q[QTM] = tauM;
+            q[QTC] = tauC;
+            q[QTB] = tb;
+            T sv[3];
+            for (int c = 0; c < 3; ++c) sv[c] = up[0] * gu[c][0] + up[1] * gu[c][1] + up[2] * gu[c][2];
+            const T tr = tauM * rho, tbtr = tb * tauM * rho, tbt = tb * tauM, tir = tauM * irho;
+            for (int c = 0; c < 3; ++c) {
+                q[QUT + c] = ut[c];
+                q[QUP + c] = up[c];
+                q[QY + c] = tr * ut[c] + tauM * up[c];
+                q[QX + c] = -tbtr * up[c];
+                q[QCP + c] = tauM * up[c] - tbtr * sv[c];
+                q[QV0 + c] = th * (rho * ut[c] + up[c]);
+                q[QW0 + c] = -th * tr * ut[c];
+                q[QYM + c] = tauM * ut[c] + tir * up[c];
+                q[QCM + c] = tir * up[c] - tbt * sv[c];
+                q[QXM + c] = -tbt * up[c];
+                for (int m = 0; m < 3; ++m) {
+                    const T Acm = (c == m ? idt : T(0)) + th * gu[c][m];
+                    q[QA + 3 * c + m] = Acm;
+                    q[QG + 3 * c + m] = gu[c][m];
+                    T v = T(0);
+                    for (int k = 0; k < 3; ++k) v += gu[c][k] * ((k == m ? idt : T(0)) + th * gu[k][m]);
+                    q[QGA + 3 * c + m] = v;
+                    q[QS9 + 3 * c + m] = th * (tr * ut[c] * ut[m] + tauM * up[c] * ut[m] + tb * up[c] * up[m]);
+                    q[QZ9 + 3 * c + m] = -tbtr * th * up[c] * ut[m];
+                }
+            }
+            // residual coefficients r^i[k] (times W)
+            for (int c = 0; c < 3; ++c) {
+                q[QRC + 4 * c] = W * (rho * at[c] + rho * conv[c] + sv[c]);
+                for (int k = 0; k < 3; ++k)
+                    q[QRC + 4 * c + 1 + k] =
+                        W * (mu * (gu[c][k] + gu[k][c]) - (k == c ? pr + pp : T(0)) - ut[k] * up[c] -
+                             up[k] * up[c] * irho + tb * up[k] * sv[c]);
+            }
+            q[QRC + 12] = W * div;
+            for (int k = 0; k < 3; ++k) q[QRC + 13 + k] = -W * up[k] * irho;
+            if (MODE == 2) {
+                // balance a power of two between the two fp16 operands: a product is
+                // about W (2/h)^2 100 (mass coefficient rho/dt ~ 100 for the workloads)
+                const float x = (float)((double)W * 4.0 / (hd * hd) * 100.0);
+                int ex;
+                frexpf(x, &ex);
+                sSc[p] = ldexpf(1.0f, ex / 2);
+            }
+        }
+        __syncthreads();
+        if (MAT) {
+            // ---- phase 4: D blocks (one (p, i, j) block per task), weight folded in
+            for (int bidx = lane; bidx < CP * 16; bidx += 64) {
+                const int p = bidx >> 4, i = (bidx >> 2) & 3, j = bidx & 3;
+                T D[4][4];
+                if (p < np) {
+                    dblock<T>(sQ[p], i, j, rho, mu, th, D);
+                } else {
+                    for (int k = 0; k < 4; ++k)
+                        for (int l = 0; l < 4; ++l) D[k][l] = T(0);
+                }
+                for (int k = 0; k < 4; ++k)
+                    for (int l = 0; l < 4; ++l) sD[p][i][j][k][l] = D[k][l];
+            }
+            __syncthreads();
+            // ---- phase 5: stage 1 (VALU) and stage 2 (MFMA)
+            const int col = lane & 15, bb = col >> 2, jc = col & 3;
+            if (MODE == 0) {
+                const int k = lane >> 4, arow = lane & 15;
+                for (int p = 0; p < np; ++p) {
+                    const double A = arow < 8 ? (double)sB[p][k][arow] : 0.0;
+                    double Bv[2][4];
+                    for (int bh = 0; bh < 2; ++bh)
+                        for (int m = 0; m < 4; ++m) Bv[bh][m] = (double)sB[p][m][4 * bh + bb];
+                    for (int i = 0; i < 4; ++i) {
+                        double Dv[4];
+                        for (int m = 0; m < 4; ++m) Dv[m] = (double)sD[p][i][jc][k][m];
+                        for (int bh = 0; bh < 2; ++bh) {
+                            const double F = Dv[0] * Bv[bh][0] + Dv[1] * Bv[bh][1] + Dv[2] * Bv[bh][2] +
+                                             Dv[3] * Bv[bh][3];
+                            accd[2 * i + bh] = __builtin_amdgcn_mfma_f64_16x16x4f64(A, F, accd[2 * i + bh], 0, 0, 0);
+                        }
+                    }
+                }
+            } else {
+                // k-step of 32 = 8 points x 4 derivative rows; lane group g holds points 2g, 2g+1
+                const int g = lane >> 4, row = lane & 15;
+                const int ar = row & 7;
+                const bool hi_rows = row < 8;
+                float Av[8];
+                for (int t = 0; t < 8; ++t) {
+                    const int p = 2 * g + (t >> 2), k = t & 3;
+                    float v = (float)sB[p][k][ar] * (float)bscale;
+                    if (MODE == 2) v *= (float)sSc[p];
+                    Av[t] = v;
+                }
+                // basis values of the lane's two points at its two columns b
+                float Bc[2][2][4];
+                for (int pp = 0; pp < 2; ++pp)
+                    for (int bh = 0; bh < 2; ++bh)
+                        for (int m = 0; m < 4; ++m) Bc[pp][bh][m] = (float)sB[2 * g + pp][m][4 * bh + bb];
+                float fs[2] = {1.f, 1.f};
+                if (MODE == 2)
+                    for (int pp = 0; pp < 2; ++pp)
+                        fs[pp] = (float)(1.0 / (double)bscale) / (float)sSc[2 * g + pp];
+                if (MODE == 1) {
+                    v8bf Ahm, Alo;
+                    for (int t = 0; t < 8; ++t) {
+                        __bf16 x1, x2, x3;
+                        split3(Av[t], x1, x2, x3);
+                        Ahm[t] = hi_rows ? x1 : x2;
+                        Alo[t] = hi_rows ? x3 : (__bf16)0.0f;
+                    }
+                    for (int i = 0; i < 4; ++i) {
+                        v8bf F1[2], F2[2], F3[2];
+                        for (int t = 0; t < 8; ++t) {
+                            const int pp = t >> 2, p = 2 * g + pp, k = t & 3;
+                            float d[4];
+                            for (int m = 0; m < 4; ++m) d[m] = (float)sD[p][i][jc][k][m];
+                            for (int bh = 0; bh < 2; ++bh) {
+                                const float F = d[0] * Bc[pp][bh][0] + d[1] * Bc[pp][bh][1] +
+                                                d[2] * Bc[pp][bh][2] + d[3] * Bc[pp][bh][3];
+                                __bf16 x1, x2, x3;
+                                split3(F, x1, x2, x3);
+                                F1[bh][t] = x1; F2[bh][t] = x2; F3[bh][t] = x3;
+                            }
+                        }
+                        for (int bh = 0; bh < 2; ++bh) {
+                            v4f acc = accf[2 * i + bh];
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ahm, F1[bh], acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ahm, F2[bh], acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ahm, F3[bh], acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Alo, F1[bh], acc, 0, 0, 0);
+                            accf[2 * i + bh] = acc;
+                        }
+                    }
+                } else {
+                    v8h Ahm;
+                    for (int t = 0; t < 8; ++t) {
+                        _Float16 x1, x2;
+                        split2h(Av[t], x1, x2);
+                        Ahm[t] = hi_rows ? x1 : x2;
+                    }
+                    for (int i = 0; i < 4; ++i) {
+                        v8h F1[2], F2[2];
+                        for (int t = 0; t < 8; ++t) {
+                            const int pp = t >> 2, p = 2 * g + pp, k = t & 3;
+                            float d[4];
+                            for (int m = 0; m < 4; ++m) d[m] = (float)sD[p][i][jc][k][m];
+                            for (int bh = 0; bh < 2; ++bh) {
+                                // undo the basis scaling and the balance on this operand
+                                const float F = (d[0] * Bc[pp][bh][0] + d[1] * Bc[pp][bh][1] +
+                                                 d[2] * Bc[pp][bh][2] + d[3] * Bc[pp][bh][3]) * fs[pp];
+                                _Float16 x1, x2;
+                                split2h(F, x1, x2);
+                                F1[bh][t] = x1; F2[bh][t] = x2;
+                            }
+                        }
+                        for (int bh = 0; bh < 2; ++bh) {
+                            v4f acc = accf[2 * i + bh];
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ahm, F1[bh], acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ahm, F2[bh], acc, 0, 0, 0);
+                            accf[2 * i + bh] = acc;
+                        }
+                    }
+                }
+            }
+        }
+        // residual: lanes < 32, (a = lane & 7, i = lane >> 3)
+        if (lane < 32) {
+            const int av = lane & 7, i = lane >> 3;
+            for (int p = 0; p < np; ++p)
+                R += sB[p][0][av] * sQ[p][QRC + 4 * i] + sB[p][1][av] * sQ[p][QRC + 4 * i + 1] +
+                     sB[p][2][av] * sQ[p][QRC + 4 * i + 2] + sB[p][3][av] * sQ[p][QRC + 4 * i + 3];
+        }
+        __syncthreads();
+    }
+
+    // ---- scatter
+    if (MAT) {
+        const int col = lane & 15, bb = col >> 2, jc = col & 3;
+        if (MODE == 0) {
+            double *vals = (double *)a.vals;
+            for (int t = 0; t < 8; ++t) {
+                const int i = t >> 1, b = 4 * (t & 1) + bb;
+                if (sM[b] < 0) continue;
+                for (int r = 0; r < 2; ++r) {
+                    const int av = 4 * r + (lane >> 4);  // output row = 4 r + lane / 16
+                    if (sM[av] < 0) continue;
+                    const int64_t idx = a.rowbase[8 * (int64_t)e + av] +
+                                        (int64_t)i * a.rowlen[8 * (int64_t)e + av] +
+                                        4 * (int64_t)a.kk[64 * (int64_t)e + 8 * av + b] + jc;
+                    atomicAdd(vals + idx, accd[t][r]);
+                }
+            }
+        } else {
+            // rows 8..15 carry the second split term: fold them onto rows 0..7
+            float *vals = (float *)a.vals;
+            for (int t = 0; t < 8; ++t) {
+                v4f v = accf[t];
+                for (int r = 0; r < 4; ++r) v[r] += __shfl_down(v[r], 32, 64);
+                if (lane >= 32) continue;
+                const int i = t >> 1, b = 4 * (t & 1) + bb;
+                if (sM[b] < 0) continue;
+                for (int r = 0; r < 4; ++r) {
+                    const int av = 4 * (lane >> 4) + r;  // output row = 4 (lane / 16) + r
+                    if (sM[av] < 0) continue;
+                    const int64_t idx = a.rowbase[8 * (int64_t)e + av] +
+                                        (int64_t)i * a.rowlen[8 * (int64_t)e + av] +
+                                        4 * (int64_t)a.kk[64 * (int64_t)e + 8 * av + b] + jc;
+                    atomicAdd(vals + idx, v[r]);
+                }
+            }
+        }
+    }
+    if (lane < 32 && a.resid) {
+        const int av = lane & 7, i = lane >> 3;
+        if (sM[av] >= 0) atomicAdd(a.resid + 4 * (int64_t)sM[av] + i, (double)R);
+    }
+}
+
+void launch_assemble_f64(hipStream_t s, const AsmArgs &a, bool sub, bool mat) {
+    if (a.n_items <= 0) return;
+    dim3 grid((unsigned)a.n_items), block(64);
+    if (!sub) {
+        if (mat) hipLaunchKernelGGL((k_asm2<double, 0, false, true, VMS_CP64>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_asm2<double, 0, false, false, VMS_CP64>), grid, block, 0, s, a);
+    } else {
+        if (mat) hipLaunchKernelGGL((k_asm2<double, 0, true, true, VMS_CP64>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_asm2<double, 0, true, false, VMS_CP64>), grid, block, 0, s, a);
+    }
+}
+
+void launch_assemble_mixed(hipStream_t s, const AsmArgs &a, bool sub, bool mat, int fp16) {
+    if (a.n_items <= 0) return;
+    dim3 grid((unsigned)a.n_items), block(64);
+#define VMS_L(MODE)                                                                              \
+    do {                                                                                         \
+        if (!sub) {                                                                              \
+            if (mat) hipLaunchKernelGGL((k_asm2<float, MODE, false, true, 8>), grid, block, 0, s, a); \
+            else hipLaunchKernelGGL((k_asm2<float, MODE, false, false, 8>), grid, block, 0, s, a);    \
+        } else {                                                                                 \
+            if (mat) hipLaunchKernelGGL((k_asm2<float, MODE, true, true, 8>), grid, block, 0, s, a);  \
+            else hipLaunchKernelGGL((k_asm2<float, MODE, true, false, 8>), grid, block, 0, s, a);     \
+        }                                                                                        \
+    } while (0)
+    if (fp16) VMS_L(2);
+    else VMS_L(1);
+#undef VMS_L
+}
+
+}  // namespace vmsk

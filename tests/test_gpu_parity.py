@@ -249,3 +249,24 @@ def test_inout_classify_exact_parity(vms, oracle):
     torch.cuda.synchronize()
     assert np.array_equal(lab.cpu().numpy(), ref)
     assert ref[-200:].all()  # surface vertices are IN
+
+
+@pytest.mark.parametrize("prec,tol", [(1, 1e-5), (2, 1e-4)])
+def test_mixed_precision_error(vms, oracle, prec, tol):
+    """BF16x3 / FP16x2 MFMA contractions with FP32 accumulation: normwise relative error
+    of the Jacobian and the residual against the FP64 reference, per output."""
+    c = tuple(0.5 + o for o in I.BODY_OFFSET)
+    t = I.sphere_refined_octree(c, 0.2, 3, 5, 1.5)
+    s = I.icosphere(2, 0.2, c)
+    asm = vms.Assembler(t, s, vms.make_params(quad_depth=3, precision=prec))
+    f = I.make_fields(node_xyz(asm, t), 1001)
+    asm.set_fields(f)
+    asm.assemble()
+    vals = asm.vals.cpu().numpy().astype(np.float64)
+    res = asm.resid.cpu().numpy()
+    ms, mk, sub, V, R = oracle_run(oracle, t, s, f)
+    ej = np.linalg.norm(vals - V) / np.linalg.norm(V)
+    er = np.linalg.norm(res - R) / np.linalg.norm(R)
+    print(f"precision {prec}: rel err J {ej:.3e} R {er:.3e}")
+    assert ej <= tol and er <= tol
+    asm.close()
