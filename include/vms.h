@@ -166,8 +166,8 @@ int vms_apply(vms_ctx *ctx, const vms_fields *f, double *resid, double *norm2);
 /* Exact in-out labels of n points against a surface (Alg. 5's question,
  * answered exactly): px, py, pz DEVICE arrays of n doubles, labels DEVICE
  * uint8 (1 IN or on the surface, 0 OUT). mode VMS_INOUT_EXACT, or
- * VMS_INOUT_LEARNED with mlp a DEVICE pointer to a vms_mlp (points whose
- * |prediction| >= margin take the network's sign, the rest the exact test).
+ * VMS_INOUT_LEARNED with mlp a vms_mlp handle (points whose |prediction| >=
+ * its margin take the network's sign, the rest the exact test).
  * The surface's acceleration structure is built on the host at each call
  * unless a context-free cache handle is used (see inout_prepare).
  * stream is a hipStream_t. */
@@ -202,6 +202,44 @@ void vms_mesh_destroy(vms_mesh *h);
  * assembly kernel, of the last vms_assemble / vms_apply. */
 int vms_set_timing(vms_ctx *ctx, int on);
 int vms_last_timing(vms_ctx *ctx, float *ms);
+
+/* Learned in-out filter (signed-distance network; negative inside):
+ * xh = 2 (x - lo)/(hi - lo) - 1, phi = [sin 2 pi B xh; cos 2 pi B xh] with
+ * B (32 x 3, HOST float, row-major), three hidden SiLU layers of width 64, a
+ * linear output; theta (HOST float[12545]): W1 (64x64 row-major, out x in),
+ * b1, W2, b2, W3, b3, w4 (64), b4. Training regresses the signed distance
+ * clamped to [-trunc, trunc] (loss: mean of squared error / 2) with Adam.
+ * The handle owns its device memory and is bound to stream. Callers that use
+ * it for classification: points with |prediction| >= margin take its sign, the
+ * rest the exact test (the margin is the caller's calibration, default +inf).
+ * The box must contain the surface's box: a point outside it is reported as
+ * far outside (prediction +inf), which is exact. */
+typedef struct vms_mlp vms_mlp;
+int vms_mlp_create(vms_mlp **out, const double *lo, const double *hi, const float *theta,
+                   const float *B, float trunc, void *stream);
+int vms_mlp_get_params(vms_mlp *m, float *theta /* HOST */);
+int vms_mlp_set_margin(vms_mlp *m, float margin);
+/* Loss and gradient over n samples (DEVICE points, DEVICE exact signed
+ * distances); grad DEVICE float[12545] (nullable), loss HOST (nullable). */
+int vms_mlp_grad(vms_mlp *m, const double *px, const double *py, const double *pz, const double *sdf,
+                 int64_t n, float *grad, double *loss);
+/* steps Adam updates (beta 0.9, 0.999, eps 1e-8) over consecutive batches of
+ * the n samples (wrapping around); last_loss HOST (nullable): loss of the last batch. */
+int vms_mlp_train(vms_mlp *m, const double *px, const double *py, const double *pz, const double *sdf,
+                  int64_t n, int steps, int batch, float lr, double *last_loss);
+/* One Adam update with a given DEVICE gradient. */
+int vms_mlp_adam_step(vms_mlp *m, const float *grad, float lr);
+/* Network outputs of n DEVICE points into DEVICE float pred (FP16 MFMA inference). */
+int vms_mlp_predict(vms_mlp *m, const double *px, const double *py, const double *pz, int64_t n,
+                    float *pred);
+const char *vms_mlp_last_error(void);
+void vms_mlp_destroy(vms_mlp *m);
+
+/* Exact signed distance of n DEVICE points to the handle's surface, clamped to
+ * [-trunc, trunc] (negative inside; sign from the exact in-out test), into
+ * DEVICE sdf. Synchronises the handle's stream. */
+int vms_sdf_sample(inout_handle *h, const double *px, const double *py, const double *pz, int64_t n,
+                   double trunc, double *sdf);
 
 /* Counters of a context (HOST out[6]): OUT elements, INTERCEPTED elements,
  * points labelled by the last sub-cell quadrature, degenerate directions

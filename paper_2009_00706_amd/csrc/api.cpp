@@ -18,6 +18,10 @@
 
 using vmsk::SurfDev;
 
+int vmsm_sdf(hipStream_t s, const vmsk::SurfDev &S, const std::vector<double> &tv, const double *lo,
+             const double *hi, const double *px, const double *py, const double *pz, int64_t n,
+             double trunc, double *out);
+
 namespace {
 
 std::mutex g_err_mu;
@@ -818,7 +822,7 @@ int inout_classify_prepared(inout_handle *h, const double *px, const double *py,
         vmsk::launch_point_labels(h->stream, h->surf.S, n, px, py, pz, labels, nullptr);
     } else if (mode == VMS_INOUT_LEARNED) {
         if (!mlp) return fail(nullptr, VMS_EINVAL, "learned mode needs a network");
-        int rc = vmsm::classify_learned(h->stream, h->filter, (const vmsm::MlpDev *)mlp, h->surf.S, px,
+        int rc = vmsm::classify_learned(h->stream, h->filter, (const vmsm::MlpHandle *)mlp, h->surf.S, px,
                                         py, pz, n, labels);
         if (rc) return fail(nullptr, rc, "learned classification failed");
     } else {
@@ -826,6 +830,15 @@ int inout_classify_prepared(inout_handle *h, const double *px, const double *py,
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(nullptr, VMS_EHIP, hipGetErrorString(e));
+    return VMS_OK;
+}
+
+int vms_sdf_sample(inout_handle *h, const double *px, const double *py, const double *pz, int64_t n,
+                   double trunc, double *sdf) {
+    if (!h || n < 0 || (n > 0 && (!px || !py || !pz || !sdf)) || !(trunc > 0))
+        return fail(nullptr, VMS_EINVAL, "bad arguments");
+    int rc = vmsm_sdf(h->stream, h->surf.S, h->surf.tv, h->surf.lo, h->surf.hi, px, py, pz, n, trunc, sdf);
+    if (rc) return fail(nullptr, rc, "signed-distance sampling failed");
     return VMS_OK;
 }
 

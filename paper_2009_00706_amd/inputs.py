@@ -441,3 +441,27 @@ def box_surface(lo, hi) -> Surface:
     s = Surface(v, np.array(t, np.int32), {"kind": "box", "lo": lo.tolist(), "hi": hi.tolist()})
     orient_outward(s)
     return s
+
+
+def sdf_sample_points(surf: Surface, lo, hi, n: int, seed: int, near_frac: float = 0.7,
+                      near_dist: float = 0.1):
+    """Training positions for the signed-distance network: a fraction near the
+    surface (area-weighted random surface point, offset along the triangle
+    normal by U(-near_dist, near_dist)), the rest uniform in the box."""
+    rng = np.random.default_rng(seed)
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    n_near = int(round(near_frac * n))
+    a, b, c = (surf.verts[surf.tris[:, k]] for k in range(3))
+    cr = np.cross(b - a, c - a)
+    area = 0.5 * np.linalg.norm(cr, axis=1)
+    t = rng.choice(surf.n_tri, n_near, p=area / area.sum())
+    r1, r2 = rng.uniform(size=(2, n_near))
+    s = np.sqrt(r1)
+    pts = (1 - s)[:, None] * a[t] + (s * (1 - r2))[:, None] * b[t] + (s * r2)[:, None] * c[t]
+    nrm = cr[t] / np.linalg.norm(cr[t], axis=1, keepdims=True)
+    pts = pts + nrm * rng.uniform(-near_dist, near_dist, n_near)[:, None]
+    uni = rng.uniform(lo, hi, (n - n_near, 3))
+    out = np.concatenate([pts, uni])
+    out = np.clip(out, lo, hi)
+    return out[rng.permutation(n)]

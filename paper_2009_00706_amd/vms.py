@@ -26,7 +26,9 @@ VMS_RELABEL = 1
 EXPORTED = ["vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply", "inout_classify",
             "inout_prepare", "inout_classify_prepared", "inout_release", "vms_stats",
             "vms_mesh_create", "vms_mesh_sizes", "vms_mesh_export", "vms_mesh_destroy",
-            "vms_set_timing", "vms_last_timing",
+            "vms_set_timing", "vms_last_timing", "vms_mlp_create", "vms_mlp_get_params",
+            "vms_mlp_set_margin", "vms_mlp_grad", "vms_mlp_train", "vms_mlp_adam_step",
+            "vms_mlp_predict", "vms_mlp_last_error", "vms_mlp_destroy", "vms_sdf_sample",
             "vms_last_error", "vms_destroy"]
 
 
@@ -85,6 +87,18 @@ def lib():
         L.vms_mesh_export.argtypes = [p, u32, p]
         L.vms_mesh_destroy.argtypes = [p]
         L.vms_mesh_destroy.restype = None
+        L.vms_mlp_create.argtypes = [C.POINTER(p), p, p, p, p, C.c_float, p]
+        L.vms_mlp_get_params.argtypes = [p, p]
+        L.vms_mlp_set_margin.argtypes = [p, C.c_float]
+        L.vms_mlp_grad.argtypes = [p, p, p, p, p, i64, p, p]
+        L.vms_mlp_train.argtypes = [p, p, p, p, p, i64, C.c_int, C.c_int, C.c_float, p]
+        L.vms_mlp_adam_step.argtypes = [p, p, C.c_float]
+        L.vms_mlp_predict.argtypes = [p, p, p, p, i64, p]
+        L.vms_mlp_last_error.argtypes = []
+        L.vms_mlp_last_error.restype = C.c_char_p
+        L.vms_mlp_destroy.argtypes = [p]
+        L.vms_mlp_destroy.restype = None
+        L.vms_sdf_sample.argtypes = [p, p, p, p, i64, C.c_double, p]
         L.vms_set_timing.argtypes = [p, C.c_int]
         L.vms_last_timing.argtypes = [p, p]
         L.vms_last_error.argtypes = [p]
@@ -94,7 +108,9 @@ def lib():
         for n in ("vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply",
                   "inout_classify", "inout_prepare", "inout_classify_prepared", "vms_stats",
                   "vms_mesh_create", "vms_mesh_sizes", "vms_mesh_export", "vms_set_timing",
-                  "vms_last_timing"):
+                  "vms_last_timing", "vms_mlp_create", "vms_mlp_get_params", "vms_mlp_set_margin",
+                  "vms_mlp_grad", "vms_mlp_train", "vms_mlp_adam_step", "vms_mlp_predict",
+                  "vms_sdf_sample"):
             getattr(L, n).restype = C.c_int
         _lib = L
     return _lib
@@ -282,6 +298,61 @@ def vms_last_timing(ctx):
     v = (C.c_float * 4)()
     _check(lib().vms_last_timing(ctx, v), ctx)
     return list(v)
+
+
+def _mcheck(rc):
+    if rc != VMS_OK:
+        raise VmsError(rc, lib().vms_mlp_last_error().decode())
+
+
+def vms_mlp_create(lo, hi, theta, B, trunc, stream=None):
+    lo = _np(lo, np.float64); hi = _np(hi, np.float64)
+    th = _np(theta, np.float32); Bm = _np(B, np.float32)
+    h = C.c_void_p()
+    _mcheck(lib().vms_mlp_create(C.byref(h), lo.ctypes.data, hi.ctypes.data, th.ctypes.data,
+                                 Bm.ctypes.data, float(trunc), _stream(stream)))
+    return h
+
+
+def vms_mlp_get_params(h):
+    out = np.zeros(12545, np.float32)
+    _mcheck(lib().vms_mlp_get_params(h, out.ctypes.data))
+    return out
+
+
+def vms_mlp_set_margin(h, m):
+    _mcheck(lib().vms_mlp_set_margin(h, float(m)))
+
+
+def vms_mlp_grad(h, px, py, pz, sdf, grad=None):
+    loss = C.c_double(0)
+    _mcheck(lib().vms_mlp_grad(h, _ptr(px), _ptr(py), _ptr(pz), _ptr(sdf), px.numel(), _ptr(grad),
+                               C.byref(loss)))
+    return loss.value
+
+
+def vms_mlp_train(h, px, py, pz, sdf, steps, batch, lr):
+    loss = C.c_double(0)
+    _mcheck(lib().vms_mlp_train(h, _ptr(px), _ptr(py), _ptr(pz), _ptr(sdf), px.numel(), int(steps),
+                                int(batch), float(lr), C.byref(loss)))
+    return loss.value
+
+
+def vms_mlp_adam_step(h, grad, lr):
+    _mcheck(lib().vms_mlp_adam_step(h, _ptr(grad), float(lr)))
+
+
+def vms_mlp_predict(h, px, py, pz, pred):
+    _mcheck(lib().vms_mlp_predict(h, _ptr(px), _ptr(py), _ptr(pz), px.numel(), _ptr(pred)))
+
+
+def vms_mlp_destroy(h):
+    lib().vms_mlp_destroy(h)
+
+
+def vms_sdf_sample(h, px, py, pz, trunc, sdf):
+    _check(lib().vms_sdf_sample(h, _ptr(px), _ptr(py), _ptr(pz), px.numel(), float(trunc), _ptr(sdf)),
+           None)
 
 
 def vms_last_error(ctx=None):
