@@ -241,6 +241,27 @@ void vms_mlp_destroy(vms_mlp *m);
 int vms_sdf_sample(inout_handle *h, const double *px, const double *py, const double *pz, int64_t n,
                    double trunc, double *sdf);
 
+/* Batched assembly of many contexts (independent octrees, one precision) in
+ * one persistent launch: workgroups take units of work (runs of `tile` OUT
+ * elements, or sub-cell work items) from a device counter until the queue is
+ * empty. fields/vals/resid are arrays with one entry per context (resid
+ * entries nullable), with the meaning of vms_assemble (labels are not
+ * recomputed). vms_batch_autotune times every (tile, workgroups per CU)
+ * candidate on the given buffers and keeps the fastest. With
+ * vms_batch_use_graph(b, 1) the launch sequence (zeroing kernels and the
+ * persistent assembly) is captured into a HIP graph at the first call and
+ * replayed while the buffer pointers stay the same. */
+typedef struct vms_batch vms_batch;
+int vms_batch_create(vms_batch **out, vms_ctx *const *ctxs, int n, void *stream);
+int vms_batch_set_config(vms_batch *b, int tile, int groups_per_cu);
+int vms_batch_get_config(vms_batch *b, int *tile, int *groups_per_cu, int64_t *n_units);
+int vms_batch_use_graph(vms_batch *b, int on);
+int vms_batch_assemble(vms_batch *b, const vms_fields *fields, void *const *vals,
+                       double *const *resid);
+int vms_batch_autotune(vms_batch *b, const vms_fields *fields, void *const *vals,
+                       double *const *resid, float *ms);
+void vms_batch_destroy(vms_batch *b);
+
 /* Counters of a context (HOST out[6]): OUT elements, INTERCEPTED elements,
  * points labelled by the last sub-cell quadrature, degenerate directions
  * abandoned, hanging vertices, kept sub-cell points. */

@@ -932,3 +932,275 @@ int vms_mesh_export(vms_mesh *h, uint32_t what, void *dst) {
 void vms_mesh_destroy(vms_mesh *h) { delete h; }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched assembly over many contexts: one persistent launch, device queue
+// ---------------------------------------------------------------------------
+
+struct vms_batch {
+    hipStream_t stream = nullptr;
+    std::vector<vms_ctx *> ctx;
+    int precision = 0;
+    int tile = 4, groups_per_cu = 8, n_cu = 256;
+    std::vector<vmsk::AsmArgs> h_std, h_sub;
+    vmsk::AsmArgs *d_std = nullptr, *d_sub = nullptr;
+    vmsk::BatchUnit *d_units = nullptr;
+    int64_t n_units = 0, units_cap = 0;
+    unsigned long long *d_counter = nullptr;
+    DevBuf buf;
+    // graph replay
+    bool use_graph = false, captured = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const void *> cap_ptrs;
+    std::string err = "no error";
+    ~vms_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+namespace {
+
+int bfail(vms_batch *b, int code, const std::string &m) {
+    if (b) b->err = m;
+    set_global_err(m);
+    return code;
+}
+
+vmsk::AsmArgs base_args(vms_ctx *c) {
+    vmsk::AsmArgs a{};
+    a.masters = c->d_masters;
+    a.ccode = c->d_ccode;
+    a.has_hang = c->d_hang;
+    a.level = c->d_level;
+    a.rowbase = c->d_rowbase;
+    a.rowlen = c->d_rowlen;
+    a.kk = c->d_kk;
+    a.depth = c->prm.quad_depth;
+    a.rho = c->prm.rho; a.mu = c->prm.mu; a.dt = c->prm.dt; a.theta = c->prm.theta;
+    a.c_t = c->prm.c_t; a.c_i = c->prm.c_i; a.root_len = c->root_len;
+    return a;
+}
+
+int batch_units(vms_batch *b) {
+    std::vector<vmsk::BatchUnit> u;
+    // sub-cell work first (heavier units), then runs of `tile` OUT elements
+    for (size_t t = 0; t < b->ctx.size(); ++t)
+        for (int64_t i = 0; i < b->ctx[t]->n_sub_items; ++i) u.push_back({(int32_t)t, 1, i, 1, 0});
+    for (size_t t = 0; t < b->ctx.size(); ++t)
+        for (int64_t i = 0; i < b->ctx[t]->n_std; i += b->tile)
+            u.push_back({(int32_t)t, 0, i, (int32_t)std::min<int64_t>(b->tile, b->ctx[t]->n_std - i), 0});
+    b->n_units = (int64_t)u.size();
+    if (b->n_units > b->units_cap) {
+        if (b->buf.alloc(&b->d_units, (size_t)b->n_units)) return bfail(b, VMS_ENOMEM, "device allocation failed");
+        b->units_cap = b->n_units;
+    }
+    if (hipMemcpyAsync(b->d_units, u.data(), u.size() * sizeof(vmsk::BatchUnit), hipMemcpyHostToDevice,
+                       b->stream) ||
+        hipStreamSynchronize(b->stream))
+        return bfail(b, VMS_EHIP, "device copy failed (units)");
+    return VMS_OK;
+}
+
+int batch_tables(vms_batch *b, const vms_fields *f, void *const *vals, double *const *resid) {
+    const size_t n = b->ctx.size();
+    for (size_t t = 0; t < n; ++t) {
+        vms_ctx *c = b->ctx[t];
+        const double *fp[7] = {f[t].ux, f[t].uy, f[t].uz, f[t].p, f[t].ux0, f[t].uy0, f[t].uz0};
+        for (const double *p : fp)
+            if (!p) return bfail(b, VMS_EINVAL, "null field pointer");
+        if (!vals[t]) return bfail(b, VMS_EINVAL, "null csr_vals");
+        vmsk::AsmArgs a = base_args(c);
+        for (int k = 0; k < 7; ++k) a.f[k] = fp[k];
+        a.vals = vals[t];
+        a.resid = resid ? resid[t] : nullptr;
+        a.n_items = c->n_std;
+        a.items = c->d_std;
+        b->h_std[t] = a;
+        a.n_items = c->n_sub_items;
+        a.items = c->d_sub_el;
+        a.pt_off = c->d_sub_off;
+        a.pt_cnt = c->d_sub_cnt;
+        a.entries = c->d_entries;
+        b->h_sub[t] = a;
+    }
+    if (hipMemcpyAsync(b->d_std, b->h_std.data(), n * sizeof(vmsk::AsmArgs), hipMemcpyHostToDevice, b->stream) ||
+        hipMemcpyAsync(b->d_sub, b->h_sub.data(), n * sizeof(vmsk::AsmArgs), hipMemcpyHostToDevice, b->stream) ||
+        hipStreamSynchronize(b->stream))
+        return bfail(b, VMS_EHIP, "device copy failed (tables)");
+    return VMS_OK;
+}
+
+// fills, identity rows and the persistent assembly (all kernels; no memset)
+void batch_enqueue(vms_batch *b) {
+    for (size_t t = 0; t < b->ctx.size(); ++t) {
+        vms_ctx *c = b->ctx[t];
+        const vmsk::AsmArgs &a = b->h_std[t];
+        if (b->precision == VMS_FP64) {
+            vmsk::launch_fill_f64(b->stream, (double *)a.vals, c->mesh.nnz, 0.0);
+            vmsk::launch_set_ones_f64(b->stream, (double *)a.vals, c->d_ones, c->n_ones);
+        } else {
+            vmsk::launch_fill_f32(b->stream, (float *)a.vals, c->mesh.nnz, 0.0f);
+            vmsk::launch_set_ones_f32(b->stream, (float *)a.vals, c->d_ones, c->n_ones);
+        }
+        if (a.resid) vmsk::launch_fill_f64(b->stream, a.resid, 4 * c->mesh.n_nodes, 0.0);
+    }
+    vmsk::launch_assemble_batch(b->stream, b->precision, b->d_std, b->d_sub, b->d_units, b->n_units,
+                                b->d_counter, b->n_cu * b->groups_per_cu);
+}
+
+}  // namespace
+
+extern "C" {
+
+int vms_batch_create(vms_batch **out, vms_ctx *const *ctxs, int n, void *stream) {
+    if (!out || !ctxs || n <= 0) return bfail(nullptr, VMS_EINVAL, "bad arguments");
+    *out = nullptr;
+    vms_batch *b = new vms_batch();
+    b->stream = (hipStream_t)stream;
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i]) { delete b; return bfail(nullptr, VMS_EINVAL, "null context"); }
+        b->ctx.push_back(ctxs[i]);
+    }
+    b->precision = (int)ctxs[0]->prm.precision;
+    for (vms_ctx *c : b->ctx)
+        if ((int)c->prm.precision != b->precision) {
+            delete b;
+            return bfail(nullptr, VMS_EINVAL, "contexts of a batch must share one precision");
+        }
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        b->n_cu = cus;
+    b->h_std.resize(n);
+    b->h_sub.resize(n);
+    if (b->buf.alloc(&b->d_std, (size_t)n) || b->buf.alloc(&b->d_sub, (size_t)n) ||
+        b->buf.alloc(&b->d_counter, 1)) {
+        delete b;
+        return bfail(nullptr, VMS_ENOMEM, "device allocation failed");
+    }
+    int rc = batch_units(b);
+    if (rc) { delete b; return rc; }
+    *out = b;
+    return VMS_OK;
+}
+
+int vms_batch_set_config(vms_batch *b, int tile, int groups_per_cu) {
+    if (!b || tile <= 0 || groups_per_cu <= 0) return bfail(b, VMS_EINVAL, "bad configuration");
+    b->groups_per_cu = groups_per_cu;
+    if (tile != b->tile) {
+        b->tile = tile;
+        if (b->captured) {  // the captured graph refers to the old unit list
+            (void)hipGraphExecDestroy(b->exec);
+            (void)hipGraphDestroy(b->graph);
+            b->exec = nullptr;
+            b->graph = nullptr;
+            b->captured = false;
+        }
+        return batch_units(b);
+    }
+    return VMS_OK;
+}
+
+int vms_batch_get_config(vms_batch *b, int *tile, int *groups_per_cu, int64_t *n_units) {
+    if (!b) return bfail(nullptr, VMS_EINVAL, "null batch");
+    if (tile) *tile = b->tile;
+    if (groups_per_cu) *groups_per_cu = b->groups_per_cu;
+    if (n_units) *n_units = b->n_units;
+    return VMS_OK;
+}
+
+int vms_batch_use_graph(vms_batch *b, int on) {
+    if (!b) return bfail(nullptr, VMS_EINVAL, "null batch");
+    b->use_graph = on != 0;
+    return VMS_OK;
+}
+
+int vms_batch_assemble(vms_batch *b, const vms_fields *f, void *const *vals, double *const *resid) {
+    if (!b || !f || !vals) return bfail(b, VMS_EINVAL, "null argument");
+    const size_t n = b->ctx.size();
+    std::vector<const void *> ptrs;
+    for (size_t t = 0; t < n; ++t) {
+        const double *fp[7] = {f[t].ux, f[t].uy, f[t].uz, f[t].p, f[t].ux0, f[t].uy0, f[t].uz0};
+        for (const double *p : fp) ptrs.push_back(p);
+        ptrs.push_back(vals[t]);
+        ptrs.push_back(resid ? resid[t] : nullptr);
+    }
+    if (b->use_graph && b->captured && ptrs == b->cap_ptrs) {
+        if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return bfail(b, VMS_EHIP, "graph launch failed");
+        return VMS_OK;
+    }
+    int rc = batch_tables(b, f, vals, resid);
+    if (rc) return rc;
+    if (!b->use_graph) {
+        batch_enqueue(b);
+        if (hipGetLastError() != hipSuccess) return bfail(b, VMS_EHIP, "launch failed");
+        return VMS_OK;
+    }
+    if (b->captured) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        b->captured = false;
+    }
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return bfail(b, VMS_EHIP, "stream capture failed to start");
+    batch_enqueue(b);
+    if (hipStreamEndCapture(b->stream, &b->graph) != hipSuccess ||
+        hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+        return bfail(b, VMS_EHIP, "graph capture failed");
+    b->captured = true;
+    b->cap_ptrs = ptrs;
+    if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return bfail(b, VMS_EHIP, "graph launch failed");
+    return VMS_OK;
+}
+
+// Time every (tile, groups per CU) candidate on the given buffers and keep the
+// fastest. ms (HOST, nullable) receives the best time of one assembly.
+int vms_batch_autotune(vms_batch *b, const vms_fields *f, void *const *vals, double *const *resid,
+                       float *ms_out) {
+    if (!b) return bfail(nullptr, VMS_EINVAL, "null batch");
+    const int tiles[] = {1, 2, 4, 8, 16};
+    const int gpcs[] = {4, 8, 16, 32};
+    const bool g = b->use_graph;
+    b->use_graph = false;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) || hipEventCreate(&e1)) return bfail(b, VMS_EHIP, "event creation failed");
+    float best = INFINITY;
+    int bt = b->tile, bg = b->groups_per_cu;
+    int rc = VMS_OK;
+    for (int tile : tiles) {
+        for (int gpc : gpcs) {
+            if ((rc = vms_batch_set_config(b, tile, gpc))) break;
+            if ((rc = vms_batch_assemble(b, f, vals, resid))) break;  // warm-up
+            float tmin = INFINITY;
+            for (int r = 0; r < 3; ++r) {
+                (void)hipEventRecord(e0, b->stream);
+                if ((rc = vms_batch_assemble(b, f, vals, resid))) break;
+                (void)hipEventRecord(e1, b->stream);
+                float t = 0;
+                if (hipEventSynchronize(e1) || hipEventElapsedTime(&t, e0, e1)) { rc = VMS_EHIP; break; }
+                tmin = std::min(tmin, t);
+            }
+            if (rc) break;
+            if (tmin < best) { best = tmin; bt = tile; bg = gpc; }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->use_graph = g;
+    if (rc) return rc;
+    if (ms_out) *ms_out = best;
+    return vms_batch_set_config(b, bt, bg);
+}
+
+void vms_batch_destroy(vms_batch *b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    delete b;
+}
+
+}  // extern "C"

@@ -176,18 +176,32 @@ __device__ inline void split2h(float x, _Float16 &h, _Float16 &l) {
 }
 
 // CP points per chunk (FP64: 4, mixed: 8 = one MFMA k-step of 32)
+template <typename T, int CP>
+struct Smem {
+    T sU[7][8];
+    T sC[8][8];
+    T sB[CP][4][8];
+    T sI[CP][7][4];
+    T sQ[CP][NQ2];
+    T sD[CP][4][4][4][4];  // [p][i][j][k][l], weight folded in
+    T sSc[CP];             // fp16 form: per-point power-of-two balance
+    int sM[8];
+};
+
+// One work item (an element, or a run of sub-cell points of one element) by
+// one 64-lane workgroup.
 template <typename T, int MODE, bool SUB, bool MAT, int CP>
-__global__ __launch_bounds__(64) void k_asm2(AsmArgs a) {
-    __shared__ T sU[7][8];
-    __shared__ T sC[8][8];
-    __shared__ T sB[CP][4][8];
-    __shared__ T sI[CP][7][4];
-    __shared__ T sQ[CP][NQ2];
-    __shared__ T sD[CP][4][4][4][4];  // [p][i][j][k][l], weight folded in
-    __shared__ T sSc[CP];             // fp16 form: per-point power-of-two balance
-    __shared__ int sM[8];
+__device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) {
+    auto &sU = sm.sU;
+    auto &sC = sm.sC;
+    auto &sB = sm.sB;
+    auto &sI = sm.sI;
+    auto &sQ = sm.sQ;
+    auto &sD = sm.sD;
+    auto &sSc = sm.sSc;
+    auto &sM = sm.sM;
     const int lane = threadIdx.x;
-    const int64_t item = blockIdx.x;
+    __syncthreads();  // the previous item of this workgroup is done with the LDS
     const int e = a.items[item];
     const bool hang = a.has_hang[e] != 0;
     const double hd = ldexp(a.root_len, -(int)a.level[e]);
@@ -514,6 +528,59 @@ __global__ __launch_bounds__(64) void k_asm2(AsmArgs a) {
         const int av = lane & 7, i = lane >> 3;
         if (sM[av] >= 0) atomicAdd(a.resid + 4 * (int64_t)sM[av] + i, (double)R);
     }
+}
+
+template <typename T, int MODE, bool SUB, bool MAT, int CP>
+__global__ __launch_bounds__(64) void k_asm2(AsmArgs a) {
+    __shared__ Smem<T, CP> sm;
+    asm_item<T, MODE, SUB, MAT, CP>(a, blockIdx.x, sm);
+}
+
+// Persistent form over many contexts: every workgroup takes units from a
+// device counter until none is left (each unit: a run of OUT elements or of
+// sub-cell work items of one tree).
+template <typename T, int MODE, int CP>
+__global__ __launch_bounds__(64) void k_asm_batch(const AsmArgs *std_args, const AsmArgs *sub_args,
+                                                  const BatchUnit *units, int64_t n_units,
+                                                  unsigned long long *counter) {
+    __shared__ Smem<T, CP> sm;
+    __shared__ int64_t su;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) su = (int64_t)atomicAdd(counter, 1ull);
+        __syncthreads();
+        const int64_t u = su;
+        if (u >= n_units) break;
+        const BatchUnit U = units[u];
+        if (U.sub) {
+            const AsmArgs a = sub_args[U.tree];
+            for (int k = 0; k < U.count; ++k) asm_item<T, MODE, true, true, CP>(a, U.first + k, sm);
+        } else {
+            const AsmArgs a = std_args[U.tree];
+            for (int k = 0; k < U.count; ++k) asm_item<T, MODE, false, true, CP>(a, U.first + k, sm);
+        }
+    }
+}
+
+__global__ void k_reset_counter(unsigned long long *c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0ull;
+}
+
+void launch_assemble_batch(hipStream_t s, int precision, const AsmArgs *std_args,
+                           const AsmArgs *sub_args, const BatchUnit *units, int64_t n_units,
+                           unsigned long long *counter, int n_groups) {
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
+    if (n_units <= 0) return;
+    dim3 grid((unsigned)n_groups), block(64);
+    if (precision == 0)
+        hipLaunchKernelGGL((k_asm_batch<double, 0, VMS_CP64>), grid, block, 0, s, std_args, sub_args,
+                           units, n_units, counter);
+    else if (precision == 1)
+        hipLaunchKernelGGL((k_asm_batch<float, 1, 8>), grid, block, 0, s, std_args, sub_args, units,
+                           n_units, counter);
+    else
+        hipLaunchKernelGGL((k_asm_batch<float, 2, 8>), grid, block, 0, s, std_args, sub_args, units,
+                           n_units, counter);
 }
 
 void launch_assemble_f64(hipStream_t s, const AsmArgs &a, bool sub, bool mat) {

@@ -89,6 +89,19 @@ struct AsmArgs {
     double *resid;
 };
 void launch_assemble_f64(hipStream_t s, const AsmArgs &a, bool sub, bool mat);
+
+// one unit of the persistent batched assembly: items [first, first + count) of
+// tree `tree`'s OUT-element list (sub = 0) or sub-cell work-item list (sub = 1)
+struct BatchUnit {
+    int32_t tree;
+    int32_t sub;
+    int64_t first;
+    int32_t count;
+    int32_t pad;
+};
+void launch_assemble_batch(hipStream_t s, int precision, const AsmArgs *std_args,
+                           const AsmArgs *sub_args, const BatchUnit *units, int64_t n_units,
+                           unsigned long long *counter, int n_groups);
 void launch_assemble_mixed(hipStream_t s, const AsmArgs &a, bool sub, bool mat, int fp16);
 
 void launch_fill_f64(hipStream_t s, double *p, int64_t n, double v);

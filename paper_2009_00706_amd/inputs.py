@@ -137,7 +137,7 @@ def balance_21(ax, ay, az, lev, M, ext):
 
 
 def refined_octree(M: int, lmin: int, refine, ext=None, origin=(0.0, 0.0, 0.0),
-                   root_len: float = 1.0, meta=None) -> Octree:
+                   root_len: float = 1.0, meta=None, balance: bool = True) -> Octree:
     """Top-down construction: start uniform at lmin, split while refine() says so.
 
     refine(cx, cy, cz, h, level) -> bool mask, with octant centres and side in
@@ -166,7 +166,8 @@ def refined_octree(M: int, lmin: int, refine, ext=None, origin=(0.0, 0.0, 0.0),
         ax, ay, az, lev = _children(ax[m], ay[m], az[m], lev[m], M)
     ax, ay, az, lev = (np.concatenate(l) for l in done)
     n_pre = int(ax.shape[0])
-    ax, ay, az, lev = balance_21(ax, ay, az, lev, M, ext)
+    if balance:
+        ax, ay, az, lev = balance_21(ax, ay, az, lev, M, ext)
     ax, ay, az, lev, _ = _sort_leaves(ax, ay, az, lev)
     md = {"kind": "refined", "n_before_balance": n_pre}
     if meta:
@@ -465,3 +466,58 @@ def sdf_sample_points(surf: Surface, lo, hi, n: int, seed: int, near_frac: float
     out = np.concatenate([pts, uni])
     out = np.clip(out, lo, hi)
     return out[rng.permutation(n)]
+
+
+def ellipsoid_refined_octree(center, semi, rot, lmin, lmax, beta, balance=True) -> Octree:
+    """Refine octants whose centre lies within about beta*h of the ellipsoid
+    surface (distance estimated as |r - 1| * min(semi), r the normalised radius)."""
+    c = np.asarray(center, np.float64)
+    a = np.asarray(semi, np.float64)
+    R = np.asarray(rot, np.float64)
+
+    def refine(cx, cy, cz, h, lev):
+        y = (np.stack([cx, cy, cz], 1) - c) @ R      # body frame
+        r = np.sqrt(((y / a) ** 2).sum(1))
+        return (np.abs(r - 1.0) * a.min() < beta * h) & (lev < lmax)
+
+    return refined_octree(lmax, lmin, refine, balance=balance,
+                          meta={"body": "ellipsoid", "beta": beta, "lmin": lmin, "lmax": lmax})
+
+
+def batch_workload(n_trees: int, seed: int, size_lo=1e4, size_hi=5e5, lmin=4, lmax=9,
+                   tri_lo=2000, tri_hi=20000):
+    """Independent octrees of log-uniform target sizes, each refined around its own
+    ellipsoid (semi-axes U(0.05, 0.2), random rotation, centre U(0.25, 0.75)^3,
+    lat-long tessellation with U(tri_lo, tri_hi) triangles). The refinement width
+    beta is bisected per tree so the leaf count before balancing is within 10%
+    of the target."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_trees):
+        target = float(np.exp(rng.uniform(np.log(size_lo), np.log(size_hi))))
+        semi = rng.uniform(0.05, 0.2, 3)
+        R = random_rotation(rng)
+        c = rng.uniform(0.25, 0.75, 3)
+        ntri = int(rng.integers(tri_lo, tri_hi + 1))
+        n_lat = max(3, int(round(np.sqrt(ntri / 4.0))))
+        surf = ellipsoid(semi, c, R, n_lat, 2 * n_lat)
+        goal = target
+        for attempt in range(2):   # second pass corrects for the growth from balancing
+            lo_b, hi_b = 0.01, 64.0
+            beta = 1.0
+            for _ in range(24):
+                beta = np.sqrt(lo_b * hi_b)
+                n = ellipsoid_refined_octree(c, semi, R, lmin, lmax, beta, balance=False).n
+                if abs(n - goal) <= 0.1 * goal:
+                    break
+                if n < goal:
+                    lo_b = beta
+                else:
+                    hi_b = beta
+            tree = ellipsoid_refined_octree(c, semi, R, lmin, lmax, beta)
+            if tree.n <= 1.1 * target:
+                break
+            goal = goal * target / tree.n
+        tree.meta["target"] = target
+        out.append((tree, surf))
+    return out

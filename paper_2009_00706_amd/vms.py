@@ -29,6 +29,8 @@ EXPORTED = ["vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply"
             "vms_set_timing", "vms_last_timing", "vms_mlp_create", "vms_mlp_get_params",
             "vms_mlp_set_margin", "vms_mlp_grad", "vms_mlp_train", "vms_mlp_adam_step",
             "vms_mlp_predict", "vms_mlp_last_error", "vms_mlp_destroy", "vms_sdf_sample",
+            "vms_batch_create", "vms_batch_set_config", "vms_batch_get_config",
+            "vms_batch_use_graph", "vms_batch_assemble", "vms_batch_autotune", "vms_batch_destroy",
             "vms_last_error", "vms_destroy"]
 
 
@@ -99,6 +101,14 @@ def lib():
         L.vms_mlp_destroy.argtypes = [p]
         L.vms_mlp_destroy.restype = None
         L.vms_sdf_sample.argtypes = [p, p, p, p, i64, C.c_double, p]
+        L.vms_batch_create.argtypes = [C.POINTER(p), p, C.c_int, p]
+        L.vms_batch_set_config.argtypes = [p, C.c_int, C.c_int]
+        L.vms_batch_get_config.argtypes = [p, p, p, p]
+        L.vms_batch_use_graph.argtypes = [p, C.c_int]
+        L.vms_batch_assemble.argtypes = [p, p, p, p]
+        L.vms_batch_autotune.argtypes = [p, p, p, p, p]
+        L.vms_batch_destroy.argtypes = [p]
+        L.vms_batch_destroy.restype = None
         L.vms_set_timing.argtypes = [p, C.c_int]
         L.vms_last_timing.argtypes = [p, p]
         L.vms_last_error.argtypes = [p]
@@ -110,7 +120,9 @@ def lib():
                   "vms_mesh_create", "vms_mesh_sizes", "vms_mesh_export", "vms_set_timing",
                   "vms_last_timing", "vms_mlp_create", "vms_mlp_get_params", "vms_mlp_set_margin",
                   "vms_mlp_grad", "vms_mlp_train", "vms_mlp_adam_step", "vms_mlp_predict",
-                  "vms_sdf_sample"):
+                  "vms_sdf_sample", "vms_batch_create", "vms_batch_set_config",
+                  "vms_batch_get_config", "vms_batch_use_graph", "vms_batch_assemble",
+                  "vms_batch_autotune"):
             getattr(L, n).restype = C.c_int
         _lib = L
     return _lib
@@ -353,6 +365,52 @@ def vms_mlp_destroy(h):
 def vms_sdf_sample(h, px, py, pz, trunc, sdf):
     _check(lib().vms_sdf_sample(h, _ptr(px), _ptr(py), _ptr(pz), px.numel(), float(trunc), _ptr(sdf)),
            None)
+
+
+def vms_batch_create(ctxs, stream=None):
+    arr = (C.c_void_p * len(ctxs))(*[c.value for c in ctxs])
+    h = C.c_void_p()
+    _check(lib().vms_batch_create(C.byref(h), arr, len(ctxs), _stream(stream)), None)
+    h._keep = arr
+    return h
+
+
+def vms_batch_set_config(b, tile, groups_per_cu):
+    _check(lib().vms_batch_set_config(b, int(tile), int(groups_per_cu)), None)
+
+
+def vms_batch_get_config(b):
+    t, g, n = C.c_int(), C.c_int(), C.c_int64()
+    _check(lib().vms_batch_get_config(b, C.byref(t), C.byref(g), C.byref(n)), None)
+    return {"tile": t.value, "groups_per_cu": g.value, "n_units": n.value}
+
+
+def vms_batch_use_graph(b, on=True):
+    _check(lib().vms_batch_use_graph(b, 1 if on else 0), None)
+
+
+def _batch_arrays(fields, vals, resid):
+    fa = (Fields * len(fields))(*[_fields(f) for f in fields])
+    va = (C.c_void_p * len(vals))(*[v.data_ptr() for v in vals])
+    ra = (C.c_void_p * len(vals))(*[(r.data_ptr() if r is not None else None) for r in resid]) \
+        if resid is not None else None
+    return fa, va, ra
+
+
+def vms_batch_assemble(b, fields, vals, resid=None):
+    fa, va, ra = _batch_arrays(fields, vals, resid)
+    _check(lib().vms_batch_assemble(b, fa, va, ra), None)
+
+
+def vms_batch_autotune(b, fields, vals, resid=None):
+    fa, va, ra = _batch_arrays(fields, vals, resid)
+    ms = C.c_float(0)
+    _check(lib().vms_batch_autotune(b, fa, va, ra, C.byref(ms)), None)
+    return ms.value
+
+
+def vms_batch_destroy(b):
+    lib().vms_batch_destroy(b)
 
 
 def vms_last_error(ctx=None):

@@ -517,3 +517,56 @@ def test_adaptive_quadrature_sphere_converges_to_polyhedron_volume(oracle):
     assert errs[0] > 5 * errs[1] > 25 * errs[2]
     assert errs[-1] < 5e-4 * vpoly
     assert abs(vpoly - 4 / 3 * np.pi * 0.3 ** 3) > 10 * errs[-1]
+
+
+# ---------------------------------------------------------------------------
+# Unsigned distance to a triangulated surface (training targets of the
+# learned in-out filter)
+# ---------------------------------------------------------------------------
+
+
+def _brute_distance(verts, tris, x, n=200):
+    """min over a dense barycentric grid of every triangle (an upper bound that
+    is within the grid spacing of the true distance)."""
+    u, v = np.meshgrid(np.linspace(0, 1, n + 1), np.linspace(0, 1, n + 1))
+    m = (u + v) <= 1.0
+    u, v = u[m], v[m]
+    best = np.full(x.shape[0], np.inf)
+    for t in tris:
+        a, b, c = verts[t[0]], verts[t[1]], verts[t[2]]
+        P = a[None] + u[:, None] * (b - a)[None] + v[:, None] * (c - a)[None]
+        d = np.sqrt(((x[:, None, :] - P[None]) ** 2).sum(-1)).min(1)
+        best = np.minimum(best, d)
+    return best
+
+
+def test_unsigned_distance_closed_forms_and_brute_force(oracle):
+    class S:
+        pass
+    s = S()
+    s.verts = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 1.0, 0.0]])
+    s.tris = np.array([[0, 1, 2]], np.int32)
+    x = np.array([
+        [0.2, 0.2, 0.7],     # face region: distance = height
+        [-0.3, -0.4, 0.0],   # vertex region of a: |x - a|
+        [0.5, -0.2, 0.1],    # edge region of ab: distance to the line
+        [1.0, 1.0, 0.0],     # edge region of bc (in plane)
+        [2.0, -1.0, 0.5],    # vertex region of b
+    ])
+    ref = np.array([0.7, 0.5, np.hypot(0.2, 0.1), np.sqrt(0.5), np.sqrt(1 + 1 + 0.25)])
+    np.testing.assert_allclose(oracle.unsigned_distance(s, x), ref, rtol=1e-14, atol=1e-15)
+    # a closed polyhedron: brute force within the grid spacing, never above it
+    c = np.array([0.5, 0.5, 0.5])
+    ico = I.icosphere(1, 0.3, c)
+    rng = np.random.default_rng(4)
+    q = rng.uniform(0.0, 1.0, (60, 3))
+    d = oracle.unsigned_distance(ico, q)
+    bf = _brute_distance(ico.verts, ico.tris, q)
+    edge = max(np.linalg.norm(ico.verts[t[0]] - ico.verts[t[1]]) for t in ico.tris)
+    assert np.all(d <= bf + 1e-12)
+    assert np.all(bf - d <= edge / 200 * 1.5)
+    # the icosphere's centre is at the inradius from every face
+    nrm = [np.cross(ico.verts[t[1]] - ico.verts[t[0]], ico.verts[t[2]] - ico.verts[t[0]])
+           for t in ico.tris]
+    inr = min(abs(np.dot(n / np.linalg.norm(n), ico.verts[t[0]] - c)) for n, t in zip(nrm, ico.tris))
+    assert abs(oracle.unsigned_distance(ico, c[None])[0] - inr) <= 1e-15
