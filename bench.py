@@ -1,14 +1,21 @@
 """Benchmark of the VMS assembly + in-out hot path on one MI355X.
 
-One step = vms_assemble with relabelling: adaptive sub-cell quadrature of every
-INTERCEPTED element with an exact in-out test of each candidate point, then
-the residual and Jacobian of every non-IN element scattered into the CSR
-(zeroing and identity rows included). Inputs are resident in HBM before the
-timed region. Prints one JSON line.
+One step (default workload) = vms_assemble with relabelling: adaptive sub-cell
+quadrature of every INTERCEPTED element with an exact in-out test of each
+candidate point, then the residual and Jacobian of every non-IN element
+scattered into the CSR (zeroing and identity rows included). Inputs are
+resident in HBM before the timed region. Prints one JSON line.
 
-Workload (default): immersed sphere r = 0.1 (icosphere, 5120 triangles) at the
-unit cube's centre, octree levels 5-8 refined at the surface (194,328 octants,
-hanging nodes), sub-cell quadrature depth 3, FP64.
+Workloads:
+  sphere    immersed sphere r = 0.1 (icosphere, 5120 triangles) at the unit
+            cube's centre, octree levels 5-8 refined at the surface (194,328
+            octants, hanging nodes), sub-cell quadrature depth 3. FP64 headline,
+            with the BF16 and FP16 forms timed on the same inputs.
+  uniform16 16^3 uniform octants, no body.
+  batch64   64 independent octrees (log-uniform 1e4..5e5 octants, one ellipsoid
+            body each) assembled by one persistent launch, autotuned, replayed
+            as a captured graph; BF16 form by default. Labels are computed at
+            context creation; a step is the assembly.
 """
 from __future__ import annotations
 
@@ -23,12 +30,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# algorithmic work per quadrature point: the dense B^T D B
-# contraction, (16x4x32 + 32x4x32) multiply-adds x 2 = 12,288 flop; an OUT
-# element has 8 points, an INTERCEPTED element its kept sub-cell points
+# algorithmic work per quadrature point: the dense B^T D B contraction,
+# (16x4x32 + 32x4x32) multiply-adds x 2 = 12,288 flop; an OUT element has 8
+# points, an INTERCEPTED element its kept sub-cell points
 FLOP_PER_POINT = 12288
-PEAK_FP64_TFLOPS = 78.6
-PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6     # FP64 vector and FP64 MFMA
+PEAK_FP32_TFLOPS = 157.3    # FP32 vector (the mixed forms' per-point and stage-1 work)
 
 
 def parse():
@@ -36,8 +43,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="sphere", choices=["sphere", "uniform16"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "bf16", "fp16"])
+    ap.add_argument("--workload", default="sphere", choices=["sphere", "uniform16", "batch64"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "bf16", "fp16"])
+    ap.add_argument("--n-trees", type=int, default=64)
+    ap.add_argument("--no-forms", action="store_true", help="skip the BF16/FP16 comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1500, help="elements in the oracle sample")
     ap.add_argument("--copy-calib", type=int, default=0,
@@ -70,6 +79,31 @@ def workload(name):
         "octants": tree.n}
 
 
+def node_xyz(vms, ctx, tree):
+    return vms.vms_export(ctx, vms.VMS_EXPORT_NODE_XYZ).T.astype(np.float64) / \
+        float(1 << tree.max_level) * tree.root_len + np.asarray(tree.origin)
+
+
+def traffic_for(path, workload, precision):
+    """HBM bytes per launch of the dominant kernel from the recorded counter runs
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration); None when no
+    record exists or the kernel source changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(path):
+        return None
+    try:
+        tr = json.load(open(path))
+        src = open(os.path.join(ROOT, "paper_2009_00706_amd", "csrc", "assemble2.hip"), "rb").read()
+    except (OSError, ValueError):
+        return None
+    sha = hashlib.sha256(src).hexdigest()[:16]
+    for e in tr.get("entries", []):
+        if e.get("workload") == workload and e.get("precision") == precision and \
+                e.get("kernel_source_sha256_16") == sha:
+            return e.get("bytes_per_launch")
+    return None
+
+
 def cpu_baseline(tree, surf, fields, n_sample):
     """The CPU reference as it stands, single-threaded, on a bounded sample."""
     from oracle import core as O
@@ -95,98 +129,214 @@ def cpu_baseline(tree, surf, fields, n_sample):
                       f"of the INTERCEPTED ones included, {dt:.1f} s"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
-    if args.copy_calib:
-        copy_calibration(args.copy_calib)
-        return
-    import torch
-    from paper_2009_00706_amd import inputs as I
-    from paper_2009_00706_amd import vms
-
-    prec = {"fp64": vms.VMS_FP64, "bf16": vms.VMS_MIXED_BF16, "fp16": vms.VMS_MIXED_FP16}[args.precision]
-    tree, surf, cfg = workload(args.workload)
+def run_single(torch, vms, tree, surf, f, prec, steps, warmup, flags):
+    """Time `steps` whole steps of one context; returns numbers and the outputs."""
     t_setup = time.perf_counter()
     asm = vms.Assembler(tree, surf, vms.make_params(quad_depth=3, precision=prec))
     setup_s = time.perf_counter() - t_setup
-    xyz = asm.export(vms.VMS_EXPORT_NODE_XYZ).T / float(1 << tree.max_level)
-    f = I.make_fields(xyz, 1001)
     asm.set_fields(f)
     st = vms.vms_stats(asm.ctx)
     n_active = st["n_out"] + st["n_intercepted"]
-    flags = vms.VMS_RELABEL if surf is not None else 0
     vms.vms_set_timing(asm.ctx, True)
-    stream = asm.stream
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         asm.assemble(flags=flags)
     torch.cuda.synchronize()
-    # ---- timed region: K whole steps, per-stage HIP events on the context stream
-    stage = np.zeros((args.steps, 4))
-    torch.cuda.synchronize()
+    stage = np.zeros((steps, 4))
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         asm.assemble(flags=flags)
         stage[k] = vms.vms_last_timing(asm.ctx)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    ms_step = 1e3 * elapsed / args.steps
-    value = n_active * args.steps / elapsed
-    # ---- steady state (labels cached), for context
+    # steady state (labels cached), for context
     t1 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         asm.assemble(flags=0)
     torch.cuda.synchronize()
-    steady = n_active * args.steps / (time.perf_counter() - t1)
-    sizes = asm.sizes
-    avg = stage.mean(0)
+    steady = n_active * steps / (time.perf_counter() - t1)
+    asm.assemble(flags=flags)
+    torch.cuda.synchronize()
+    out = {"elapsed": elapsed, "value": n_active * steps / elapsed, "ms_step": 1e3 * elapsed / steps,
+           "stage": stage.mean(0), "steady": steady, "setup_s": setup_s, "stats": st,
+           "sizes": asm.sizes, "n_active": n_active,
+           "vals": asm.vals.double().cpu().numpy(), "resid": asm.resid.cpu().numpy()}
+    asm.close()
+    return out
+
+
+def roofline(k_ms, n_pts, peak, traffic, kname):
+    achieved = FLOP_PER_POINT * n_pts / (k_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": traffic, "kernel": kname, "kernel_ms": k_ms,
+            "points_per_launch": int(n_pts), "flop_per_point": FLOP_PER_POINT}
+
+
+def main_single(args):
+    import torch
+    from paper_2009_00706_amd import inputs as I
+    from paper_2009_00706_amd import vms
+
+    pname = args.precision or "fp64"
+    prec = {"fp64": vms.VMS_FP64, "bf16": vms.VMS_MIXED_BF16, "fp16": vms.VMS_MIXED_FP16}[pname]
+    tree, surf, cfg = workload(args.workload)
+    mh = vms.vms_mesh_create(tree)
+    xyz = vms.vms_mesh_export(mh, vms.VMS_EXPORT_NODE_XYZ).T.astype(np.float64)
+    vms.vms_mesh_destroy(mh)
+    f = I.make_fields(xyz / float(1 << tree.max_level) * tree.root_len + np.asarray(tree.origin),
+                      1001)
+    flags = vms.VMS_RELABEL if surf is not None else 0
+    r = run_single(torch, vms, tree, surf, f, prec, args.steps, args.warmup, flags)
+    st, avg = r["stats"], r["stage"]
     # dominant kernel: the assembly kernel with the larger time
     if avg[3] > avg[2]:
-        k_ms, n_pts, kname = avg[3], st["n_subgp"], "k_asm_f64 (INTERCEPTED elements, sub-cell points)"
+        k_ms, n_pts, kname = avg[3], st["n_subgp"], "k_asm2 (INTERCEPTED elements, sub-cell points)"
     else:
-        k_ms, n_pts, kname = avg[2], 8 * st["n_out"], "k_asm_f64 (OUT elements)"
-    achieved = FLOP_PER_POINT * n_pts / (k_ms * 1e-3) / 1e12
-    traffic = None
-    if os.path.exists(args.traffic):
-        try:
-            tr = json.load(open(args.traffic))
-            if tr.get("workload") == args.workload and tr.get("precision") == args.precision:
-                traffic = tr.get("bytes_per_launch")
-        except Exception:
-            traffic = None
+        k_ms, n_pts, kname = avg[2], 8 * st["n_out"], "k_asm2 (OUT elements)"
+    peak = PEAK_FP64_TFLOPS if prec == vms.VMS_FP64 else PEAK_FP32_TFLOPS
     out = {
         "metric": "VMS elements assembled/s + in-out tests/s; learned+mixed vs FP64 at err<=1e-5",
-        "value": value,
+        "value": r["value"],
         "unit": "elements/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": r["ms_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if prec == vms.VMS_FP64 else ("f32+bf16" if prec == 1 else "f32+f16"),
         "data": "synthetic",
-        "config": dict(cfg, n_nodes=sizes["n_nodes"], nnz=sizes["nnz"], n_out=st["n_out"],
-                       n_intercepted=st["n_intercepted"], n_subgp=st["n_subgp"],
-                       precision=args.precision),
+        "config": dict(cfg, n_nodes=r["sizes"]["n_nodes"], nnz=r["sizes"]["nnz"],
+                       n_out=st["n_out"], n_intercepted=st["n_intercepted"],
+                       n_subgp=st["n_subgp"], precision=pname),
         "inout_tests_per_s": (st["n_labelled"] / (avg[0] * 1e-3)) if avg[0] > 0 else None,
-        "steady_state_elements_per_s": steady,
+        "steady_state_elements_per_s": r["steady"],
         "stage_ms": {"relabel": avg[0], "zero": avg[1], "out_elements": avg[2],
                      "intercepted_elements": avg[3]},
-        "setup_s": setup_s,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "kernel": kname, "kernel_ms": k_ms, "points_per_launch": n_pts,
-                     "flop_per_point": FLOP_PER_POINT},
+        "setup_s": r["setup_s"],
+        "roofline": roofline(k_ms, n_pts, peak, traffic_for(args.traffic, args.workload, pname),
+                             kname),
     }
+    if prec == vms.VMS_FP64 and not args.no_forms:
+        forms = {}
+        for name, p in (("bf16", vms.VMS_MIXED_BF16), ("fp16", vms.VMS_MIXED_FP16)):
+            m = run_single(torch, vms, tree, surf, f, p, args.steps, args.warmup, flags)
+            ej = np.linalg.norm(m["vals"] - r["vals"]) / np.linalg.norm(r["vals"])
+            er = np.linalg.norm(m["resid"] - r["resid"]) / np.linalg.norm(r["resid"])
+            forms[name] = {"value": m["value"], "ms_per_step": m["ms_step"],
+                           "speedup_vs_fp64": m["value"] / r["value"],
+                           "rel_err_jacobian": ej, "rel_err_residual": er,
+                           "stage_ms": {"relabel": m["stage"][0], "zero": m["stage"][1],
+                                        "out_elements": m["stage"][2],
+                                        "intercepted_elements": m["stage"][3]}}
+        out["forms"] = forms
+        out["forms_note"] = ("mixed forms on the same inputs and step; errors are normwise against "
+                             "this FP64 GPU result (itself within 1e-12 of the CPU reference)")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(tree, surf, f, args.cpu_sample)
-    asm.close()
     print(json.dumps(out))
+
+
+def main_batch(args):
+    from paper_2009_00706_amd import inputs as I
+    pname = args.precision or "bf16"
+    t0 = time.perf_counter()
+    work = I.batch_workload(args.n_trees, 3, workers=min(16, os.cpu_count() or 1))
+    gen_s = time.perf_counter() - t0
+    import torch
+    from paper_2009_00706_amd import vms
+    prec = {"fp64": vms.VMS_FP64, "bf16": vms.VMS_MIXED_BF16, "fp16": vms.VMS_MIXED_FP16}[pname]
+    stream = torch.cuda.Stream()
+    ctxs, fields, vals, resid = [], [], [], []
+    n_active = n_pts = n_oct = n_sub = 0
+    t1 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for k, (tree, surf) in enumerate(work):
+            ctx = vms.vms_create(tree, surf, vms.make_params(quad_depth=3, precision=prec),
+                                 stream.cuda_stream)
+            sz = vms.vms_sizes(ctx)
+            st = vms.vms_stats(ctx)
+            f = I.make_fields(node_xyz(vms, ctx, tree), 3000 + k)
+            fields.append({n: torch.as_tensor(f[n], device="cuda") for n in f})
+            dt = torch.float64 if prec == vms.VMS_FP64 else torch.float32
+            vals.append(torch.zeros(sz["nnz"], dtype=dt, device="cuda"))
+            resid.append(torch.zeros(sz["n_rows"], dtype=torch.float64, device="cuda"))
+            ctxs.append(ctx)
+            n_active += st["n_out"] + st["n_intercepted"]
+            n_pts += 8 * st["n_out"] + st["n_subgp"]
+            n_sub += st["n_subgp"]
+            n_oct += tree.n
+        setup_s = time.perf_counter() - t1
+        b = vms.vms_batch_create(ctxs, stream.cuda_stream)
+        tune_ms = vms.vms_batch_autotune(b, fields, vals, resid)
+        cfgb = vms.vms_batch_get_config(b)
+        # kernel time of the persistent launch (eager), for the roofline
+        kms = []
+        for _ in range(3):
+            vms.vms_batch_assemble(b, fields, vals, resid)
+            kms.append(vms.vms_batch_last_timing(b))
+        kms = np.array(kms).mean(0)
+        vms.vms_batch_use_graph(b, True)
+        for _ in range(args.warmup):
+            vms.vms_batch_assemble(b, fields, vals, resid)
+        stream.synchronize()
+        ts = time.perf_counter()
+        for _ in range(args.steps):
+            vms.vms_batch_assemble(b, fields, vals, resid)
+        stream.synchronize()
+        elapsed = time.perf_counter() - ts
+        vms.vms_batch_destroy(b)
+    sizes = sorted(t.n for t, _ in work)
+    out = {
+        "metric": "VMS elements assembled/s + in-out tests/s; learned+mixed vs FP64 at err<=1e-5",
+        "value": n_active * args.steps / elapsed,
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == vms.VMS_FP64 else ("f32+bf16" if prec == 1 else "f32+f16"),
+        "data": "synthetic",
+        "config": {"workload": f"{args.n_trees} independent octrees, log-uniform 1e4..5e5 octants "
+                               "(seed 3), one ellipsoid body each (2k-20k triangles), one persistent "
+                               "launch replayed as a graph, sub-cell quadrature depth 3",
+                   "octants": n_oct, "active_elements": n_active, "quadrature_points": n_pts,
+                   "n_subgp": n_sub, "tree_sizes_min_median_max": [sizes[0], sizes[len(sizes) // 2],
+                                                                   sizes[-1]],
+                   "precision": pname, "autotuned": cfgb, "autotune_best_ms": tune_ms},
+        "stage_ms": {"zero": float(kms[0]), "persistent_assembly": float(kms[1])},
+        "setup_s": {"generate": gen_s, "contexts": setup_s},
+        "roofline": roofline(float(kms[1]), n_pts,
+                             PEAK_FP64_TFLOPS if prec == vms.VMS_FP64 else PEAK_FP32_TFLOPS,
+                             traffic_for(args.traffic, "batch64", pname),
+                             "k_asm_batch (persistent, all trees)"),
+    }
+    if not args.no_cpu_baseline:
+        tree, surf = work[0]
+        f = {k: v.cpu().numpy() for k, v in fields[0].items()}
+        out["cpu_baseline"] = cpu_baseline(tree, surf, f, args.cpu_sample)
+        out["cpu_baseline"]["sample"] += " (first tree of the batch)"
+    for c in ctxs:
+        vms.vms_destroy(c)
+    print(json.dumps(out))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this implementation runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.copy_calib:
+        copy_calibration(args.copy_calib)
+        return
+    if args.workload == "batch64":
+        main_batch(args)
+    else:
+        main_single(args)
 
 
 if __name__ == "__main__":

@@ -250,7 +250,13 @@ int vms_sdf_sample(inout_handle *h, const double *px, const double *py, const do
  * candidate on the given buffers and keeps the fastest. With
  * vms_batch_use_graph(b, 1) the launch sequence (zeroing kernels and the
  * persistent assembly) is captured into a HIP graph at the first call and
- * replayed while the buffer pointers stay the same. */
+ * replayed while the buffer pointers stay the same. The queue puts the sub-cell
+ * work first: INTERCEPTED elements carry more quadrature points and in-out
+ * work, the load imbalance that the paper's weighted partition (eq. Wpart,
+ * section on dynamic load balancing) addresses across processes.
+ * vms_batch_last_timing writes HOST ms[2] (zeroing kernels, persistent
+ * assembly kernel) of the last eager (not graph-replayed) vms_batch_assemble,
+ * synchronising on it; VMS_EINVAL if there was none. */
 typedef struct vms_batch vms_batch;
 int vms_batch_create(vms_batch **out, vms_ctx *const *ctxs, int n, void *stream);
 int vms_batch_set_config(vms_batch *b, int tile, int groups_per_cu);
@@ -260,6 +266,7 @@ int vms_batch_assemble(vms_batch *b, const vms_fields *fields, void *const *vals
                        double *const *resid);
 int vms_batch_autotune(vms_batch *b, const vms_fields *fields, void *const *vals,
                        double *const *resid, float *ms);
+int vms_batch_last_timing(vms_batch *b, float *ms);
 void vms_batch_destroy(vms_batch *b);
 
 /* Counters of a context (HOST out[6]): OUT elements, INTERCEPTED elements,

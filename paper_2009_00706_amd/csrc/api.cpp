@@ -953,10 +953,15 @@ struct vms_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<const void *> cap_ptrs;
+    // timing of the last eager launch sequence
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    bool timed = false;
     std::string err = "no error";
     ~vms_batch() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
     }
 };
 
@@ -1032,8 +1037,10 @@ int batch_tables(vms_batch *b, const vms_fields *f, void *const *vals, double *c
     return VMS_OK;
 }
 
-// fills, identity rows and the persistent assembly (all kernels; no memset)
-void batch_enqueue(vms_batch *b) {
+// fills, identity rows and the persistent assembly (all kernels; no memset).
+// With timed set, events bracket the fills and the persistent kernel.
+void batch_enqueue(vms_batch *b, bool timed) {
+    if (timed) (void)hipEventRecord(b->ev[0], b->stream);
     for (size_t t = 0; t < b->ctx.size(); ++t) {
         vms_ctx *c = b->ctx[t];
         const vmsk::AsmArgs &a = b->h_std[t];
@@ -1046,8 +1053,11 @@ void batch_enqueue(vms_batch *b) {
         }
         if (a.resid) vmsk::launch_fill_f64(b->stream, a.resid, 4 * c->mesh.n_nodes, 0.0);
     }
+    if (timed) (void)hipEventRecord(b->ev[1], b->stream);
     vmsk::launch_assemble_batch(b->stream, b->precision, b->d_std, b->d_sub, b->d_units, b->n_units,
                                 b->d_counter, b->n_cu * b->groups_per_cu);
+    if (timed) (void)hipEventRecord(b->ev[2], b->stream);
+    b->timed = timed;
 }
 
 }  // namespace
@@ -1073,6 +1083,11 @@ int vms_batch_create(vms_batch **out, vms_ctx *const *ctxs, int n, void *stream)
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
         b->n_cu = cus;
+    for (hipEvent_t &e : b->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            delete b;
+            return bfail(nullptr, VMS_EHIP, "event creation failed");
+        }
     b->h_std.resize(n);
     b->h_sub.resize(n);
     if (b->buf.alloc(&b->d_std, (size_t)n) || b->buf.alloc(&b->d_sub, (size_t)n) ||
@@ -1134,7 +1149,7 @@ int vms_batch_assemble(vms_batch *b, const vms_fields *f, void *const *vals, dou
     int rc = batch_tables(b, f, vals, resid);
     if (rc) return rc;
     if (!b->use_graph) {
-        batch_enqueue(b);
+        batch_enqueue(b, true);
         if (hipGetLastError() != hipSuccess) return bfail(b, VMS_EHIP, "launch failed");
         return VMS_OK;
     }
@@ -1147,7 +1162,7 @@ int vms_batch_assemble(vms_batch *b, const vms_fields *f, void *const *vals, dou
     }
     if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return bfail(b, VMS_EHIP, "stream capture failed to start");
-    batch_enqueue(b);
+    batch_enqueue(b, false);
     if (hipStreamEndCapture(b->stream, &b->graph) != hipSuccess ||
         hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
         return bfail(b, VMS_EHIP, "graph capture failed");
@@ -1195,6 +1210,16 @@ int vms_batch_autotune(vms_batch *b, const vms_fields *f, void *const *vals, dou
     if (rc) return rc;
     if (ms_out) *ms_out = best;
     return vms_batch_set_config(b, bt, bg);
+}
+
+int vms_batch_last_timing(vms_batch *b, float *ms) {
+    if (!b || !ms) return bfail(b, VMS_EINVAL, "null argument");
+    if (!b->timed) return bfail(b, VMS_EINVAL, "no eager batched assembly to time");
+    if (hipEventSynchronize(b->ev[2]) != hipSuccess ||
+        hipEventElapsedTime(&ms[0], b->ev[0], b->ev[1]) != hipSuccess ||
+        hipEventElapsedTime(&ms[1], b->ev[1], b->ev[2]) != hipSuccess)
+        return bfail(b, VMS_EHIP, "event timing failed");
+    return VMS_OK;
 }
 
 void vms_batch_destroy(vms_batch *b) {

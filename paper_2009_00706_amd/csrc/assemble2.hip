@@ -176,17 +176,29 @@ __device__ inline void split2h(float x, _Float16 &h, _Float16 &l) {
 }
 
 // CP points per chunk (FP64: 4, mixed: 8 = one MFMA k-step of 32)
+// LDS of one work item. Arrays are flat with padded strides so that the
+// accesses of the phases below spread over the banks (64-bit accesses by 16
+// lanes and 32-bit accesses by 32 lanes touch distinct banks):
+//   U(f, s)          fields at the master slots, row stride 9
+//   B(p, k, s)       constrained basis rows, point stride 40
+//   I(p, f, k)       interpolated fields, field stride 5, point stride 35
+//   D(p, i, j, k, l) coefficient blocks, block stride 17, point stride 276
+constexpr int LU = 9, LB = 40, LI = 35, LDB = 17, LDP = 16 * LDB + 4;
 template <typename T, int CP>
 struct Smem {
-    T sU[7][8];
+    T sU[7 * LU];
     T sC[8][8];
-    T sB[CP][4][8];
-    T sI[CP][7][4];
+    T sB[CP * LB];
+    T sI[CP * LI];
     T sQ[CP][NQ2];
-    T sD[CP][4][4][4][4];  // [p][i][j][k][l], weight folded in
-    T sSc[CP];             // fp16 form: per-point power-of-two balance
+    T sD[CP * LDP];  // weight folded in
+    T sSc[CP];       // fp16 form: per-point power-of-two balance
     int sM[8];
 };
+#define SU(f, s) sU[(f) * LU + (s)]
+#define SB(p, k, s) sB[(p) * LB + (k) * 8 + (s)]
+#define SI(p, f, k) sI[(p) * LI + (f) * 5 + (k)]
+#define SD(p, i, j, k, l) sD[(p) * LDP + ((i) * 4 + (j)) * LDB + (k) * 4 + (l)]
 
 // One work item (an element, or a run of sub-cell points of one element) by
 // one 64-lane workgroup.
@@ -216,7 +228,7 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
     __syncthreads();
     if (lane < 56) {
         const int f = lane >> 3, s = lane & 7, m = sM[s];
-        sU[f][s] = m >= 0 ? (T)field_in(a, f)[m] : T(0);
+        SU(f, s) = m >= 0 ? (T)field_in(a, f)[m] : T(0);
     }
     const int npts = SUB ? a.pt_cnt[item] : 8;
     const T rho = (T)a.rho, mu = (T)a.mu, th = (T)a.theta;
@@ -264,7 +276,7 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
                     b[3] += c * (T)(f[0] * f[1] * g[2]);
                 }
             }
-            for (int k = 0; k < 4; ++k) sB[p][k][s] = b[k];
+            for (int k = 0; k < 4; ++k) SB(p, k, s) = b[k];
             if (s == 0) {
                 sQ[p][QW] = (T)w;
                 sSc[p] = T(1);
@@ -277,10 +289,10 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
             if (p < np && f < 7) {
                 T v[4] = {T(0), T(0), T(0), T(0)};
                 for (int s = 0; s < 8; ++s) {
-                    const T u = sU[f][s];
-                    for (int k = 0; k < 4; ++k) v[k] += sB[p][k][s] * u;
+                    const T u = SU(f, s);
+                    for (int k = 0; k < 4; ++k) v[k] += SB(p, k, s) * u;
                 }
-                for (int k = 0; k < 4; ++k) sI[p][f][k] = v[k];
+                for (int k = 0; k < 4; ++k) SI(p, f, k) = v[k];
             }
         }
         __syncthreads();
@@ -289,12 +301,12 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
             const int p = lane;
             T ut[3], at[3], gu[3][3], gp[3];
             for (int c = 0; c < 3; ++c) {
-                ut[c] = th * sI[p][c][0] + (T(1) - th) * sI[p][4 + c][0];
-                at[c] = (sI[p][c][0] - sI[p][4 + c][0]) * idt;
-                for (int m = 0; m < 3; ++m) gu[c][m] = th * sI[p][c][1 + m] + (T(1) - th) * sI[p][4 + c][1 + m];
-                gp[c] = sI[p][3][1 + c];
+                ut[c] = th * SI(p, c, 0) + (T(1) - th) * SI(p, 4 + c, 0);
+                at[c] = (SI(p, c, 0) - SI(p, 4 + c, 0)) * idt;
+                for (int m = 0; m < 3; ++m) gu[c][m] = th * SI(p, c, 1 + m) + (T(1) - th) * SI(p, 4 + c, 1 + m);
+                gp[c] = SI(p, 3, 1 + c);
             }
-            const T pr = sI[p][3][0];
+            const T pr = SI(p, 3, 0);
             T conv[3], rM[3];
             for (int c = 0; c < 3; ++c) {
                 conv[c] = ut[0] * gu[c][0] + ut[1] * gu[c][1] + ut[2] * gu[c][2];
@@ -371,7 +383,7 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
                         for (int l = 0; l < 4; ++l) D[k][l] = T(0);
                 }
                 for (int k = 0; k < 4; ++k)
-                    for (int l = 0; l < 4; ++l) sD[p][i][j][k][l] = D[k][l];
+                    for (int l = 0; l < 4; ++l) SD(p, i, j, k, l) = D[k][l];
             }
             __syncthreads();
             // ---- phase 5: stage 1 (VALU) and stage 2 (MFMA)
@@ -379,13 +391,13 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
             if (MODE == 0) {
                 const int k = lane >> 4, arow = lane & 15;
                 for (int p = 0; p < np; ++p) {
-                    const double A = arow < 8 ? (double)sB[p][k][arow] : 0.0;
+                    const double A = arow < 8 ? (double)SB(p, k, arow) : 0.0;
                     double Bv[2][4];
                     for (int bh = 0; bh < 2; ++bh)
-                        for (int m = 0; m < 4; ++m) Bv[bh][m] = (double)sB[p][m][4 * bh + bb];
+                        for (int m = 0; m < 4; ++m) Bv[bh][m] = (double)SB(p, m, 4 * bh + bb);
                     for (int i = 0; i < 4; ++i) {
                         double Dv[4];
-                        for (int m = 0; m < 4; ++m) Dv[m] = (double)sD[p][i][jc][k][m];
+                        for (int m = 0; m < 4; ++m) Dv[m] = (double)SD(p, i, jc, k, m);
                         for (int bh = 0; bh < 2; ++bh) {
                             const double F = Dv[0] * Bv[bh][0] + Dv[1] * Bv[bh][1] + Dv[2] * Bv[bh][2] +
                                              Dv[3] * Bv[bh][3];
@@ -401,7 +413,7 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
                 float Av[8];
                 for (int t = 0; t < 8; ++t) {
                     const int p = 2 * g + (t >> 2), k = t & 3;
-                    float v = (float)sB[p][k][ar] * (float)bscale;
+                    float v = (float)SB(p, k, ar) * (float)bscale;
                     if (MODE == 2) v *= (float)sSc[p];
                     Av[t] = v;
                 }
@@ -409,7 +421,7 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
                 float Bc[2][2][4];
                 for (int pp = 0; pp < 2; ++pp)
                     for (int bh = 0; bh < 2; ++bh)
-                        for (int m = 0; m < 4; ++m) Bc[pp][bh][m] = (float)sB[2 * g + pp][m][4 * bh + bb];
+                        for (int m = 0; m < 4; ++m) Bc[pp][bh][m] = (float)SB(2 * g + pp, m, 4 * bh + bb);
                 float fs[2] = {1.f, 1.f};
                 if (MODE == 2)
                     for (int pp = 0; pp < 2; ++pp)
@@ -427,7 +439,7 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
                         for (int t = 0; t < 8; ++t) {
                             const int pp = t >> 2, p = 2 * g + pp, k = t & 3;
                             float d[4];
-                            for (int m = 0; m < 4; ++m) d[m] = (float)sD[p][i][jc][k][m];
+                            for (int m = 0; m < 4; ++m) d[m] = (float)SD(p, i, jc, k, m);
                             for (int bh = 0; bh < 2; ++bh) {
                                 const float F = d[0] * Bc[pp][bh][0] + d[1] * Bc[pp][bh][1] +
                                                 d[2] * Bc[pp][bh][2] + d[3] * Bc[pp][bh][3];
@@ -457,7 +469,7 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
                         for (int t = 0; t < 8; ++t) {
                             const int pp = t >> 2, p = 2 * g + pp, k = t & 3;
                             float d[4];
-                            for (int m = 0; m < 4; ++m) d[m] = (float)sD[p][i][jc][k][m];
+                            for (int m = 0; m < 4; ++m) d[m] = (float)SD(p, i, jc, k, m);
                             for (int bh = 0; bh < 2; ++bh) {
                                 // undo the basis scaling and the balance on this operand
                                 const float F = (d[0] * Bc[pp][bh][0] + d[1] * Bc[pp][bh][1] +
@@ -481,8 +493,8 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
         if (lane < 32) {
             const int av = lane & 7, i = lane >> 3;
             for (int p = 0; p < np; ++p)
-                R += sB[p][0][av] * sQ[p][QRC + 4 * i] + sB[p][1][av] * sQ[p][QRC + 4 * i + 1] +
-                     sB[p][2][av] * sQ[p][QRC + 4 * i + 2] + sB[p][3][av] * sQ[p][QRC + 4 * i + 3];
+                R += SB(p, 0, av) * sQ[p][QRC + 4 * i] + SB(p, 1, av) * sQ[p][QRC + 4 * i + 1] +
+                     SB(p, 2, av) * sQ[p][QRC + 4 * i + 2] + SB(p, 3, av) * sQ[p][QRC + 4 * i + 3];
         }
         __syncthreads();
     }

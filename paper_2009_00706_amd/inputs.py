@@ -16,6 +16,8 @@ from __future__ import annotations
 import math
 from dataclasses import dataclass, field
 
+import os
+
 import numpy as np
 
 # ---------------------------------------------------------------------------
@@ -484,40 +486,49 @@ def ellipsoid_refined_octree(center, semi, rot, lmin, lmax, beta, balance=True) 
                           meta={"body": "ellipsoid", "beta": beta, "lmin": lmin, "lmax": lmax})
 
 
-def batch_workload(n_trees: int, seed: int, size_lo=1e4, size_hi=5e5, lmin=4, lmax=9,
-                   tri_lo=2000, tri_hi=20000):
+def _batch_tree(arg):
+    target, semi, R, c, ntri, lmin = arg
+    n_lat = max(3, int(round(np.sqrt(ntri / 4.0))))
+    surf = ellipsoid(semi, c, R, n_lat, 2 * n_lat)
+    # the band count at beta = 1 grows about 4x per level
+    l_ref = lmin + 2
+    n_ref = ellipsoid_refined_octree(c, semi, R, lmin, l_ref, 1.0).n
+    lmax = int(np.clip(np.round(l_ref + np.log(target / n_ref) / np.log(4.0)), lmin + 1, 11))
+    beta = float(np.clip(target / (n_ref * 4.0 ** (lmax - l_ref)), 0.25, 8.0))
+    tree = None
+    for _ in range(8):
+        tree = ellipsoid_refined_octree(c, semi, R, lmin, lmax, beta)
+        if abs(tree.n - target) <= 0.1 * target:
+            break
+        beta = float(np.clip(beta * (target / tree.n), 0.05, 32.0))
+    tree.meta["target"] = target
+    return tree, surf
+
+
+def batch_workload(n_trees: int, seed: int, size_lo=1e4, size_hi=5e5, lmin=4, tri_lo=2000,
+                   tri_hi=20000, workers=None):
     """Independent octrees of log-uniform target sizes, each refined around its own
     ellipsoid (semi-axes U(0.05, 0.2), random rotation, centre U(0.25, 0.75)^3,
-    lat-long tessellation with U(tri_lo, tri_hi) triangles). The refinement width
-    beta is bisected per tree so the leaf count before balancing is within 10%
-    of the target."""
+    lat-long tessellation with U(tri_lo, tri_hi) triangles).
+
+    Each tree gets the finest level whose refinement band of about one cell
+    (beta = 1) holds the target leaf count most closely, then beta is adjusted
+    (the count grows about linearly in beta) until the 2:1-balanced tree is
+    within 10% of the target. All random draws happen first, in tree order, so
+    the result does not depend on the number of worker processes (workers > 1
+    starts a spawn-context pool: the calling script needs a main guard)."""
     rng = np.random.default_rng(seed)
-    out = []
+    args = []
     for _ in range(n_trees):
         target = float(np.exp(rng.uniform(np.log(size_lo), np.log(size_hi))))
         semi = rng.uniform(0.05, 0.2, 3)
         R = random_rotation(rng)
         c = rng.uniform(0.25, 0.75, 3)
         ntri = int(rng.integers(tri_lo, tri_hi + 1))
-        n_lat = max(3, int(round(np.sqrt(ntri / 4.0))))
-        surf = ellipsoid(semi, c, R, n_lat, 2 * n_lat)
-        goal = target
-        for attempt in range(2):   # second pass corrects for the growth from balancing
-            lo_b, hi_b = 0.01, 64.0
-            beta = 1.0
-            for _ in range(24):
-                beta = np.sqrt(lo_b * hi_b)
-                n = ellipsoid_refined_octree(c, semi, R, lmin, lmax, beta, balance=False).n
-                if abs(n - goal) <= 0.1 * goal:
-                    break
-                if n < goal:
-                    lo_b = beta
-                else:
-                    hi_b = beta
-            tree = ellipsoid_refined_octree(c, semi, R, lmin, lmax, beta)
-            if tree.n <= 1.1 * target:
-                break
-            goal = goal * target / tree.n
-        tree.meta["target"] = target
-        out.append((tree, surf))
-    return out
+        args.append((target, semi, R, c, ntri, lmin))
+    workers = min(workers or 1, n_trees)
+    if workers <= 1:
+        return [_batch_tree(a) for a in args]
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(workers) as pool:
+        return pool.map(_batch_tree, args, chunksize=1)

@@ -30,8 +30,8 @@ EXPORTED = ["vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply"
             "vms_mlp_set_margin", "vms_mlp_grad", "vms_mlp_train", "vms_mlp_adam_step",
             "vms_mlp_predict", "vms_mlp_last_error", "vms_mlp_destroy", "vms_sdf_sample",
             "vms_batch_create", "vms_batch_set_config", "vms_batch_get_config",
-            "vms_batch_use_graph", "vms_batch_assemble", "vms_batch_autotune", "vms_batch_destroy",
-            "vms_last_error", "vms_destroy"]
+            "vms_batch_use_graph", "vms_batch_assemble", "vms_batch_autotune", "vms_batch_last_timing",
+            "vms_batch_destroy", "vms_last_error", "vms_destroy"]
 
 
 class VmsError(RuntimeError):
@@ -107,6 +107,7 @@ def lib():
         L.vms_batch_use_graph.argtypes = [p, C.c_int]
         L.vms_batch_assemble.argtypes = [p, p, p, p]
         L.vms_batch_autotune.argtypes = [p, p, p, p, p]
+        L.vms_batch_last_timing.argtypes = [p, p]
         L.vms_batch_destroy.argtypes = [p]
         L.vms_batch_destroy.restype = None
         L.vms_set_timing.argtypes = [p, C.c_int]
@@ -122,7 +123,7 @@ def lib():
                   "vms_mlp_grad", "vms_mlp_train", "vms_mlp_adam_step", "vms_mlp_predict",
                   "vms_sdf_sample", "vms_batch_create", "vms_batch_set_config",
                   "vms_batch_get_config", "vms_batch_use_graph", "vms_batch_assemble",
-                  "vms_batch_autotune"):
+                  "vms_batch_autotune", "vms_batch_last_timing"):
             getattr(L, n).restype = C.c_int
         _lib = L
     return _lib
@@ -407,6 +408,12 @@ def vms_batch_autotune(b, fields, vals, resid=None):
     ms = C.c_float(0)
     _check(lib().vms_batch_autotune(b, fa, va, ra, C.byref(ms)), None)
     return ms.value
+
+
+def vms_batch_last_timing(b):
+    ms = (C.c_float * 2)()
+    _check(lib().vms_batch_last_timing(b, ms), None)
+    return [ms[0], ms[1]]
 
 
 def vms_batch_destroy(b):

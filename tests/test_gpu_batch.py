@@ -20,7 +20,7 @@ def env():
 
 
 def build(torch, vms, prec, n_trees=5, seed=1003):
-    work = I.batch_workload(n_trees, seed, size_lo=2e3, size_hi=3e4, lmin=3, lmax=8)
+    work = I.batch_workload(n_trees, seed, size_lo=2e3, size_hi=3e4, lmin=3)
     stream = torch.cuda.Stream()
     ctxs, fields, vals, resid, trees = [], [], [], [], []
     with torch.cuda.stream(stream):
