@@ -141,7 +141,7 @@ def run_single(torch, vms, tree, surf, f, prec, steps, warmup, flags):
     for _ in range(warmup):
         asm.assemble(flags=flags)
     torch.cuda.synchronize()
-    stage = np.zeros((steps, 4))
+    stage = np.zeros((steps, 5))
     t0 = time.perf_counter()
     for k in range(steps):
         asm.assemble(flags=flags)
@@ -212,7 +212,7 @@ def main_single(args):
         "inout_tests_per_s": (st["n_labelled"] / (avg[0] * 1e-3)) if avg[0] > 0 else None,
         "steady_state_elements_per_s": r["steady"],
         "stage_ms": {"relabel": avg[0], "zero": avg[1], "out_elements": avg[2],
-                     "intercepted_elements": avg[3]},
+                     "intercepted_elements": avg[3], "csr_gather": avg[4]},
         "setup_s": r["setup_s"],
         "roofline": roofline(k_ms, n_pts, peak, traffic_for(args.traffic, args.workload, pname),
                              kname),
@@ -228,7 +228,8 @@ def main_single(args):
                            "rel_err_jacobian": ej, "rel_err_residual": er,
                            "stage_ms": {"relabel": m["stage"][0], "zero": m["stage"][1],
                                         "out_elements": m["stage"][2],
-                                        "intercepted_elements": m["stage"][3]}}
+                                        "intercepted_elements": m["stage"][3],
+                                        "csr_gather": m["stage"][4]}}
         out["forms"] = forms
         out["forms_note"] = ("mixed forms on the same inputs and step; errors are normwise against "
                              "this FP64 GPU result (itself within 1e-12 of the CPU reference)")
@@ -307,7 +308,8 @@ def main_batch(args):
                    "n_subgp": n_sub, "tree_sizes_min_median_max": [sizes[0], sizes[len(sizes) // 2],
                                                                    sizes[-1]],
                    "precision": pname, "autotuned": cfgb, "autotune_best_ms": tune_ms},
-        "stage_ms": {"zero": float(kms[0]), "persistent_assembly": float(kms[1])},
+        "stage_ms": {"zero": float(kms[0]), "persistent_assembly": float(kms[1]),
+                     "csr_gather": float(kms[2])},
         "setup_s": {"generate": gen_s, "contexts": setup_s},
         "roofline": roofline(float(kms[1]), n_pts,
                              PEAK_FP64_TFLOPS if prec == vms.VMS_FP64 else PEAK_FP32_TFLOPS,

@@ -197,9 +197,10 @@ void vms_mesh_destroy(vms_mesh *h);
 
 /* Per-stage timing with HIP events recorded on the context stream (off by
  * default). vms_last_timing synchronises on the last recorded event and
- * writes HOST ms[4]: relabelling (sub-cell quadrature and in-out tests),
- * zeroing and identity rows, OUT-element assembly kernel, INTERCEPTED-element
- * assembly kernel, of the last vms_assemble / vms_apply. */
+ * writes HOST ms[5]: relabelling (sub-cell quadrature and in-out tests),
+ * zeroing of the residual, OUT-element assembly kernel, INTERCEPTED-element
+ * assembly kernel, CSR summation of the element matrices (with identity
+ * rows), of the last vms_assemble / vms_apply. */
 int vms_set_timing(vms_ctx *ctx, int on);
 int vms_last_timing(vms_ctx *ctx, float *ms);
 
@@ -254,9 +255,9 @@ int vms_sdf_sample(inout_handle *h, const double *px, const double *py, const do
  * work first: INTERCEPTED elements carry more quadrature points and in-out
  * work, the load imbalance that the paper's weighted partition (eq. Wpart,
  * section on dynamic load balancing) addresses across processes.
- * vms_batch_last_timing writes HOST ms[2] (zeroing kernels, persistent
- * assembly kernel) of the last eager (not graph-replayed) vms_batch_assemble,
- * synchronising on it; VMS_EINVAL if there was none. */
+ * vms_batch_last_timing writes HOST ms[3] (zeroing kernels, persistent
+ * assembly kernel, CSR summations) of the last eager (not graph-replayed)
+ * vms_batch_assemble, synchronising on it; VMS_EINVAL if there was none. */
 typedef struct vms_batch vms_batch;
 int vms_batch_create(vms_batch **out, vms_ctx *const *ctxs, int n, void *stream);
 int vms_batch_set_config(vms_batch *b, int tile, int groups_per_cu);

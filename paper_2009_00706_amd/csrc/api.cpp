@@ -213,17 +213,24 @@ struct vms_ctx {
     int64_t n_subgp = 0;
     // assembly work items over the sub-cell points: at most ITEM_PTS points each
     int64_t n_sub_items = 0;
+    std::vector<int32_t> sub_item_el;  // element of each item (host copy)
     int32_t *d_sub_el = nullptr, *d_sub_cnt = nullptr;
     int64_t *d_sub_off = nullptr;
     // identity rows of inactive nodes
     int64_t n_ones = 0;
     int64_t *d_ones = nullptr;
+    // element-matrix records (one per work item: OUT elements first, then the
+    // sub-cell items) and, per CSR block, the list of record blocks summed into it
+    int64_t n_slots = 0, n_blocks = 0;
+    void *d_em = nullptr;
+    int64_t *d_cb_off = nullptr, *d_nrow_ptr = nullptr;
+    int32_t *d_contrib = nullptr, *d_blk_row = nullptr;
     unsigned long long *d_counters = nullptr;  // 0: labelled points, 1: degenerate directions
     unsigned int *d_flag = nullptr;            // device-side overflow flag
     double *d_norm = nullptr;
     // optional per-stage timing with events on the context stream
     bool timing = false;
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     uint64_t n_labelled = 0, n_degenerate = 0;
 };
 
@@ -391,6 +398,65 @@ int run_subquad(vms_ctx *c, bool first) {
 
 }  // namespace
 
+// Per CSR block, the element-matrix record blocks that sum into it, in
+// ascending record order (record r = work item slot * 64 + 8 s + t for master
+// slots s, t; slots: OUT elements in list order, then the sub-cell items).
+static int build_gather(vms_ctx *c, const std::vector<int32_t> &stdl) {
+    const vms::MeshHost &m = c->mesh;
+    const std::vector<int32_t> &sub_el = c->sub_item_el;
+    c->n_slots = c->n_std + c->n_sub_items;
+    c->n_blocks = m.nrow_ptr[m.n_nodes];
+    if (c->n_slots * 64 > INT32_MAX) return fail(c, VMS_EUNSUPPORTED, "too many element-matrix records");
+    auto el_of = [&](int64_t slot) { return slot < c->n_std ? stdl[slot] : sub_el[slot - c->n_std]; };
+    std::vector<int64_t> off(c->n_blocks + 1, 0);
+    for (int64_t sl = 0; sl < c->n_slots; ++sl) {
+        const int64_t e = el_of(sl);
+        for (int s = 0; s < 8; ++s) {
+            const int ms = m.masters[8 * e + s];
+            if (ms < 0) continue;
+            for (int t = 0; t < 8; ++t)
+                if (m.masters[8 * e + t] >= 0) ++off[m.nrow_ptr[ms] + m.el_kk[64 * e + 8 * s + t] + 1];
+        }
+    }
+    for (int64_t b = 0; b < c->n_blocks; ++b) off[b + 1] += off[b];
+    std::vector<int32_t> contrib(off[c->n_blocks]);
+    std::vector<int64_t> pos(off.begin(), off.end() - 1);
+    for (int64_t sl = 0; sl < c->n_slots; ++sl) {
+        const int64_t e = el_of(sl);
+        for (int s = 0; s < 8; ++s) {
+            const int ms = m.masters[8 * e + s];
+            if (ms < 0) continue;
+            for (int t = 0; t < 8; ++t)
+                if (m.masters[8 * e + t] >= 0)
+                    contrib[pos[m.nrow_ptr[ms] + m.el_kk[64 * e + 8 * s + t]]++] = (int32_t)(sl * 64 + 8 * s + t);
+        }
+    }
+    std::vector<int32_t> blk_row(c->n_blocks);
+    for (int64_t n = 0; n < m.n_nodes; ++n)
+        for (int64_t b = m.nrow_ptr[n]; b < m.nrow_ptr[n + 1]; ++b) blk_row[b] = (int32_t)n;
+    const size_t esz = c->prm.precision == VMS_FP64 ? 8 : 4;
+    char *em = nullptr;
+    if (upload(c, &c->d_cb_off, off) || upload(c, &c->d_contrib, contrib) ||
+        upload(c, &c->d_blk_row, blk_row) || upload(c, &c->d_nrow_ptr, m.nrow_ptr) ||
+        c->buf.alloc(&em, (size_t)std::max<int64_t>(c->n_slots, 1) * 1024 * esz))
+        return fail(c, VMS_ENOMEM, "device allocation failed (element-matrix records)");
+    c->d_em = em;
+    return VMS_OK;
+}
+
+// CSR values = sums of the element-matrix records, then identity blocks
+static void gather_csr(vms_ctx *c, hipStream_t st, void *vals) {
+    if (c->prm.precision == VMS_FP64) {
+        vmsk::launch_gather_f64(st, (const double *)c->d_em, c->d_cb_off, c->d_contrib, c->d_blk_row,
+                                c->d_nrow_ptr, c->n_blocks, (double *)vals);
+        vmsk::launch_set_ones_f64(st, (double *)vals, c->d_ones, c->n_ones);
+    } else {
+        vmsk::launch_gather_f32(st, (const float *)c->d_em, c->d_cb_off, c->d_contrib, c->d_blk_row,
+                                c->d_nrow_ptr, c->n_blocks, (float *)vals);
+        vmsk::launch_set_ones_f32(st, (float *)vals, c->d_ones, c->n_ones);
+    }
+}
+
 extern "C" {
 
 const char *vms_last_error(vms_ctx *ctx) {
@@ -548,6 +614,7 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
                 icnt.push_back((int32_t)std::min<int64_t>(ITEM_PTS, c->sq_cnt[i] - p));
             }
         c->n_sub_items = (int64_t)iel.size();
+        c->sub_item_el = iel;
         if (upload(c, &c->d_sub_el, iel) || upload(c, &c->d_sub_off, ioff) ||
             upload(c, &c->d_sub_cnt, icnt))
             return bail(VMS_ENOMEM);
@@ -577,6 +644,8 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
         upload(c, &c->d_rowbase, m.el_rowbase) || upload(c, &c->d_rowlen, m.el_rowlen) ||
         upload(c, &c->d_kk, m.el_kk) || upload(c, &c->d_std, stdl) || upload(c, &c->d_ones, ones))
         return bail(VMS_ENOMEM);
+    rc = build_gather(c, stdl);
+    if (rc) return bail(rc);
     if (hipStreamSynchronize(c->stream) != hipSuccess) {
         c->err = "device synchronisation failed at create";
         return bail(VMS_EHIP);
@@ -690,15 +759,6 @@ static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *re
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
     const bool fp64 = c->prm.precision == VMS_FP64;
     const int64_t nrows = 4 * c->mesh.n_nodes;
-    if (mat) {
-        if (fp64) {
-            vmsk::launch_fill_f64(c->stream, (double *)vals, c->mesh.nnz, 0.0);
-            vmsk::launch_set_ones_f64(c->stream, (double *)vals, c->d_ones, c->n_ones);
-        } else {
-            vmsk::launch_fill_f32(c->stream, (float *)vals, c->mesh.nnz, 0.0f);
-            vmsk::launch_set_ones_f32(c->stream, (float *)vals, c->d_ones, c->n_ones);
-        }
-    }
     if (resid) vmsk::launch_fill_f64(c->stream, resid, nrows, 0.0);
     vmsk::AsmArgs a{};
     a.masters = c->d_masters;
@@ -714,6 +774,8 @@ static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *re
     a.c_t = c->prm.c_t; a.c_i = c->prm.c_i; a.root_len = c->root_len;
     a.vals = vals;
     a.resid = resid;
+    a.em = c->d_em;
+    a.slot0 = 0;
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
     // OUT elements: 2x2x2 Gauss points
     a.n_items = c->n_std;
@@ -729,11 +791,17 @@ static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *re
         a.pt_off = c->d_sub_off;
         a.pt_cnt = c->d_sub_cnt;
         a.entries = c->d_entries;
+        a.slot0 = c->n_std;
         if (fp64) vmsk::launch_assemble_f64(c->stream, a, true, mat);
         else vmsk::launch_assemble_mixed(c->stream, a, true, mat, c->prm.precision == VMS_MIXED_FP16);
         HIPCHK(c, hipGetLastError());
     }
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[4], c->stream));
+    if (mat) {
+        gather_csr(c, c->stream, vals);
+        HIPCHK(c, hipGetLastError());
+    }
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[5], c->stream));
     return VMS_OK;
 }
 
@@ -749,8 +817,8 @@ int vms_set_timing(vms_ctx *c, int on) {
 int vms_last_timing(vms_ctx *c, float *ms) {
     if (!c || !ms) return fail(c, VMS_EINVAL, "null argument");
     if (!c->timing) return fail(c, VMS_EINVAL, "timing is off");
-    HIPCHK(c, hipEventSynchronize(c->ev[4]));
-    for (int k = 0; k < 4; ++k) HIPCHK(c, hipEventElapsedTime(&ms[k], c->ev[k], c->ev[k + 1]));
+    HIPCHK(c, hipEventSynchronize(c->ev[5]));
+    for (int k = 0; k < 5; ++k) HIPCHK(c, hipEventElapsedTime(&ms[k], c->ev[k], c->ev[k + 1]));
     return VMS_OK;
 }
 
@@ -954,7 +1022,7 @@ struct vms_batch {
     hipGraphExec_t exec = nullptr;
     std::vector<const void *> cap_ptrs;
     // timing of the last eager launch sequence
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool timed = false;
     std::string err = "no error";
     ~vms_batch() {
@@ -1020,6 +1088,8 @@ int batch_tables(vms_batch *b, const vms_fields *f, void *const *vals, double *c
         for (int k = 0; k < 7; ++k) a.f[k] = fp[k];
         a.vals = vals[t];
         a.resid = resid ? resid[t] : nullptr;
+        a.em = c->d_em;
+        a.slot0 = 0;
         a.n_items = c->n_std;
         a.items = c->d_std;
         b->h_std[t] = a;
@@ -1028,6 +1098,7 @@ int batch_tables(vms_batch *b, const vms_fields *f, void *const *vals, double *c
         a.pt_off = c->d_sub_off;
         a.pt_cnt = c->d_sub_cnt;
         a.entries = c->d_entries;
+        a.slot0 = c->n_std;
         b->h_sub[t] = a;
     }
     if (hipMemcpyAsync(b->d_std, b->h_std.data(), n * sizeof(vmsk::AsmArgs), hipMemcpyHostToDevice, b->stream) ||
@@ -1042,21 +1113,15 @@ int batch_tables(vms_batch *b, const vms_fields *f, void *const *vals, double *c
 void batch_enqueue(vms_batch *b, bool timed) {
     if (timed) (void)hipEventRecord(b->ev[0], b->stream);
     for (size_t t = 0; t < b->ctx.size(); ++t) {
-        vms_ctx *c = b->ctx[t];
         const vmsk::AsmArgs &a = b->h_std[t];
-        if (b->precision == VMS_FP64) {
-            vmsk::launch_fill_f64(b->stream, (double *)a.vals, c->mesh.nnz, 0.0);
-            vmsk::launch_set_ones_f64(b->stream, (double *)a.vals, c->d_ones, c->n_ones);
-        } else {
-            vmsk::launch_fill_f32(b->stream, (float *)a.vals, c->mesh.nnz, 0.0f);
-            vmsk::launch_set_ones_f32(b->stream, (float *)a.vals, c->d_ones, c->n_ones);
-        }
-        if (a.resid) vmsk::launch_fill_f64(b->stream, a.resid, 4 * c->mesh.n_nodes, 0.0);
+        if (a.resid) vmsk::launch_fill_f64(b->stream, a.resid, 4 * b->ctx[t]->mesh.n_nodes, 0.0);
     }
     if (timed) (void)hipEventRecord(b->ev[1], b->stream);
     vmsk::launch_assemble_batch(b->stream, b->precision, b->d_std, b->d_sub, b->d_units, b->n_units,
                                 b->d_counter, b->n_cu * b->groups_per_cu);
     if (timed) (void)hipEventRecord(b->ev[2], b->stream);
+    for (size_t t = 0; t < b->ctx.size(); ++t) gather_csr(b->ctx[t], b->stream, b->h_std[t].vals);
+    if (timed) (void)hipEventRecord(b->ev[3], b->stream);
     b->timed = timed;
 }
 
@@ -1215,9 +1280,10 @@ int vms_batch_autotune(vms_batch *b, const vms_fields *f, void *const *vals, dou
 int vms_batch_last_timing(vms_batch *b, float *ms) {
     if (!b || !ms) return bfail(b, VMS_EINVAL, "null argument");
     if (!b->timed) return bfail(b, VMS_EINVAL, "no eager batched assembly to time");
-    if (hipEventSynchronize(b->ev[2]) != hipSuccess ||
+    if (hipEventSynchronize(b->ev[3]) != hipSuccess ||
         hipEventElapsedTime(&ms[0], b->ev[0], b->ev[1]) != hipSuccess ||
-        hipEventElapsedTime(&ms[1], b->ev[1], b->ev[2]) != hipSuccess)
+        hipEventElapsedTime(&ms[1], b->ev[1], b->ev[2]) != hipSuccess ||
+        hipEventElapsedTime(&ms[2], b->ev[2], b->ev[3]) != hipSuccess)
         return bfail(b, VMS_EHIP, "event timing failed");
     return VMS_OK;
 }

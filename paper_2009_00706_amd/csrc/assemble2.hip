@@ -184,14 +184,21 @@ __device__ inline void split2h(float x, _Float16 &h, _Float16 &l) {
 //   I(p, f, k)       interpolated fields, field stride 5, point stride 35
 //   D(p, i, j, k, l) coefficient blocks, block stride 17, point stride 276
 constexpr int LU = 9, LB = 40, LI = 35, LDB = 17, LDP = 16 * LDB + 4;
+// element-matrix staging: block (a, b) of master slots, entry e = 4 i + j
+// (test component i, trial component j), padded strides; EMS_SIZE entries
+#define EMS(av, b, e) ((av) * 164 + (b) * 20 + (e))
+constexpr int EMS_SIZE = 7 * 164 + 7 * 20 + 16;
 template <typename T, int CP>
 struct Smem {
     T sU[7 * LU];
     T sC[8][8];
     T sB[CP * LB];
-    T sI[CP * LI];
     T sQ[CP][NQ2];
-    T sD[CP * LDP];  // weight folded in
+    union {  // the interpolated fields are dead once the point quantities exist
+        T sI[CP * LI];
+        T sD[CP * LDP];  // weight folded in
+        T sE[EMS_SIZE];  // element-matrix staging after the last chunk
+    };
     T sSc[CP];       // fp16 form: per-point power-of-two balance
     int sM[8];
 };
@@ -200,10 +207,13 @@ struct Smem {
 #define SI(p, f, k) sI[(p) * LI + (f) * 5 + (k)]
 #define SD(p, i, j, k, l) sD[(p) * LDP + ((i) * 4 + (j)) * LDB + (k) * 4 + (l)]
 
+
 // One work item (an element, or a run of sub-cell points of one element) by
 // one 64-lane workgroup.
 template <typename T, int MODE, bool SUB, bool MAT, int CP>
 __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) {
+    static_assert(MODE == 0 || CP == 8, "the mixed forms take 8 points per MFMA k-step");
+    static_assert(CP >= 1 && CP <= 8, "at most 8 points per chunk (one lane group of 8 per point)");
     auto &sU = sm.sU;
     auto &sC = sm.sC;
     auto &sB = sm.sB;
@@ -499,42 +509,37 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
         __syncthreads();
     }
 
-    // ---- scatter
+    // ---- element matrix out: accumulators -> LDS (block-major, padded) -> one
+    // coalesced 1024-entry record per work item; the CSR is summed from these
+    // records by the gather kernel (no atomics, fixed summation order)
     if (MAT) {
+        T *stage = sm.sE;  // shares the D area, free after the last chunk
         const int col = lane & 15, bb = col >> 2, jc = col & 3;
+        __syncthreads();
         if (MODE == 0) {
-            double *vals = (double *)a.vals;
             for (int t = 0; t < 8; ++t) {
                 const int i = t >> 1, b = 4 * (t & 1) + bb;
-                if (sM[b] < 0) continue;
                 for (int r = 0; r < 2; ++r) {
                     const int av = 4 * r + (lane >> 4);  // output row = 4 r + lane / 16
-                    if (sM[av] < 0) continue;
-                    const int64_t idx = a.rowbase[8 * (int64_t)e + av] +
-                                        (int64_t)i * a.rowlen[8 * (int64_t)e + av] +
-                                        4 * (int64_t)a.kk[64 * (int64_t)e + 8 * av + b] + jc;
-                    atomicAdd(vals + idx, accd[t][r]);
+                    stage[EMS(av, b, 4 * i + jc)] = (T)accd[t][r];
                 }
             }
         } else {
             // rows 8..15 carry the second split term: fold them onto rows 0..7
-            float *vals = (float *)a.vals;
             for (int t = 0; t < 8; ++t) {
                 v4f v = accf[t];
                 for (int r = 0; r < 4; ++r) v[r] += __shfl_down(v[r], 32, 64);
                 if (lane >= 32) continue;
                 const int i = t >> 1, b = 4 * (t & 1) + bb;
-                if (sM[b] < 0) continue;
                 for (int r = 0; r < 4; ++r) {
                     const int av = 4 * (lane >> 4) + r;  // output row = 4 (lane / 16) + r
-                    if (sM[av] < 0) continue;
-                    const int64_t idx = a.rowbase[8 * (int64_t)e + av] +
-                                        (int64_t)i * a.rowlen[8 * (int64_t)e + av] +
-                                        4 * (int64_t)a.kk[64 * (int64_t)e + 8 * av + b] + jc;
-                    atomicAdd(vals + idx, v[r]);
+                    stage[EMS(av, b, 4 * i + jc)] = (T)v[r];
                 }
             }
         }
+        __syncthreads();
+        T *dst = (T *)a.em + (a.slot0 + item) * 1024;
+        for (int v = lane; v < 1024; v += 64) dst[v] = stage[EMS(v >> 7, (v >> 4) & 7, v & 15)];
     }
     if (lane < 32 && a.resid) {
         const int av = lane & 7, i = lane >> 3;
@@ -593,6 +598,48 @@ void launch_assemble_batch(hipStream_t s, int precision, const AsmArgs *std_args
     else
         hipLaunchKernelGGL((k_asm_batch<float, 2, 8>), grid, block, 0, s, std_args, sub_args, units,
                            n_units, counter);
+}
+
+// CSR values from the element-matrix records: thread (block B, entry e) sums
+// the entry over B's contributions in list order (ascending record), then
+// writes it at its place in the CSR (node row n, block kk within the row:
+// dof row 4 n + i, value 16 nrow_ptr[n] + i 4 deg(n) + 4 kk + j).
+template <typename T>
+__global__ void k_gather(const T *em, const int64_t *cb_off, const int32_t *contrib,
+                         const int32_t *blk_row, const int64_t *nrow_ptr, int64_t nb, T *vals) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t B = g >> 4;
+    if (B >= nb) return;
+    const int e = (int)(g & 15);
+    // contributions fetched four at a time (independent loads), summed in list order
+    const int64_t c0 = cb_off[B], c1 = cb_off[B + 1];
+    double s = 0.0;
+    for (int64_t c = c0; c < c1; c += 4) {
+        int32_t r[4];
+        for (int u = 0; u < 4; ++u) r[u] = c + u < c1 ? contrib[c + u] : -1;
+        double v[4];
+        for (int u = 0; u < 4; ++u) v[u] = r[u] >= 0 ? (double)em[(int64_t)r[u] * 16 + e] : 0.0;
+        for (int u = 0; u < 4; ++u)
+            if (r[u] >= 0) s += v[u];
+    }
+    const int n = blk_row[B];
+    const int64_t b0 = nrow_ptr[n], deg = nrow_ptr[n + 1] - b0;
+    vals[16 * b0 + (int64_t)(e >> 2) * 4 * deg + 4 * (B - b0) + (e & 3)] = (T)s;
+}
+
+void launch_gather_f64(hipStream_t s, const double *em, const int64_t *cb_off, const int32_t *contrib,
+                       const int32_t *blk_row, const int64_t *nrow_ptr, int64_t nb, double *vals) {
+    if (nb <= 0) return;
+    const int64_t n = 16 * nb;
+    hipLaunchKernelGGL(k_gather<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, em, cb_off,
+                       contrib, blk_row, nrow_ptr, nb, vals);
+}
+void launch_gather_f32(hipStream_t s, const float *em, const int64_t *cb_off, const int32_t *contrib,
+                       const int32_t *blk_row, const int64_t *nrow_ptr, int64_t nb, float *vals) {
+    if (nb <= 0) return;
+    const int64_t n = 16 * nb;
+    hipLaunchKernelGGL(k_gather<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, em, cb_off,
+                       contrib, blk_row, nrow_ptr, nb, vals);
 }
 
 void launch_assemble_f64(hipStream_t s, const AsmArgs &a, bool sub, bool mat) {

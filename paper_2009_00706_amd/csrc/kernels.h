@@ -84,9 +84,12 @@ struct AsmArgs {
     const double *f[7];       // ux uy uz p ux0 uy0 uz0
     // parameters
     double rho, mu, dt, theta, c_t, c_i, root_len;
-    // outputs
+    // outputs: element-matrix records (1024 entries per work item, record
+    // slot0 + item) and the residual (atomic additions)
     void *vals;
     double *resid;
+    void *em;
+    int64_t slot0;
 };
 void launch_assemble_f64(hipStream_t s, const AsmArgs &a, bool sub, bool mat);
 
@@ -104,6 +107,11 @@ void launch_assemble_batch(hipStream_t s, int precision, const AsmArgs *std_args
                            unsigned long long *counter, int n_groups);
 void launch_assemble_mixed(hipStream_t s, const AsmArgs &a, bool sub, bool mat, int fp16);
 
+// CSR values from element-matrix records (see k_gather)
+void launch_gather_f64(hipStream_t s, const double *em, const int64_t *cb_off, const int32_t *contrib,
+                       const int32_t *blk_row, const int64_t *nrow_ptr, int64_t nb, double *vals);
+void launch_gather_f32(hipStream_t s, const float *em, const int64_t *cb_off, const int32_t *contrib,
+                       const int32_t *blk_row, const int64_t *nrow_ptr, int64_t nb, float *vals);
 void launch_fill_f64(hipStream_t s, double *p, int64_t n, double v);
 void launch_fill_f32(hipStream_t s, float *p, int64_t n, float v);
 void launch_set_ones_f64(hipStream_t s, double *vals, const int64_t *idx, int64_t n);

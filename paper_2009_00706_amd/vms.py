@@ -307,8 +307,9 @@ def vms_set_timing(ctx, on=True):
 
 
 def vms_last_timing(ctx):
-    """ms of the last call: relabel, zero/identity, OUT-element kernel, INTERCEPTED kernel."""
-    v = (C.c_float * 4)()
+    """ms of the last call: relabel, zeroing, OUT-element kernel, INTERCEPTED kernel,
+    CSR summation (with identity rows)."""
+    v = (C.c_float * 5)()
     _check(lib().vms_last_timing(ctx, v), ctx)
     return list(v)
 
@@ -411,9 +412,10 @@ def vms_batch_autotune(b, fields, vals, resid=None):
 
 
 def vms_batch_last_timing(b):
-    ms = (C.c_float * 2)()
+    """ms of the last eager batched call: zeroing, persistent kernel, CSR summations."""
+    ms = (C.c_float * 3)()
     _check(lib().vms_batch_last_timing(b, ms), None)
-    return [ms[0], ms[1]]
+    return list(ms)
 
 
 def vms_batch_destroy(b):
