@@ -163,6 +163,39 @@ __device__ inline void dblock(const T *Q, int i, int j, T rho, T mu, T th, T D[4
         for (int l = 0; l < 4; ++l) D[k][l] *= W;
 }
 
+// D blocks of the three simple kinds in one code path (weight folded in):
+// momentum test / pressure trial (i < 3, j = 3), continuity test / velocity
+// trial (i = 3, j < 3) and continuity / pressure (i = j = 3); the kind flags
+// multiply exact zeros into the terms of the other kinds.
+template <typename T>
+__device__ inline void dblock_simple(const T *Q, int i, int j, T rho, T th, T D[4][4]) {
+    const T W = Q[QW], tauM = Q[QTM];
+    const T fmp = (i < 3 && j == 3) ? T(1) : T(0);
+    const T fcv = (i == 3 && j < 3) ? T(1) : T(0);
+    const T fcc = (i == 3 && j == 3) ? T(1) : T(0);
+    const int ii = i < 3 ? i : 2, jj = j < 3 ? j : 2;
+    T g[3], Acol[3], ym[3], xm[3], ut[3];
+    for (int l = 0; l < 3; ++l) {
+        g[l] = Q[QG + 3 * ii + l];
+        Acol[l] = Q[QA + 3 * l + jj];
+        ym[l] = Q[QYM + l];
+        xm[l] = Q[QXM + l];
+        ut[l] = Q[QUT + l];
+    }
+    const T cmi = Q[QCM + ii], tth = tauM * th, tr = tauM / rho;
+    D[0][0] = T(0);
+    for (int l = 0; l < 3; ++l) D[0][1 + l] = fmp * (-tauM * g[l]) + fcv * ((l == j) ? th : T(0));
+    for (int k = 0; k < 3; ++k) {
+        D[1 + k][0] = fmp * ((k == i) ? T(-1) : T(0)) + fcv * (tauM * Acol[k]);
+        for (int l = 0; l < 3; ++l) {
+            const T mp = ((l == i) ? ym[k] : T(0)) + ((k == l) ? cmi : T(0)) + xm[k] * g[l];
+            D[1 + k][1 + l] = fmp * mp + fcv * ((k == j) ? tth * ut[l] : T(0)) + fcc * ((k == l) ? tr : T(0));
+        }
+    }
+    for (int k = 0; k < 4; ++k)
+        for (int l = 0; l < 4; ++l) D[k][l] *= W;
+}
+
 // split x into three bf16 terms with x ~= h + m + l
 __device__ inline void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l) {
     h = (__bf16)x;
@@ -271,19 +304,25 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
             if (p < np) {
                 double xi[3];
                 point_xw<SUB>(a, item, base + p, hd, xi, w);
-                for (int v = 0; v < 8; ++v) {
-                    const T c = hang ? sC[v][s] : (v == s ? T(1) : T(0));
+                // vertex v of the constrained slot s: v = s without hanging
+                // corners, else every v with C[v][s] != 0
+                const T xt[3] = {(T)xi[0], (T)xi[1], (T)xi[2]};
+                const T hg = T(0.5) * (T)two_over_h;
+                const int v0 = hang ? 0 : s, v1 = hang ? 8 : s + 1;
+#pragma unroll 1
+                for (int v = v0; v < v1; ++v) {
+                    const T c = hang ? sC[v][s] : T(1);
                     if (c == T(0)) continue;
-                    double f[3], g[3];
+                    T f[3], g[3];
                     for (int k = 0; k < 3; ++k) {
-                        const double sg = ((v >> k) & 1) ? 1.0 : -1.0;
-                        f[k] = 0.5 * (1.0 + sg * xi[k]);
-                        g[k] = 0.5 * sg * two_over_h;
+                        const bool up = (v >> k) & 1;
+                        f[k] = T(0.5) * (up ? T(1) + xt[k] : T(1) - xt[k]);
+                        g[k] = up ? hg : -hg;
                     }
-                    b[0] += c * (T)(f[0] * f[1] * f[2]);
-                    b[1] += c * (T)(g[0] * f[1] * f[2]);
-                    b[2] += c * (T)(f[0] * g[1] * f[2]);
-                    b[3] += c * (T)(f[0] * f[1] * g[2]);
+                    b[0] += c * (f[0] * f[1] * f[2]);
+                    b[1] += c * (g[0] * f[1] * f[2]);
+                    b[2] += c * (f[0] * g[1] * f[2]);
+                    b[3] += c * (f[0] * f[1] * g[2]);
                 }
             }
             for (int k = 0; k < 4; ++k) SB(p, k, s) = b[k];
@@ -382,15 +421,31 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
         }
         __syncthreads();
         if (MAT) {
-            // ---- phase 4: D blocks (one (p, i, j) block per task), weight folded in
-            for (int bidx = lane; bidx < CP * 16; bidx += 64) {
-                const int p = bidx >> 4, i = (bidx >> 2) & 3, j = bidx & 3;
-                T D[4][4];
-                if (p < np) {
-                    dblock<T>(sQ[p], i, j, rho, mu, th, D);
+            // ---- phase 4: D blocks (one (p, i, j) block per task), weight folded in.
+            // Tasks are ordered by kind so that the lanes of a pass share a code
+            // path: the 9 momentum/velocity blocks of every point first, then the
+            // 7 simple blocks of every point.
+            for (int t = lane; t < CP * 16; t += 64) {
+                int p, i, j;
+                const bool mv = t < 9 * CP;
+                if (mv) {
+                    p = t / 9;
+                    i = (t % 9) / 3;
+                    j = t % 3;
                 } else {
+                    const int u = t - 9 * CP, r = u % 7;
+                    p = u / 7;
+                    i = r < 3 ? r : 3;
+                    j = r < 3 ? 3 : (r < 6 ? r - 3 : 3);
+                }
+                T D[4][4];
+                if (p >= np) {
                     for (int k = 0; k < 4; ++k)
                         for (int l = 0; l < 4; ++l) D[k][l] = T(0);
+                } else if (mv) {
+                    dblock<T>(sQ[p], i, j, rho, mu, th, D);
+                } else {
+                    dblock_simple<T>(sQ[p], i, j, rho, th, D);
                 }
                 for (int k = 0; k < 4; ++k)
                     for (int l = 0; l < 4; ++l) SD(p, i, j, k, l) = D[k][l];
