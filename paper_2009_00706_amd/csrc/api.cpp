@@ -223,8 +223,8 @@ struct vms_ctx {
     // sub-cell items) and, per CSR block, the list of record blocks summed into it
     int64_t n_slots = 0, n_blocks = 0;
     void *d_em = nullptr;
-    int64_t *d_cb_off = nullptr, *d_nrow_ptr = nullptr;
-    int32_t *d_contrib = nullptr, *d_blk_row = nullptr;
+    int64_t *d_cb_off = nullptr, *d_vbase = nullptr;
+    int32_t *d_contrib = nullptr, *d_vstride = nullptr;
     unsigned long long *d_counters = nullptr;  // 0: labelled points, 1: degenerate directions
     unsigned int *d_flag = nullptr;            // device-side overflow flag
     double *d_norm = nullptr;
@@ -431,13 +431,21 @@ static int build_gather(vms_ctx *c, const std::vector<int32_t> &stdl) {
                     contrib[pos[m.nrow_ptr[ms] + m.el_kk[64 * e + 8 * s + t]]++] = (int32_t)(sl * 64 + 8 * s + t);
         }
     }
-    std::vector<int32_t> blk_row(c->n_blocks);
-    for (int64_t n = 0; n < m.n_nodes; ++n)
-        for (int64_t b = m.nrow_ptr[n]; b < m.nrow_ptr[n + 1]; ++b) blk_row[b] = (int32_t)n;
+    // CSR place of entry (i, j) of block b in node row n: 16 nrow_ptr[n] + 4 (b - nrow_ptr[n])
+    // + i 4 deg(n) + j
+    std::vector<int64_t> vbase(c->n_blocks);
+    std::vector<int32_t> vstride(c->n_blocks);
+    for (int64_t n = 0; n < m.n_nodes; ++n) {
+        const int64_t b0 = m.nrow_ptr[n], deg = m.nrow_ptr[n + 1] - b0;
+        for (int64_t b = b0; b < m.nrow_ptr[n + 1]; ++b) {
+            vbase[b] = 16 * b0 + 4 * (b - b0);
+            vstride[b] = (int32_t)(4 * deg);
+        }
+    }
     const size_t esz = c->prm.precision == VMS_FP64 ? 8 : 4;
     char *em = nullptr;
     if (upload(c, &c->d_cb_off, off) || upload(c, &c->d_contrib, contrib) ||
-        upload(c, &c->d_blk_row, blk_row) || upload(c, &c->d_nrow_ptr, m.nrow_ptr) ||
+        upload(c, &c->d_vbase, vbase) || upload(c, &c->d_vstride, vstride) ||
         c->buf.alloc(&em, (size_t)std::max<int64_t>(c->n_slots, 1) * 1024 * esz))
         return fail(c, VMS_ENOMEM, "device allocation failed (element-matrix records)");
     c->d_em = em;
@@ -447,12 +455,12 @@ static int build_gather(vms_ctx *c, const std::vector<int32_t> &stdl) {
 // CSR values = sums of the element-matrix records, then identity blocks
 static void gather_csr(vms_ctx *c, hipStream_t st, void *vals) {
     if (c->prm.precision == VMS_FP64) {
-        vmsk::launch_gather_f64(st, (const double *)c->d_em, c->d_cb_off, c->d_contrib, c->d_blk_row,
-                                c->d_nrow_ptr, c->n_blocks, (double *)vals);
+        vmsk::launch_gather_f64(st, (const double *)c->d_em, c->d_cb_off, c->d_contrib, c->d_vbase,
+                                c->d_vstride, c->n_blocks, (double *)vals);
         vmsk::launch_set_ones_f64(st, (double *)vals, c->d_ones, c->n_ones);
     } else {
-        vmsk::launch_gather_f32(st, (const float *)c->d_em, c->d_cb_off, c->d_contrib, c->d_blk_row,
-                                c->d_nrow_ptr, c->n_blocks, (float *)vals);
+        vmsk::launch_gather_f32(st, (const float *)c->d_em, c->d_cb_off, c->d_contrib, c->d_vbase,
+                                c->d_vstride, c->n_blocks, (float *)vals);
         vmsk::launch_set_ones_f32(st, (float *)vals, c->d_ones, c->n_ones);
     }
 }

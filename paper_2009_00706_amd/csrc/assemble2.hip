@@ -655,46 +655,52 @@ void launch_assemble_batch(hipStream_t s, int precision, const AsmArgs *std_args
                            n_units, counter);
 }
 
-// CSR values from the element-matrix records: thread (block B, entry e) sums
-// the entry over B's contributions in list order (ascending record), then
-// writes it at its place in the CSR (node row n, block kk within the row:
-// dof row 4 n + i, value 16 nrow_ptr[n] + i 4 deg(n) + 4 kk + j).
-template <typename T>
+// CSR values from the element-matrix records. A thread takes V consecutive
+// entries of one row of a CSR block B (entries e0 .. e0+V-1, e = 4 i + j) and
+// sums them over B's contributions in list order (ascending record), fetching
+// the record entries V at a time and four contributions at a time; the CSR
+// place of entry (i, j) is vbase[B] + i vstride[B] + j.
+template <typename T, int V>
 __global__ void k_gather(const T *em, const int64_t *cb_off, const int32_t *contrib,
-                         const int32_t *blk_row, const int64_t *nrow_ptr, int64_t nb, T *vals) {
+                         const int64_t *vbase, const int32_t *vstride, int64_t nb, T *vals) {
+    typedef T vec __attribute__((ext_vector_type(V)));
+    constexpr int TPB = 16 / V;  // threads per block
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t B = g >> 4;
+    const int64_t B = g / TPB;
     if (B >= nb) return;
-    const int e = (int)(g & 15);
-    // contributions fetched four at a time (independent loads), summed in list order
+    const int e0 = (int)(g % TPB) * V;
     const int64_t c0 = cb_off[B], c1 = cb_off[B + 1];
-    double s = 0.0;
+    const int64_t base = vbase[B];
+    const int stride = vstride[B];
+    double s[V];
+    for (int q = 0; q < V; ++q) s[q] = 0.0;
     for (int64_t c = c0; c < c1; c += 4) {
         int32_t r[4];
         for (int u = 0; u < 4; ++u) r[u] = c + u < c1 ? contrib[c + u] : -1;
-        double v[4];
-        for (int u = 0; u < 4; ++u) v[u] = r[u] >= 0 ? (double)em[(int64_t)r[u] * 16 + e] : 0.0;
+        vec v[4];
         for (int u = 0; u < 4; ++u)
-            if (r[u] >= 0) s += v[u];
+            if (r[u] >= 0) v[u] = *(const vec *)(em + (int64_t)r[u] * 16 + e0);
+        for (int u = 0; u < 4; ++u)
+            if (r[u] >= 0)
+                for (int q = 0; q < V; ++q) s[q] += (double)v[u][q];
     }
-    const int n = blk_row[B];
-    const int64_t b0 = nrow_ptr[n], deg = nrow_ptr[n + 1] - b0;
-    vals[16 * b0 + (int64_t)(e >> 2) * 4 * deg + 4 * (B - b0) + (e & 3)] = (T)s;
+    T *dst = vals + base + (int64_t)(e0 >> 2) * stride + (e0 & 3);
+    for (int q = 0; q < V; ++q) dst[q] = (T)s[q];
 }
 
 void launch_gather_f64(hipStream_t s, const double *em, const int64_t *cb_off, const int32_t *contrib,
-                       const int32_t *blk_row, const int64_t *nrow_ptr, int64_t nb, double *vals) {
+                       const int64_t *vbase, const int32_t *vstride, int64_t nb, double *vals) {
     if (nb <= 0) return;
-    const int64_t n = 16 * nb;
-    hipLaunchKernelGGL(k_gather<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, em, cb_off,
-                       contrib, blk_row, nrow_ptr, nb, vals);
+    const int64_t n = 8 * nb;
+    hipLaunchKernelGGL((k_gather<double, 2>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, em,
+                       cb_off, contrib, vbase, vstride, nb, vals);
 }
 void launch_gather_f32(hipStream_t s, const float *em, const int64_t *cb_off, const int32_t *contrib,
-                       const int32_t *blk_row, const int64_t *nrow_ptr, int64_t nb, float *vals) {
+                       const int64_t *vbase, const int32_t *vstride, int64_t nb, float *vals) {
     if (nb <= 0) return;
-    const int64_t n = 16 * nb;
-    hipLaunchKernelGGL(k_gather<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, em, cb_off,
-                       contrib, blk_row, nrow_ptr, nb, vals);
+    const int64_t n = 4 * nb;
+    hipLaunchKernelGGL((k_gather<float, 4>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, em,
+                       cb_off, contrib, vbase, vstride, nb, vals);
 }
 
 void launch_assemble_f64(hipStream_t s, const AsmArgs &a, bool sub, bool mat) {

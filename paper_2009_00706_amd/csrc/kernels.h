@@ -109,9 +109,9 @@ void launch_assemble_mixed(hipStream_t s, const AsmArgs &a, bool sub, bool mat, 
 
 // CSR values from element-matrix records (see k_gather)
 void launch_gather_f64(hipStream_t s, const double *em, const int64_t *cb_off, const int32_t *contrib,
-                       const int32_t *blk_row, const int64_t *nrow_ptr, int64_t nb, double *vals);
+                       const int64_t *vbase, const int32_t *vstride, int64_t nb, double *vals);
 void launch_gather_f32(hipStream_t s, const float *em, const int64_t *cb_off, const int32_t *contrib,
-                       const int32_t *blk_row, const int64_t *nrow_ptr, int64_t nb, float *vals);
+                       const int64_t *vbase, const int32_t *vstride, int64_t nb, float *vals);
 void launch_fill_f64(hipStream_t s, double *p, int64_t n, double v);
 void launch_fill_f32(hipStream_t s, float *p, int64_t n, float v);
 void launch_set_ones_f64(hipStream_t s, double *vals, const int64_t *idx, int64_t n);
