@@ -35,9 +35,6 @@
 namespace vmsk {
 using namespace vmsd;
 
-#ifndef VMS_CP64
-#define VMS_CP64 8
-#endif
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -208,7 +205,6 @@ __device__ inline void split2h(float x, _Float16 &h, _Float16 &l) {
     l = (_Float16)(x - (float)h);
 }
 
-// CP points per chunk (FP64: 4, mixed: 8 = one MFMA k-step of 32)
 // LDS of one work item. Arrays are flat with padded strides so that the
 // accesses of the phases below spread over the banks (64-bit accesses by 16
 // lanes and 32-bit accesses by 32 lanes touch distinct banks):
@@ -221,16 +217,21 @@ constexpr int LU = 9, LB = 40, LI = 35, LDB = 17, LDP = 16 * LDB + 4;
 // (test component i, trial component j), padded strides; EMS_SIZE entries
 #define EMS(av, b, e) ((av) * 164 + (b) * 20 + (e))
 constexpr int EMS_SIZE = 7 * 164 + 7 * 20 + 16;
-template <typename T, int CP>
+// half-record staging (test components i = 2h, 2h + 1; e' = 4 (i & 1) + j)
+#define EMH(av, b, e) ((av) * 84 + (b) * 10 + (e))
+constexpr int EMH_SIZE = 7 * 84 + 7 * 10 + 8;
+// PD = points whose D blocks are held at once (FP64: 4, mixed: 8)
+template <typename T, int PD>
 struct Smem {
+    static constexpr int CP = 8;
     T sU[7 * LU];
     T sC[8][8];
     T sB[CP * LB];
     T sQ[CP][NQ2];
     union {  // the interpolated fields are dead once the point quantities exist
         T sI[CP * LI];
-        T sD[CP * LDP];  // weight folded in
-        T sE[EMS_SIZE];  // element-matrix staging after the last chunk
+        T sD[PD * LDP];  // weight folded in
+        T sE[PD == 8 ? EMS_SIZE : EMH_SIZE];  // element-matrix staging after the last chunk
     };
     T sSc[CP];       // fp16 form: per-point power-of-two balance
     int sM[8];
@@ -243,10 +244,11 @@ struct Smem {
 
 // One work item (an element, or a run of sub-cell points of one element) by
 // one 64-lane workgroup.
-template <typename T, int MODE, bool SUB, bool MAT, int CP>
-__device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) {
-    static_assert(MODE == 0 || CP == 8, "the mixed forms take 8 points per MFMA k-step");
-    static_assert(CP >= 1 && CP <= 8, "at most 8 points per chunk (one lane group of 8 per point)");
+template <typename T, int MODE, bool SUB, bool MAT, int PD>
+__device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, PD> &sm) {
+    constexpr int CP = 8;  // points per chunk (one lane group of 8 per point)
+    static_assert(MODE == 0 || PD == 8, "the mixed forms take 8 points per MFMA k-step");
+    static_assert(PD == 4 || PD == 8, "D blocks of 4 or 8 points at a time");
     auto &sU = sm.sU;
     auto &sC = sm.sC;
     auto &sB = sm.sB;
@@ -421,31 +423,35 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
         }
         __syncthreads();
         if (MAT) {
+            // ---- phases 4 and 5 over batches of PD points
+            for (int pb = 0; pb < np; pb += PD) {
+            const int nd = min(PD, np - pb);
+            if (pb > 0) __syncthreads();  // the previous batch is done with the D blocks
             // ---- phase 4: D blocks (one (p, i, j) block per task), weight folded in.
             // Tasks are ordered by kind so that the lanes of a pass share a code
             // path: the 9 momentum/velocity blocks of every point first, then the
             // 7 simple blocks of every point.
-            for (int t = lane; t < CP * 16; t += 64) {
+            for (int t = lane; t < PD * 16; t += 64) {
                 int p, i, j;
-                const bool mv = t < 9 * CP;
+                const bool mv = t < 9 * PD;
                 if (mv) {
                     p = t / 9;
                     i = (t % 9) / 3;
                     j = t % 3;
                 } else {
-                    const int u = t - 9 * CP, r = u % 7;
+                    const int u = t - 9 * PD, r = u % 7;
                     p = u / 7;
                     i = r < 3 ? r : 3;
                     j = r < 3 ? 3 : (r < 6 ? r - 3 : 3);
                 }
                 T D[4][4];
-                if (p >= np) {
+                if (p >= nd) {
                     for (int k = 0; k < 4; ++k)
                         for (int l = 0; l < 4; ++l) D[k][l] = T(0);
                 } else if (mv) {
-                    dblock<T>(sQ[p], i, j, rho, mu, th, D);
+                    dblock<T>(sQ[pb + p], i, j, rho, mu, th, D);
                 } else {
-                    dblock_simple<T>(sQ[p], i, j, rho, th, D);
+                    dblock_simple<T>(sQ[pb + p], i, j, rho, th, D);
                 }
                 for (int k = 0; k < 4; ++k)
                     for (int l = 0; l < 4; ++l) SD(p, i, j, k, l) = D[k][l];
@@ -455,11 +461,11 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
             const int col = lane & 15, bb = col >> 2, jc = col & 3;
             if (MODE == 0) {
                 const int k = lane >> 4, arow = lane & 15;
-                for (int p = 0; p < np; ++p) {
-                    const double A = arow < 8 ? (double)SB(p, k, arow) : 0.0;
+                for (int p = 0; p < nd; ++p) {
+                    const double A = arow < 8 ? (double)SB(pb + p, k, arow) : 0.0;
                     double Bv[2][4];
                     for (int bh = 0; bh < 2; ++bh)
-                        for (int m = 0; m < 4; ++m) Bv[bh][m] = (double)SB(p, m, 4 * bh + bb);
+                        for (int m = 0; m < 4; ++m) Bv[bh][m] = (double)SB(pb + p, m, 4 * bh + bb);
                     for (int i = 0; i < 4; ++i) {
                         double Dv[4];
                         for (int m = 0; m < 4; ++m) Dv[m] = (double)SD(p, i, jc, k, m);
@@ -553,6 +559,7 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
                     }
                 }
             }
+            }  // batches of PD points
         }
         // residual: lanes < 32, (a = lane & 7, i = lane >> 3)
         if (lane < 32) {
@@ -570,16 +577,26 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
     if (MAT) {
         T *stage = sm.sE;  // shares the D area, free after the last chunk
         const int col = lane & 15, bb = col >> 2, jc = col & 3;
-        __syncthreads();
+        T *dst = (T *)a.em + (a.slot0 + item) * 1024;
         if (MODE == 0) {
-            for (int t = 0; t < 8; ++t) {
-                const int i = t >> 1, b = 4 * (t & 1) + bb;
-                for (int r = 0; r < 2; ++r) {
-                    const int av = 4 * r + (lane >> 4);  // output row = 4 r + lane / 16
-                    stage[EMS(av, b, 4 * i + jc)] = (T)accd[t][r];
+            // two halves of the record: test components i = 2h, 2h + 1
+            for (int h = 0; h < 2; ++h) {
+                __syncthreads();
+                for (int t = 4 * h; t < 4 * h + 4; ++t) {
+                    const int i = t >> 1, b = 4 * (t & 1) + bb;
+                    for (int r = 0; r < 2; ++r) {
+                        const int av = 4 * r + (lane >> 4);  // output row = 4 r + lane / 16
+                        stage[EMH(av, b, 4 * (i & 1) + jc)] = (T)accd[t][r];
+                    }
+                }
+                __syncthreads();
+                for (int v = lane; v < 512; v += 64) {
+                    const int blk = v >> 3, e = v & 7;
+                    dst[blk * 16 + 8 * h + e] = stage[EMH(blk >> 3, blk & 7, e)];
                 }
             }
         } else {
+            __syncthreads();
             // rows 8..15 carry the second split term: fold them onto rows 0..7
             for (int t = 0; t < 8; ++t) {
                 v4f v = accf[t];
@@ -591,10 +608,9 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
                     stage[EMS(av, b, 4 * i + jc)] = (T)v[r];
                 }
             }
+            __syncthreads();
+            for (int v = lane; v < 1024; v += 64) dst[v] = stage[EMS(v >> 7, (v >> 4) & 7, v & 15)];
         }
-        __syncthreads();
-        T *dst = (T *)a.em + (a.slot0 + item) * 1024;
-        for (int v = lane; v < 1024; v += 64) dst[v] = stage[EMS(v >> 7, (v >> 4) & 7, v & 15)];
     }
     if (lane < 32 && a.resid) {
         const int av = lane & 7, i = lane >> 3;
@@ -602,20 +618,31 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, CP> &sm) 
     }
 }
 
-template <typename T, int MODE, bool SUB, bool MAT, int CP>
-__global__ __launch_bounds__(64) void k_asm2(AsmArgs a) {
-    __shared__ Smem<T, CP> sm;
-    asm_item<T, MODE, SUB, MAT, CP>(a, blockIdx.x, sm);
+// waves per SIMD the register allocation aims for: the LDS of one item
+// allows 8 (FP64) or 11 (mixed) one-wave workgroups per CU (4 SIMDs)
+#ifndef VMS_WPE64
+#define VMS_WPE64 2
+#endif
+#ifndef VMS_WPEMX
+#define VMS_WPEMX 3
+#endif
+#define VMS_ASM_BOUNDS(MODE) \
+    __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((MODE) == 0 ? VMS_WPE64 : VMS_WPEMX, 8)))
+
+template <typename T, int MODE, bool SUB, bool MAT>
+__global__ VMS_ASM_BOUNDS(MODE) void k_asm2(AsmArgs a) {
+    __shared__ Smem<T, MODE == 0 ? 4 : 8> sm;
+    asm_item<T, MODE, SUB, MAT, MODE == 0 ? 4 : 8>(a, blockIdx.x, sm);
 }
 
 // Persistent form over many contexts: every workgroup takes units from a
 // device counter until none is left (each unit: a run of OUT elements or of
 // sub-cell work items of one tree).
-template <typename T, int MODE, int CP>
-__global__ __launch_bounds__(64) void k_asm_batch(const AsmArgs *std_args, const AsmArgs *sub_args,
+template <typename T, int MODE>
+__global__ VMS_ASM_BOUNDS(MODE) void k_asm_batch(const AsmArgs *std_args, const AsmArgs *sub_args,
                                                   const BatchUnit *units, int64_t n_units,
                                                   unsigned long long *counter) {
-    __shared__ Smem<T, CP> sm;
+    __shared__ Smem<T, MODE == 0 ? 4 : 8> sm;
     __shared__ int64_t su;
     for (;;) {
         __syncthreads();
@@ -626,10 +653,10 @@ __global__ __launch_bounds__(64) void k_asm_batch(const AsmArgs *std_args, const
         const BatchUnit U = units[u];
         if (U.sub) {
             const AsmArgs a = sub_args[U.tree];
-            for (int k = 0; k < U.count; ++k) asm_item<T, MODE, true, true, CP>(a, U.first + k, sm);
+            for (int k = 0; k < U.count; ++k) asm_item<T, MODE, true, true, MODE == 0 ? 4 : 8>(a, U.first + k, sm);
         } else {
             const AsmArgs a = std_args[U.tree];
-            for (int k = 0; k < U.count; ++k) asm_item<T, MODE, false, true, CP>(a, U.first + k, sm);
+            for (int k = 0; k < U.count; ++k) asm_item<T, MODE, false, true, MODE == 0 ? 4 : 8>(a, U.first + k, sm);
         }
     }
 }
@@ -645,13 +672,13 @@ void launch_assemble_batch(hipStream_t s, int precision, const AsmArgs *std_args
     if (n_units <= 0) return;
     dim3 grid((unsigned)n_groups), block(64);
     if (precision == 0)
-        hipLaunchKernelGGL((k_asm_batch<double, 0, VMS_CP64>), grid, block, 0, s, std_args, sub_args,
+        hipLaunchKernelGGL((k_asm_batch<double, 0>), grid, block, 0, s, std_args, sub_args,
                            units, n_units, counter);
     else if (precision == 1)
-        hipLaunchKernelGGL((k_asm_batch<float, 1, 8>), grid, block, 0, s, std_args, sub_args, units,
+        hipLaunchKernelGGL((k_asm_batch<float, 1>), grid, block, 0, s, std_args, sub_args, units,
                            n_units, counter);
     else
-        hipLaunchKernelGGL((k_asm_batch<float, 2, 8>), grid, block, 0, s, std_args, sub_args, units,
+        hipLaunchKernelGGL((k_asm_batch<float, 2>), grid, block, 0, s, std_args, sub_args, units,
                            n_units, counter);
 }
 
@@ -707,11 +734,11 @@ void launch_assemble_f64(hipStream_t s, const AsmArgs &a, bool sub, bool mat) {
     if (a.n_items <= 0) return;
     dim3 grid((unsigned)a.n_items), block(64);
     if (!sub) {
-        if (mat) hipLaunchKernelGGL((k_asm2<double, 0, false, true, VMS_CP64>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_asm2<double, 0, false, false, VMS_CP64>), grid, block, 0, s, a);
+        if (mat) hipLaunchKernelGGL((k_asm2<double, 0, false, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_asm2<double, 0, false, false>), grid, block, 0, s, a);
     } else {
-        if (mat) hipLaunchKernelGGL((k_asm2<double, 0, true, true, VMS_CP64>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_asm2<double, 0, true, false, VMS_CP64>), grid, block, 0, s, a);
+        if (mat) hipLaunchKernelGGL((k_asm2<double, 0, true, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_asm2<double, 0, true, false>), grid, block, 0, s, a);
     }
 }
 
@@ -721,11 +748,11 @@ void launch_assemble_mixed(hipStream_t s, const AsmArgs &a, bool sub, bool mat, 
 #define VMS_L(MODE)                                                                              \
     do {                                                                                         \
         if (!sub) {                                                                              \
-            if (mat) hipLaunchKernelGGL((k_asm2<float, MODE, false, true, 8>), grid, block, 0, s, a); \
-            else hipLaunchKernelGGL((k_asm2<float, MODE, false, false, 8>), grid, block, 0, s, a);    \
+            if (mat) hipLaunchKernelGGL((k_asm2<float, MODE, false, true>), grid, block, 0, s, a); \
+            else hipLaunchKernelGGL((k_asm2<float, MODE, false, false>), grid, block, 0, s, a);    \
         } else {                                                                                 \
-            if (mat) hipLaunchKernelGGL((k_asm2<float, MODE, true, true, 8>), grid, block, 0, s, a);  \
-            else hipLaunchKernelGGL((k_asm2<float, MODE, true, false, 8>), grid, block, 0, s, a);     \
+            if (mat) hipLaunchKernelGGL((k_asm2<float, MODE, true, true>), grid, block, 0, s, a);  \
+            else hipLaunchKernelGGL((k_asm2<float, MODE, true, false>), grid, block, 0, s, a);     \
         }                                                                                        \
     } while (0)
     if (fp16) VMS_L(2);
