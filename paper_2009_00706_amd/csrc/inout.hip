@@ -87,19 +87,54 @@ void launch_point_labels_list(hipStream_t s, const SurfDev &S, const int64_t *id
 // Adaptive sub-cell quadrature: one 64-lane workgroup per INTERCEPTED element
 // ---------------------------------------------------------------------------
 
-constexpr int SQ_MAXCELL = 512;   // cells of one level at depth <= 3
-constexpr int SQ_MAXKEEP = 4096;  // 8 * 8^3 points
+constexpr int SQ_MAXCELL = 512;  // cells of one level at depth <= 3
+constexpr int SQ_KEYS = 4096;    // key space 8^(D+1) at depth 3
+constexpr int SQ_BTMAX = 64;     // background triangles staged in LDS
 
+// Exact label of P by local segments to the element corners V, with the
+// element's background triangles read from LDS (tv: 9 doubles, tb: box).
+__device__ static int local_label_lds(const SurfDev &S, const double *P, const double (*V)[3],
+                                      const uint8_t *vlab, const double (*tv)[9],
+                                      const double (*tb)[6], int nbt, unsigned long long *ndeg) {
+    for (int v = 0; v < 8; ++v) {
+        int cnt = 0;
+        bool deg = false;
+        const double *Q = V[v];
+        for (int i = 0; i < nbt; ++i) {
+            const double *bx = tb[i];
+            bool miss = false;
+            for (int k = 0; k < 3; ++k) {
+                const double lo = fmin(P[k], Q[k]), hi = fmax(P[k], Q[k]);
+                if (hi < bx[k] || lo > bx[3 + k]) miss = true;
+            }
+            if (miss) continue;
+            const int r = segment_triangle(P, Q, tv[i], tv[i] + 3, tv[i] + 6);
+            if (r == SEG_ON) return 1;
+            if (r == SEG_DEGEN) deg = true;
+            else cnt ^= r;
+        }
+        if (!deg) return vlab[v] ^ cnt;
+        if (ndeg) atomicAdd(ndeg, 1ull);
+    }
+    return ray_label(S, P, ndeg);
+}
+
+// One 64-lane workgroup per INTERCEPTED element. Sub-cells are split level by
+// level; a kept point sets the bit of its key (and records its level) in a
+// bitmap over the key space, so that the canonical (ascending key) position
+// of every kept point is the number of set bits below it: no sort is needed.
 __global__ __launch_bounds__(64) void k_subquad(SurfDev S, GeoArgs g, SubqArgs a, int pass) {
-    __shared__ uint32_t cells[2][SQ_MAXCELL];   // path digits, level 1 most significant
-    __shared__ uint32_t keep[SQ_MAXKEEP];       // key << 2 | level
-    __shared__ int ncell[2], nkeep;
+    __shared__ uint32_t cells[2][SQ_MAXCELL];  // path digits, level 1 most significant
+    __shared__ unsigned long long kbits[SQ_KEYS / 64];
+    __shared__ uint32_t klev[SQ_KEYS / 16];    // 2 bits per key
+    __shared__ int ncell[2];
     __shared__ double V[8][3];
     __shared__ uint8_t vl[8];
+    __shared__ double tv[SQ_BTMAX][9];
+    __shared__ double tb[SQ_BTMAX][6];
     const int lane = threadIdx.x;
     const int64_t i = blockIdx.x;
     if (i >= a.n) return;
-    const int e = a.el[i];
     const int D = g.depth;
     const int M = g.max_level;
     const int F = M + D;
@@ -113,13 +148,21 @@ __global__ __launch_bounds__(64) void k_subquad(SurfDev S, GeoArgs g, SubqArgs a
         vl[lane] = a.corner_lab[8 * i + lane];
     }
     if (lane == 0) {
-        nkeep = 0;
         ncell[0] = 0;
         ncell[1] = 0;
     }
-    __syncthreads();
+    kbits[lane] = 0ull;
+    for (int k = lane; k < SQ_KEYS / 16; k += 64) klev[k] = 0u;
     const int32_t *bt = a.bt_ids + a.bt_off[i];
     const int nbt = (int)(a.bt_off[i + 1] - a.bt_off[i]);
+    const bool staged = nbt <= SQ_BTMAX;
+    if (staged)
+        for (int t = lane; t < nbt; t += 64) {
+            const int id = bt[t];
+            for (int k = 0; k < 9; ++k) tv[t][k] = S.tv[9 * (int64_t)id + k];
+            for (int k = 0; k < 6; ++k) tb[t][k] = S.tbox[6 * (int64_t)id + k];
+        }
+    __syncthreads();
     int cur = 0;
     int lmin = 1;
     if (D == 0) {
@@ -155,7 +198,8 @@ __global__ __launch_bounds__(64) void k_subquad(SurfDev S, GeoArgs g, SubqArgs a
                 for (int ax = 0; ax < 3; ++ax)
                     P[ax] = point_coord(g.origin[ax], g.root_len, scF, A[ax], S_l,
                                         ((gp >> ax) & 1) ? VMS_GP : VMS_GM);
-                lab = local_label(S, P, V, vl, bt, nbt, a.ndeg);
+                lab = staged ? local_label_lds(S, P, V, vl, tv, tb, nbt, a.ndeg)
+                             : local_label(S, P, V, vl, bt, nbt, a.ndeg);
                 ++nlab;
             }
             // labels of the 8 points of each cell in this chunk
@@ -164,9 +208,9 @@ __global__ __launch_bounds__(64) void k_subquad(SurfDev S, GeoArgs g, SubqArgs a
             if (valid) {
                 bool leaf = (l == D) || nin == 0;
                 if (leaf && !lab) {
-                    int slot = atomicAdd(&nkeep, 1);
-                    uint32_t key = (((path << 3) | (uint32_t)gp) << (3 * (D - l)));
-                    if (slot < SQ_MAXKEEP) keep[slot] = (key << 2) | (uint32_t)l;
+                    const uint32_t key = (((path << 3) | (uint32_t)gp) << (3 * (D - l)));
+                    atomicOr(&kbits[key >> 6], 1ull << (key & 63));
+                    atomicOr(&klev[key >> 4], (uint32_t)l << (2 * (key & 15)));
                 } else if (!leaf && nin < 8 && gp == 0) {
                     int slot = atomicAdd(&ncell[nxt], 8);
                     for (int ch = 0; ch < 8; ++ch)
@@ -178,7 +222,16 @@ __global__ __launch_bounds__(64) void k_subquad(SurfDev S, GeoArgs g, SubqArgs a
         cur = nxt;
     }
     if (nlab && pass == 0) atomicAdd(a.nlabel, nlab);
-    const int nk = nkeep;
+    // kept points: set bits of the bitmap; lane w owns word w
+    const unsigned long long word = kbits[lane];
+    const int cw = __popcll(word);
+    // exclusive prefix sum of the word counts over the 64 lanes
+    int incl = cw;
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += y;
+    }
+    const int nk = __shfl(incl, 63, 64);
     if (pass == 0) {
         if (lane == 0) a.cnt[i] = nk;
         return;
@@ -187,26 +240,17 @@ __global__ __launch_bounds__(64) void k_subquad(SurfDev S, GeoArgs g, SubqArgs a
         if (lane == 0) atomicOr(a.flag, 1u);
         return;
     }
-    // bitonic sort of the kept entries (keys are unique), padded with ~0
-    int np2 = 1;
-    while (np2 < nk) np2 <<= 1;
-    for (int j = nk + lane; j < np2; j += 64) keep[j] = 0xffffffffu;
-    __syncthreads();
-    for (int k = 2; k <= np2; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = lane; t < np2; t += 64) {
-                int p = t ^ j;
-                if (p > t) {
-                    uint32_t x = keep[t], y = keep[p];
-                    bool up = (t & k) == 0;
-                    if ((x > y) == up) { keep[t] = y; keep[p] = x; }
-                }
-            }
-            __syncthreads();
-        }
+    // write the kept entries in ascending key order: (key << 2) | level
+    uint32_t *dst = a.entries + a.off[i] + (incl - cw);
+    unsigned long long wbits = word;
+    int r = 0;
+    while (wbits) {
+        const int b = __ffsll((long long)wbits) - 1;
+        wbits &= wbits - 1;
+        const uint32_t key = (uint32_t)lane * 64u + (uint32_t)b;
+        const uint32_t lv = (klev[key >> 4] >> (2 * (key & 15))) & 3u;
+        dst[r++] = (key << 2) | lv;
     }
-    uint32_t *dst = a.entries + a.off[i];
-    for (int j = lane; j < nk; j += 64) dst[j] = keep[j];
 }
 
 void launch_subquad(hipStream_t s, const SurfDev &S, const GeoArgs &g, const SubqArgs &a,
