@@ -1021,7 +1021,7 @@ struct vms_batch {
     std::vector<vmsk::AsmArgs> h_std, h_sub;
     vmsk::AsmArgs *d_std = nullptr, *d_sub = nullptr;
     vmsk::BatchUnit *d_units = nullptr;
-    int64_t n_units = 0, units_cap = 0;
+    int64_t n_units = 0, n_sub_units = 0, units_cap = 0;
     unsigned long long *d_counter = nullptr;
     DevBuf buf;
     // graph replay
@@ -1069,6 +1069,7 @@ int batch_units(vms_batch *b) {
     // sub-cell work first (heavier units), then runs of `tile` OUT elements
     for (size_t t = 0; t < b->ctx.size(); ++t)
         for (int64_t i = 0; i < b->ctx[t]->n_sub_items; ++i) u.push_back({(int32_t)t, 1, i, 1, 0});
+    b->n_sub_units = (int64_t)u.size();
     for (size_t t = 0; t < b->ctx.size(); ++t)
         for (int64_t i = 0; i < b->ctx[t]->n_std; i += b->tile)
             u.push_back({(int32_t)t, 0, i, (int32_t)std::min<int64_t>(b->tile, b->ctx[t]->n_std - i), 0});
@@ -1125,8 +1126,8 @@ void batch_enqueue(vms_batch *b, bool timed) {
         if (a.resid) vmsk::launch_fill_f64(b->stream, a.resid, 4 * b->ctx[t]->mesh.n_nodes, 0.0);
     }
     if (timed) (void)hipEventRecord(b->ev[1], b->stream);
-    vmsk::launch_assemble_batch(b->stream, b->precision, b->d_std, b->d_sub, b->d_units, b->n_units,
-                                b->d_counter, b->n_cu * b->groups_per_cu);
+    vmsk::launch_assemble_batch(b->stream, b->precision, b->d_std, b->d_sub, b->d_units, b->n_sub_units,
+                                b->n_units, b->d_counter, b->n_cu * b->groups_per_cu);
     if (timed) (void)hipEventRecord(b->ev[2], b->stream);
     for (size_t t = 0; t < b->ctx.size(); ++t) gather_csr(b->ctx[t], b->stream, b->h_std[t].vals);
     if (timed) (void)hipEventRecord(b->ev[3], b->stream);
@@ -1164,7 +1165,7 @@ int vms_batch_create(vms_batch **out, vms_ctx *const *ctxs, int n, void *stream)
     b->h_std.resize(n);
     b->h_sub.resize(n);
     if (b->buf.alloc(&b->d_std, (size_t)n) || b->buf.alloc(&b->d_sub, (size_t)n) ||
-        b->buf.alloc(&b->d_counter, 1)) {
+        b->buf.alloc(&b->d_counter, 2)) {
         delete b;
         return bfail(nullptr, VMS_ENOMEM, "device allocation failed");
     }

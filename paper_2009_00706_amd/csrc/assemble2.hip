@@ -50,7 +50,8 @@ enum {
     QY = 37, QX = 40, QCP = 43, QV0 = 46, QW0 = 49, QS9 = 52, QZ9 = 61,
     QYM = 70, QCM = 73, QXM = 76,
     QRC = 79,  // 16 residual coefficients r^i[k] (weight folded in)
-    NQ2 = 95
+    QSV = 95,  // s = (u'.grad) u
+    NQ2 = 98
 };
 
 __device__ inline const double *field_in(const AsmArgs &a, int f) {
@@ -374,35 +375,18 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, PD> &sm) 
             const T tb = upg > T(0) ? rsq<T>(upg) : T(0);
             T *q = sQ[p];
             const T W = q[QW];
+            T sv[3];
+            for (int c = 0; c < 3; ++c) sv[c] = up[0] * gu[c][0] + up[1] * gu[c][1] + up[2] * gu[c][2];
+            // (a) the point state and the residual coefficients r^i[k] (times W)
             q[QTM] = tauM;
             q[QTC] = tauC;
             q[QTB] = tb;
-            T sv[3];
-            for (int c = 0; c < 3; ++c) sv[c] = up[0] * gu[c][0] + up[1] * gu[c][1] + up[2] * gu[c][2];
-            const T tr = tauM * rho, tbtr = tb * tauM * rho, tbt = tb * tauM, tir = tauM * irho;
             for (int c = 0; c < 3; ++c) {
                 q[QUT + c] = ut[c];
                 q[QUP + c] = up[c];
-                q[QY + c] = tr * ut[c] + tauM * up[c];
-                q[QX + c] = -tbtr * up[c];
-                q[QCP + c] = tauM * up[c] - tbtr * sv[c];
-                q[QV0 + c] = th * (rho * ut[c] + up[c]);
-                q[QW0 + c] = -th * tr * ut[c];
-                q[QYM + c] = tauM * ut[c] + tir * up[c];
-                q[QCM + c] = tir * up[c] - tbt * sv[c];
-                q[QXM + c] = -tbt * up[c];
-                for (int m = 0; m < 3; ++m) {
-                    const T Acm = (c == m ? idt : T(0)) + th * gu[c][m];
-                    q[QA + 3 * c + m] = Acm;
-                    q[QG + 3 * c + m] = gu[c][m];
-                    T v = T(0);
-                    for (int k = 0; k < 3; ++k) v += gu[c][k] * ((k == m ? idt : T(0)) + th * gu[k][m]);
-                    q[QGA + 3 * c + m] = v;
-                    q[QS9 + 3 * c + m] = th * (tr * ut[c] * ut[m] + tauM * up[c] * ut[m] + tb * up[c] * up[m]);
-                    q[QZ9 + 3 * c + m] = -tbtr * th * up[c] * ut[m];
-                }
+                q[QSV + c] = sv[c];
+                for (int m = 0; m < 3; ++m) q[QG + 3 * c + m] = gu[c][m];
             }
-            // residual coefficients r^i[k] (times W)
             for (int c = 0; c < 3; ++c) {
                 q[QRC + 4 * c] = W * (rho * at[c] + rho * conv[c] + sv[c]);
                 for (int k = 0; k < 3; ++k)
@@ -412,10 +396,44 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, PD> &sm) 
             }
             q[QRC + 12] = W * div;
             for (int k = 0; k < 3; ++k) q[QRC + 13 + k] = -W * up[k] * irho;
+        }
+        // (b) the factors of the D blocks, from the stored point state: the
+        // round trip through LDS bounds the registers the point phase holds
+        __asm__ volatile("" ::: "memory");
+        if (lane < np) {
+            const int p = lane;
+            T *q = sQ[p];
+            T ut[3], up[3], sv[3], gu[3][3];
+            for (int c = 0; c < 3; ++c) {
+                ut[c] = q[QUT + c];
+                up[c] = q[QUP + c];
+                sv[c] = q[QSV + c];
+                for (int m = 0; m < 3; ++m) gu[c][m] = q[QG + 3 * c + m];
+            }
+            const T tauM = q[QTM], tb = q[QTB];
+            const T tr = tauM * rho, tbtr = tb * tauM * rho, tbt = tb * tauM, tir = tauM * irho;
+            for (int c = 0; c < 3; ++c) {
+                q[QY + c] = tr * ut[c] + tauM * up[c];
+                q[QX + c] = -tbtr * up[c];
+                q[QCP + c] = tauM * up[c] - tbtr * sv[c];
+                q[QV0 + c] = th * (rho * ut[c] + up[c]);
+                q[QW0 + c] = -th * tr * ut[c];
+                q[QYM + c] = tauM * ut[c] + tir * up[c];
+                q[QCM + c] = tir * up[c] - tbt * sv[c];
+                q[QXM + c] = -tbt * up[c];
+                for (int m = 0; m < 3; ++m) {
+                    q[QA + 3 * c + m] = (c == m ? idt : T(0)) + th * gu[c][m];
+                    T v = T(0);
+                    for (int k = 0; k < 3; ++k) v += gu[c][k] * ((k == m ? idt : T(0)) + th * gu[k][m]);
+                    q[QGA + 3 * c + m] = v;
+                    q[QS9 + 3 * c + m] = th * (tr * ut[c] * ut[m] + tauM * up[c] * ut[m] + tb * up[c] * up[m]);
+                    q[QZ9 + 3 * c + m] = -tbtr * th * up[c] * ut[m];
+                }
+            }
             if (MODE == 2) {
                 // balance a power of two between the two fp16 operands: a product is
                 // about W (2/h)^2 100 (mass coefficient rho/dt ~ 100 for the workloads)
-                const float x = (float)((double)W * 4.0 / (hd * hd) * 100.0);
+                const float x = (float)((double)q[QW] * 4.0 / (hd * hd) * 100.0);
                 int ex;
                 frexpf(x, &ex);
                 sSc[p] = ldexpf(1.0f, ex / 2);
@@ -461,6 +479,7 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, PD> &sm) 
             const int col = lane & 15, bb = col >> 2, jc = col & 3;
             if (MODE == 0) {
                 const int k = lane >> 4, arow = lane & 15;
+#pragma unroll 1
                 for (int p = 0; p < nd; ++p) {
                     const double A = arow < 8 ? (double)SB(pb + p, k, arow) : 0.0;
                     double Bv[2][4];
@@ -636,50 +655,49 @@ __global__ VMS_ASM_BOUNDS(MODE) void k_asm2(AsmArgs a) {
 }
 
 // Persistent form over many contexts: every workgroup takes units from a
-// device counter until none is left (each unit: a run of OUT elements or of
-// sub-cell work items of one tree).
-template <typename T, int MODE>
-__global__ VMS_ASM_BOUNDS(MODE) void k_asm_batch(const AsmArgs *std_args, const AsmArgs *sub_args,
-                                                  const BatchUnit *units, int64_t n_units,
-                                                  unsigned long long *counter) {
+// device counter until none is left; one launch per kind of unit (runs of OUT
+// elements, or sub-cell work items), each unit from one tree. Units
+// [first, last) of the list are this launch's.
+template <typename T, int MODE, bool SUB>
+__global__ VMS_ASM_BOUNDS(MODE) void k_asm_batch(const AsmArgs *args, const BatchUnit *units,
+                                                 int64_t first, int64_t last,
+                                                 unsigned long long *counter) {
     __shared__ Smem<T, MODE == 0 ? 4 : 8> sm;
     __shared__ int64_t su;
     for (;;) {
         __syncthreads();
-        if (threadIdx.x == 0) su = (int64_t)atomicAdd(counter, 1ull);
+        if (threadIdx.x == 0) su = first + (int64_t)atomicAdd(counter, 1ull);
         __syncthreads();
         const int64_t u = su;
-        if (u >= n_units) break;
+        if (u >= last) break;
         const BatchUnit U = units[u];
-        if (U.sub) {
-            const AsmArgs a = sub_args[U.tree];
-            for (int k = 0; k < U.count; ++k) asm_item<T, MODE, true, true, MODE == 0 ? 4 : 8>(a, U.first + k, sm);
-        } else {
-            const AsmArgs a = std_args[U.tree];
-            for (int k = 0; k < U.count; ++k) asm_item<T, MODE, false, true, MODE == 0 ? 4 : 8>(a, U.first + k, sm);
-        }
+        const AsmArgs a = args[U.tree];
+        for (int k = 0; k < U.count; ++k) asm_item<T, MODE, SUB, true, MODE == 0 ? 4 : 8>(a, U.first + k, sm);
     }
 }
 
 __global__ void k_reset_counter(unsigned long long *c) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *c = 0ull;
+    if (threadIdx.x < 2 && blockIdx.x == 0) c[threadIdx.x] = 0ull;
 }
 
 void launch_assemble_batch(hipStream_t s, int precision, const AsmArgs *std_args,
-                           const AsmArgs *sub_args, const BatchUnit *units, int64_t n_units,
-                           unsigned long long *counter, int n_groups) {
+                           const AsmArgs *sub_args, const BatchUnit *units, int64_t n_sub_units,
+                           int64_t n_units, unsigned long long *counter, int n_groups) {
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
-    if (n_units <= 0) return;
     dim3 grid((unsigned)n_groups), block(64);
-    if (precision == 0)
-        hipLaunchKernelGGL((k_asm_batch<double, 0>), grid, block, 0, s, std_args, sub_args,
-                           units, n_units, counter);
-    else if (precision == 1)
-        hipLaunchKernelGGL((k_asm_batch<float, 1>), grid, block, 0, s, std_args, sub_args, units,
-                           n_units, counter);
-    else
-        hipLaunchKernelGGL((k_asm_batch<float, 2>), grid, block, 0, s, std_args, sub_args, units,
-                           n_units, counter);
+#define VMS_B(T, MODE)                                                                           \
+    do {                                                                                         \
+        if (n_sub_units > 0)                                                                     \
+            hipLaunchKernelGGL((k_asm_batch<T, MODE, true>), grid, block, 0, s, sub_args, units, \
+                               (int64_t)0, n_sub_units, counter);                                \
+        if (n_units > n_sub_units)                                                               \
+            hipLaunchKernelGGL((k_asm_batch<T, MODE, false>), grid, block, 0, s, std_args, units, \
+                               n_sub_units, n_units, counter + 1);                               \
+    } while (0)
+    if (precision == 0) VMS_B(double, 0);
+    else if (precision == 1) VMS_B(float, 1);
+    else VMS_B(float, 2);
+#undef VMS_B
 }
 
 // CSR values from the element-matrix records. A thread takes V consecutive

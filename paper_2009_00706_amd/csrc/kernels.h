@@ -102,9 +102,11 @@ struct BatchUnit {
     int32_t count;
     int32_t pad;
 };
+// units [0, n_sub_units) are sub-cell units, the rest runs of OUT elements;
+// counter: two device counters (reset by the launch sequence)
 void launch_assemble_batch(hipStream_t s, int precision, const AsmArgs *std_args,
-                           const AsmArgs *sub_args, const BatchUnit *units, int64_t n_units,
-                           unsigned long long *counter, int n_groups);
+                           const AsmArgs *sub_args, const BatchUnit *units, int64_t n_sub_units,
+                           int64_t n_units, unsigned long long *counter, int n_groups);
 void launch_assemble_mixed(hipStream_t s, const AsmArgs &a, bool sub, bool mat, int fp16);
 
 // CSR values from element-matrix records (see k_gather)
