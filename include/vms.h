@@ -220,6 +220,11 @@ int vms_mlp_create(vms_mlp **out, const double *lo, const double *hi, const floa
                    const float *B, float trunc, void *stream);
 int vms_mlp_get_params(vms_mlp *m, float *theta /* HOST */);
 int vms_mlp_set_margin(vms_mlp *m, float margin);
+/* Per-cell margins: margins HOST float[nx*ny*nz] (x fastest) over a uniform
+ * grid of the network box; a point uses the margin of its cell (+inf: never
+ * decided by the network). nx = ny = nz = 0 removes the grid (the scalar
+ * margin applies again). VMS_EINVAL for negative or NaN margins. */
+int vms_mlp_set_margin_grid(vms_mlp *m, int nx, int ny, int nz, const float *margins);
 /* Loss and gradient over n samples (DEVICE points, DEVICE exact signed
  * distances); grad DEVICE float[12545] (nullable), loss HOST (nullable). */
 int vms_mlp_grad(vms_mlp *m, const double *px, const double *py, const double *pz, const double *sdf,

@@ -193,9 +193,6 @@ struct vms_ctx {
     int32_t *d_masters = nullptr;
     uint32_t *d_ccode = nullptr;
     uint8_t *d_hang = nullptr, *d_level = nullptr;
-    int64_t *d_rowbase = nullptr;
-    int32_t *d_rowlen = nullptr;
-    uint16_t *d_kk = nullptr;
     int64_t n_std = 0;
     int32_t *d_std = nullptr;
     // intercepted elements and their sub-cell points
@@ -649,8 +646,7 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
     c->n_ones = (int64_t)ones.size();
     if (upload(c, &c->d_masters, m.masters) || upload(c, &c->d_ccode, m.ccode) ||
         upload(c, &c->d_hang, m.has_hang) || upload(c, &c->d_level, c->level) ||
-        upload(c, &c->d_rowbase, m.el_rowbase) || upload(c, &c->d_rowlen, m.el_rowlen) ||
-        upload(c, &c->d_kk, m.el_kk) || upload(c, &c->d_std, stdl) || upload(c, &c->d_ones, ones))
+        upload(c, &c->d_std, stdl) || upload(c, &c->d_ones, ones))
         return bail(VMS_ENOMEM);
     rc = build_gather(c, stdl);
     if (rc) return bail(rc);
@@ -773,9 +769,6 @@ static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *re
     a.ccode = c->d_ccode;
     a.has_hang = c->d_hang;
     a.level = c->d_level;
-    a.rowbase = c->d_rowbase;
-    a.rowlen = c->d_rowlen;
-    a.kk = c->d_kk;
     a.depth = c->prm.quad_depth;
     for (int k = 0; k < 7; ++k) a.f[k] = fp[k];
     a.rho = c->prm.rho; a.mu = c->prm.mu; a.dt = c->prm.dt; a.theta = c->prm.theta;
@@ -1055,9 +1048,6 @@ vmsk::AsmArgs base_args(vms_ctx *c) {
     a.ccode = c->d_ccode;
     a.has_hang = c->d_hang;
     a.level = c->d_level;
-    a.rowbase = c->d_rowbase;
-    a.rowlen = c->d_rowlen;
-    a.kk = c->d_kk;
     a.depth = c->prm.quad_depth;
     a.rho = c->prm.rho; a.mu = c->prm.mu; a.dt = c->prm.dt; a.theta = c->prm.theta;
     a.c_t = c->prm.c_t; a.c_i = c->prm.c_i; a.root_len = c->root_len;

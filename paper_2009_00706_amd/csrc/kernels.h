@@ -70,9 +70,6 @@ struct AsmArgs {
     const uint32_t *ccode;    // [E][4]
     const uint8_t *has_hang;  // [E]
     const uint8_t *level;     // [E]
-    const int64_t *rowbase;   // [E][8]
-    const int32_t *rowlen;    // [E][8]
-    const uint16_t *kk;       // [E][64]
     // work list
     int64_t n_items;
     const int32_t *items;     // element ids

@@ -25,6 +25,13 @@ struct Net {
     double blo[3], bhi[3];   // the box itself
 };
 
+// Per-cell margins over the network box (m == nullptr: none)
+struct MarginGrid {
+    const float *m;
+    int n[3];
+    double lo[3], inv[3];  // cell of x along k: floor((x - lo) inv), clamped
+};
+
 // Scratch kept by an in-out handle for the learned mode.
 struct Filter {
     int64_t cap = 0;
@@ -40,8 +47,10 @@ struct MlpHandle;  // vms_mlp
 // FP16-MFMA network outputs of n points.
 void launch_predict(hipStream_t s, const Net &net, const double *px, const double *py,
                     const double *pz, int64_t n, float *pred);
-// labels from the network where |pred| >= margin, indices of the rest appended
-void launch_decide(hipStream_t s, const float *pred, int64_t n, float margin, uint8_t *labels,
+// labels from the network where |pred| >= margin (of the point's cell when a
+// grid is given), indices of the rest appended
+void launch_decide(hipStream_t s, const float *pred, int64_t n, float margin, const MarginGrid &grid,
+                   const double *px, const double *py, const double *pz, uint8_t *labels,
                    int64_t *idx, unsigned long long *count);
 
 int classify_learned(hipStream_t s, Filter &f, const MlpHandle *net, const vmsk::SurfDev &S,

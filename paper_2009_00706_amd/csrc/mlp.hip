@@ -254,12 +254,26 @@ __global__ __launch_bounds__(64) void k_predict(Net net, const double *px, const
     }
 }
 
-__global__ void k_decide(const float *pred, int64_t n, float margin, uint8_t *labels, int64_t *idx,
-                         unsigned long long *count) {
+// margin of a point: the scalar margin, or with a margin grid over the
+// network box the margin of the point's cell
+__device__ inline float point_margin(const MarginGrid &g, float margin, double x, double y, double z) {
+    if (!g.m) return margin;
+    const double P[3] = {x, y, z};
+    int c[3];
+    for (int k = 0; k < 3; ++k) {
+        const int v = (int)floor((P[k] - g.lo[k]) * g.inv[k]);
+        c[k] = v < 0 ? 0 : (v >= g.n[k] ? g.n[k] - 1 : v);
+    }
+    return g.m[((int64_t)c[2] * g.n[1] + c[1]) * g.n[0] + c[0]];
+}
+
+__global__ void k_decide(const float *pred, int64_t n, float margin, MarginGrid grid,
+                         const double *px, const double *py, const double *pz, uint8_t *labels,
+                         int64_t *idx, unsigned long long *count) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float y = pred[i];
-    if (fabsf(y) >= margin) {
+    if (fabsf(y) >= point_margin(grid, margin, px[i], py[i], pz[i])) {
         labels[i] = y < 0.f ? 1 : 0;
     } else {
         const unsigned long long k = atomicAdd(count, 1ull);
@@ -274,11 +288,12 @@ void launch_predict(hipStream_t s, const Net &net, const double *px, const doubl
                        pred);
 }
 
-void launch_decide(hipStream_t s, const float *pred, int64_t n, float margin, uint8_t *labels,
+void launch_decide(hipStream_t s, const float *pred, int64_t n, float margin, const MarginGrid &grid,
+                   const double *px, const double *py, const double *pz, uint8_t *labels,
                    int64_t *idx, unsigned long long *count) {
     if (n <= 0) return;
     hipLaunchKernelGGL(k_decide, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pred, n, margin,
-                       labels, idx, count);
+                       grid, px, py, pz, labels, idx, count);
 }
 
 // ---------------------------------------------------------------------------
@@ -372,7 +387,19 @@ struct vmsm::MlpHandle {
     double *loss = nullptr;
     double lo[3], hi[3];
     float trunc = 0.1f, margin = INFINITY;
+    float *mgrid = nullptr;  // per-cell margins over the network box (nullable)
+    int gn[3] = {0, 0, 0};
     int64_t step = 0;
+    vmsm::MarginGrid grid() const {
+        vmsm::MarginGrid g{};
+        g.m = mgrid;
+        for (int k = 0; k < 3; ++k) {
+            g.n[k] = gn[k];
+            g.lo[k] = lo[k];
+            g.inv[k] = gn[k] > 0 ? gn[k] / (hi[k] - lo[k]) : 0.0;
+        }
+        return g;
+    }
     vmsm::Net net() const {
         vmsm::Net t{};
         t.theta = theta;
@@ -388,7 +415,7 @@ struct vmsm::MlpHandle {
     }
     ~MlpHandle() {
         for (void *p : {(void *)theta, (void *)m, (void *)v, (void *)grad, (void *)B, (void *)w16,
-                        (void *)loss})
+                        (void *)loss, (void *)mgrid})
             if (p) (void)hipFree(p);
     }
 };
@@ -407,7 +434,7 @@ int classify_learned(hipStream_t s, Filter &f, const MlpHandle *h, const vmsk::S
     }
     if (hipMemsetAsync(f.d_count, 0, sizeof(unsigned long long), s)) return VMS_EHIP;
     launch_predict(s, h->net(), px, py, pz, n, f.d_pred);
-    launch_decide(s, f.d_pred, n, h->margin, labels, f.d_idx, f.d_count);
+    launch_decide(s, f.d_pred, n, h->margin, h->grid(), px, py, pz, labels, f.d_idx, f.d_count);
     vmsk::launch_point_labels_list(s, S, f.d_idx, f.d_count, n, px, py, pz, labels, nullptr);
     return VMS_OK;
 }
@@ -476,6 +503,30 @@ int vms_mlp_set_margin(vms_mlp *m, float margin) {
     auto *h = (vmsm::MlpHandle *)m;
     if (!h || !(margin >= 0)) return mfail(VMS_EINVAL, "bad margin");
     h->margin = margin;
+    return VMS_OK;
+}
+
+int vms_mlp_set_margin_grid(vms_mlp *m, int nx, int ny, int nz, const float *margins) {
+    auto *h = (vmsm::MlpHandle *)m;
+    if (!h) return mfail(VMS_EINVAL, "null handle");
+    if (h->mgrid) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(h->mgrid);
+        h->mgrid = nullptr;
+        h->gn[0] = h->gn[1] = h->gn[2] = 0;
+    }
+    if (nx == 0 && ny == 0 && nz == 0) return VMS_OK;
+    if (nx <= 0 || ny <= 0 || nz <= 0 || !margins || (int64_t)nx * ny * nz > (1 << 24))
+        return mfail(VMS_EINVAL, "bad margin grid");
+    const int64_t nc = (int64_t)nx * ny * nz;
+    for (int64_t c = 0; c < nc; ++c)
+        if (!(margins[c] >= 0)) return mfail(VMS_EINVAL, "bad margin in grid");
+    if (hipMalloc(&h->mgrid, nc * sizeof(float)) != hipSuccess) return mfail(VMS_ENOMEM, "allocation failed");
+    if (hipMemcpy(h->mgrid, margins, nc * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+        return mfail(VMS_EHIP, "copy failed");
+    h->gn[0] = nx;
+    h->gn[1] = ny;
+    h->gn[2] = nz;
     return VMS_OK;
 }
 

@@ -293,14 +293,14 @@ def ellipsoid(semi, center, rot, n_lat: int, n_lon: int) -> Surface:
 def rounded_box(half, fillet, center, n_face: int) -> Surface:
     """Box with rounded edges and corners (fillet radius), from a cube-surface grid.
 
-    Each point p of the cube surface [-1,1]^3 scaled to the outer box maps to
-    c + fillet * (p - c)/|p - c|, with c the closest point of the inner box
-    (half - fillet). Grid lines are graded towards the face borders.
+    Each point p of a uniform n_face x n_face grid on every face of the cube
+    surface [-1,1]^3, scaled to the outer box, maps to c + fillet (p - c)/|p - c|,
+    with c the closest point of the inner box (half - fillet): 12 n_face^2
+    triangles.
     """
     half = np.asarray(half, dtype=np.float64)
     inner = half - fillet
     t = np.linspace(-1.0, 1.0, n_face + 1)
-    t = np.sign(t) * np.abs(t) ** 0.5 * 0.0 + t  # uniform on the unit face grid
     verts = {}
     vl = []
     tris = []
@@ -323,10 +323,13 @@ def rounded_box(half, fillet, center, n_face: int) -> Surface:
                     p[u_ax] = t[i]
                     p[v_ax] = t[j]
                     ids[i, j] = vid(p)
+            # (e_u x e_v) . e_axis is +1 for axes 0 and 2, -1 for axis 1: wind the
+            # quads so that every face's normal points out of the box
+            out = (1.0 if axis != 1 else -1.0) * sgn > 0
             for i in range(n_face):
                 for j in range(n_face):
                     a, b, c, d = ids[i, j], ids[i + 1, j], ids[i, j + 1], ids[i + 1, j + 1]
-                    tris += [[a, b, d], [a, d, c]]
+                    tris += [[a, b, d], [a, d, c]] if out else [[a, d, b], [a, c, d]]
     cube = np.array(vl)
     pts = cube * half
     cl = np.clip(pts, -inner, inner)
@@ -532,3 +535,14 @@ def batch_workload(n_trees: int, seed: int, size_lo=1e4, size_hi=5e5, lmin=4, tr
     import multiprocessing as mp
     with mp.get_context("spawn").Pool(workers) as pool:
         return pool.map(_batch_tree, args, chunksize=1)
+
+
+def two_boxes(n_face: int, domain=(8.0, 2.0, 2.0)):
+    """Two bluff boxes 1.0 x 0.25 x 0.3 with 0.03 fillets, one behind the other
+    along x with a gap of 0.5, centred in y and z of an 8 x 2 x 2 domain (plus
+    the non-dyadic offset); 24 n_face^2 triangles."""
+    half = (0.5, 0.125, 0.15)
+    c0 = np.array([3.0, domain[1] / 2, domain[2] / 2]) + np.asarray(BODY_OFFSET)
+    c1 = c0 + np.array([1.0 + 0.5, 0.0, 0.0])
+    return merge_surfaces([rounded_box(half, 0.03, c0, n_face), rounded_box(half, 0.03, c1, n_face)])
+

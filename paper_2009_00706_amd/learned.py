@@ -85,13 +85,34 @@ class LearnedFilter:
         vms.vms_mlp_predict(self.net, px, py, pz, pred)
         return pred
 
-    def calibrate(self, pts, safety=1.25):
+    def calibrate(self, pts, safety=1.25, grid=None, min_samples=32):
+        """Margin from held-out points: safety x the largest |prediction - exact
+        clamped distance|. With grid = (nx, ny, nz) the margin is per cell of a
+        uniform grid over the network box (cells with fewer than min_samples
+        held-out points get +inf: the network never decides there). Returns the
+        global margin and the errors."""
         pred = self.predict(pts).cpu().numpy().astype(np.float64)
         exact = self.exact_sdf(pts).cpu().numpy()
         inside = np.isfinite(pred)        # outside the box the answer is exact
         err = np.abs(pred[inside] - exact[inside])
         self.margin = float(safety * err.max()) if err.size else 0.0
         vms.vms_mlp_set_margin(self.net, self.margin)
+        if grid is None:
+            vms.vms_mlp_set_margin_grid(self.net, None)
+            self.grid = None
+            return self.margin, err
+        n = np.asarray(grid, np.int64)
+        x = np.asarray(pts, np.float64)[inside]
+        c = np.floor((x - self.lo) / (self.hi - self.lo) * n).astype(np.int64)
+        c = np.clip(c, 0, n - 1)
+        cell = (c[:, 2] * n[1] + c[:, 1]) * n[0] + c[:, 0]
+        nc = int(np.prod(n))
+        emax = np.zeros(nc)
+        np.maximum.at(emax, cell, err)
+        cnt = np.bincount(cell, minlength=nc)
+        m = np.where(cnt >= min_samples, safety * emax, np.inf).astype(np.float32)
+        self.grid = m.reshape(n[2], n[1], n[0])
+        vms.vms_mlp_set_margin_grid(self.net, self.grid)
         return self.margin, err
 
     def classify(self, pts, learned=True):

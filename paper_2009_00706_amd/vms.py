@@ -27,7 +27,7 @@ EXPORTED = ["vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply"
             "inout_prepare", "inout_classify_prepared", "inout_release", "vms_stats",
             "vms_mesh_create", "vms_mesh_sizes", "vms_mesh_export", "vms_mesh_destroy",
             "vms_set_timing", "vms_last_timing", "vms_mlp_create", "vms_mlp_get_params",
-            "vms_mlp_set_margin", "vms_mlp_grad", "vms_mlp_train", "vms_mlp_adam_step",
+            "vms_mlp_set_margin", "vms_mlp_set_margin_grid", "vms_mlp_grad", "vms_mlp_train", "vms_mlp_adam_step",
             "vms_mlp_predict", "vms_mlp_last_error", "vms_mlp_destroy", "vms_sdf_sample",
             "vms_batch_create", "vms_batch_set_config", "vms_batch_get_config",
             "vms_batch_use_graph", "vms_batch_assemble", "vms_batch_autotune", "vms_batch_last_timing",
@@ -92,6 +92,7 @@ def lib():
         L.vms_mlp_create.argtypes = [C.POINTER(p), p, p, p, p, C.c_float, p]
         L.vms_mlp_get_params.argtypes = [p, p]
         L.vms_mlp_set_margin.argtypes = [p, C.c_float]
+        L.vms_mlp_set_margin_grid.argtypes = [p, C.c_int, C.c_int, C.c_int, p]
         L.vms_mlp_grad.argtypes = [p, p, p, p, p, i64, p, p]
         L.vms_mlp_train.argtypes = [p, p, p, p, p, i64, C.c_int, C.c_int, C.c_float, p]
         L.vms_mlp_adam_step.argtypes = [p, p, C.c_float]
@@ -120,6 +121,7 @@ def lib():
                   "inout_classify", "inout_prepare", "inout_classify_prepared", "vms_stats",
                   "vms_mesh_create", "vms_mesh_sizes", "vms_mesh_export", "vms_set_timing",
                   "vms_last_timing", "vms_mlp_create", "vms_mlp_get_params", "vms_mlp_set_margin",
+                  "vms_mlp_set_margin_grid",
                   "vms_mlp_grad", "vms_mlp_train", "vms_mlp_adam_step", "vms_mlp_predict",
                   "vms_sdf_sample", "vms_batch_create", "vms_batch_set_config",
                   "vms_batch_get_config", "vms_batch_use_graph", "vms_batch_assemble",
@@ -336,6 +338,16 @@ def vms_mlp_get_params(h):
 
 def vms_mlp_set_margin(h, m):
     _mcheck(lib().vms_mlp_set_margin(h, float(m)))
+
+
+def vms_mlp_set_margin_grid(h, margins):
+    """margins: host array (nz, ny, nx) of per-cell margins, or None to remove."""
+    if margins is None:
+        _mcheck(lib().vms_mlp_set_margin_grid(h, 0, 0, 0, None))
+        return
+    m = np.ascontiguousarray(margins, np.float32)
+    nz, ny, nx = m.shape
+    _mcheck(lib().vms_mlp_set_margin_grid(h, nx, ny, nz, m.ctypes.data))
 
 
 def vms_mlp_grad(h, px, py, pz, sdf, grad=None):
