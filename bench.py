@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--precision", default=None, choices=["fp64", "bf16", "fp16"])
     ap.add_argument("--n-trees", type=int, default=64)
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16/FP16 comparison")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned in-out comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1500, help="elements in the oracle sample")
     ap.add_argument("--copy-calib", type=int, default=0,
@@ -164,6 +165,44 @@ def run_single(torch, vms, tree, surf, f, prec, steps, warmup, flags):
     return out
 
 
+def learned_inout(torch, vms, tree, surf):
+    """In-out classification of the workload's kept sub-cell points with and
+    without the learned filter (network trained by the library's kernels on
+    exact clamped distances, per-cell margins): labels must agree exactly."""
+    from paper_2009_00706_amd import inputs as I
+    from paper_2009_00706_amd.learned import LearnedFilter
+    asm = vms.Assembler(tree, surf, vms.make_params(quad_depth=3))
+    pts = asm.export(vms.VMS_EXPORT_SUBGP)["xyz"]
+    asm.close()
+    t0 = time.perf_counter()
+    lf = LearnedFilter(surf, trunc=0.05, seed=0, sigma=1.0)
+    lf.train(1_000_000, steps=8000, batch=8192, lr=3e-3)
+    lo, hi = surf.verts.min(0) - 0.1, surf.verts.max(0) + 0.1
+    held = I.sdf_sample_points(surf, lo, hi, 2_000_000, 11, near_frac=0.9, near_dist=0.02)
+    lf.calibrate(held, grid=(16, 16, 16))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    exact = lf.classify(pts, learned=False)
+    learned = lf.classify(pts, learned=True)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(exact, learned))
+    tt = {}
+    for mode in (False, True):
+        lf.classify(pts, learned=mode)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(5):
+            lf.classify(pts, learned=mode)
+        torch.cuda.synchronize()
+        tt[mode] = (time.perf_counter() - t1) / 5
+    lf.close()
+    return {"points": int(pts.shape[0]), "labels_equal": same,
+            "exact_tests_per_s": pts.shape[0] / tt[False], "learned_tests_per_s": pts.shape[0] / tt[True],
+            "gain": tt[False] / tt[True], "train_and_calibrate_s": train_s,
+            "note": "kept sub-cell points of the workload; exact: +x ray parity with exact predicates; "
+                    "learned: FP16-MFMA network, exact test inside the per-cell margin"}
+
+
 def roofline(k_ms, n_pts, peak, traffic, kname):
     achieved = FLOP_PER_POINT * n_pts / (k_ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
@@ -233,6 +272,8 @@ def main_single(args):
         out["forms"] = forms
         out["forms_note"] = ("mixed forms on the same inputs and step; errors are normwise against "
                              "this FP64 GPU result (itself within 1e-12 of the CPU reference)")
+    if surf is not None and not args.no_learned:
+        out["learned_inout"] = learned_inout(torch, vms, tree, surf)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(tree, surf, f, args.cpu_sample)
     print(json.dumps(out))
