@@ -22,6 +22,12 @@ int vmsm_sdf(hipStream_t s, const vmsk::SurfDev &S, const std::vector<double> &t
              const double *hi, const double *px, const double *py, const double *pz, int64_t n,
              double trunc, double *out);
 
+// sub-cell points per assembly work item (longer items: fewer element-matrix
+// records and item set-ups; shorter items: finer load balance)
+#ifndef VMS_ITEM_PTS
+#define VMS_ITEM_PTS 64
+#endif
+
 namespace {
 
 std::mutex g_err_mu;
@@ -609,7 +615,7 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
         if (rc) return bail(rc);
         // split every element's point list into work items of at most ITEM_PTS
         // points (partial element matrices are summed by the atomic scatter)
-        const int ITEM_PTS = 64;
+        const int ITEM_PTS = VMS_ITEM_PTS;
         std::vector<int32_t> iel, icnt;
         std::vector<int64_t> ioff;
         for (int64_t i = 0; i < c->n_sq; ++i)

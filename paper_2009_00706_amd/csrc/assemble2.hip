@@ -72,7 +72,7 @@ template <> __device__ inline float rsq<float>(float x) { return __frsqrt_rn(x);
 
 // reference coordinates (double) and weight of point pt of the item
 template <bool SUB>
-__device__ inline void point_xw(const AsmArgs &a, int64_t item, int pt, double h, double xi[3],
+__device__ inline void point_xw(const AsmArgs &a, uint32_t en, int pt, double h, double xi[3],
                                 double &w) {
     if (!SUB) {
         for (int k = 0; k < 3; ++k) xi[k] = ((pt >> k) & 1) ? VMS_XI : -VMS_XI;
@@ -80,7 +80,6 @@ __device__ inline void point_xw(const AsmArgs &a, int64_t item, int pt, double h
         w = hh * hh * hh;
         return;
     }
-    const uint32_t en = a.entries[a.pt_off[item] + pt];
     const int l = (int)(en & 3u), D = a.depth;
     const uint32_t key = en >> 2;
     const int gp = (int)((key >> (3 * (D - l))) & 7u);
@@ -246,7 +245,7 @@ struct Smem {
 // One work item (an element, or a run of sub-cell points of one element) by
 // one 64-lane workgroup.
 template <typename T, int MODE, bool SUB, bool MAT, int PD>
-__device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, PD> &sm) {
+__device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, PD> &sm) {
     constexpr int CP = 8;  // points per chunk (one lane group of 8 per point)
     static_assert(MODE == 0 || PD == 8, "the mixed forms take 8 points per MFMA k-step");
     static_assert(PD == 4 || PD == 8, "D blocks of 4 or 8 points at a time");
@@ -296,9 +295,14 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, PD> &sm) 
         accf[t] = v4f{0, 0, 0, 0};
     }
     T R = T(0);  // lanes < 32: residual of (a = lane & 7, i = lane >> 3)
+    // sub-cell entry of the lane's point (lane = (p, s)), loaded one chunk ahead
+    const int64_t eoff = SUB ? a.pt_off[item] : 0;
+    uint32_t en_cur = (SUB && (lane >> 3) < npts) ? a.entries[eoff + (lane >> 3)] : 0u;
 
     for (int base = 0; base < npts; base += CP) {
         const int np = min(CP, npts - base);
+        const int pn = base + CP + (lane >> 3);
+        const uint32_t en_next = (SUB && pn < npts) ? a.entries[eoff + pn] : 0u;
         // ---- phase 1: constrained basis at the chunk's points (lane = (p, s))
         for (int idx = lane; idx < CP * 8; idx += 64) {
             const int p = idx >> 3, s = idx & 7;
@@ -306,7 +310,7 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, PD> &sm) 
             double w = 0.0;
             if (p < np) {
                 double xi[3];
-                point_xw<SUB>(a, item, base + p, hd, xi, w);
+                point_xw<SUB>(a, en_cur, base + p, hd, xi, w);
                 // vertex v of the constrained slot s: v = s without hanging
                 // corners, else every v with C[v][s] != 0
                 const T xt[3] = {(T)xi[0], (T)xi[1], (T)xi[2]};
@@ -587,6 +591,7 @@ __device__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, PD> &sm) 
                 R += SB(p, 0, av) * sQ[p][QRC + 4 * i] + SB(p, 1, av) * sQ[p][QRC + 4 * i + 1] +
                      SB(p, 2, av) * sQ[p][QRC + 4 * i + 2] + SB(p, 3, av) * sQ[p][QRC + 4 * i + 3];
         }
+        en_cur = en_next;
         __syncthreads();
     }
 
@@ -664,6 +669,7 @@ __global__ VMS_ASM_BOUNDS(MODE) void k_asm_batch(const AsmArgs *args, const Batc
                                                  unsigned long long *counter) {
     __shared__ Smem<T, MODE == 0 ? 4 : 8> sm;
     __shared__ int64_t su;
+    __shared__ AsmArgs sa;  // the unit's tree, read from LDS where used
     for (;;) {
         __syncthreads();
         if (threadIdx.x == 0) su = first + (int64_t)atomicAdd(counter, 1ull);
@@ -671,8 +677,9 @@ __global__ VMS_ASM_BOUNDS(MODE) void k_asm_batch(const AsmArgs *args, const Batc
         const int64_t u = su;
         if (u >= last) break;
         const BatchUnit U = units[u];
-        const AsmArgs a = args[U.tree];
-        for (int k = 0; k < U.count; ++k) asm_item<T, MODE, SUB, true, MODE == 0 ? 4 : 8>(a, U.first + k, sm);
+        if (threadIdx.x == 0) sa = args[U.tree];
+        __syncthreads();
+        for (int k = 0; k < U.count; ++k) asm_item<T, MODE, SUB, true, MODE == 0 ? 4 : 8>(sa, U.first + k, sm);
     }
 }
 
