@@ -109,52 +109,28 @@ __device__ inline void point_xw(const AsmArgs &a, uint32_t en, int pt, double h,
 //     cm = tau/rho u' - taubar tau s, Xm = -taubar tau u';
 //   continuity/velocity: D0l = theta d_lj, Dk0 = tau A_kj, Dkl = tau theta d_kj u_l;
 //   continuity/pressure: Dkl = tau/rho d_kl.
+// Momentum test / velocity trial blocks (i, j < 3); the other kinds are in
+// dblock_simple.
 template <typename T>
-__device__ inline void dblock(const T *Q, int i, int j, T rho, T mu, T th, T D[4][4]) {
+__device__ inline void dblock_mv(const T *Q, int i, int j, T rho, T mu, T th, T D[4][4]) {
     const T W = Q[QW], tauM = Q[QTM];
-    if (i < 3 && j < 3) {
-        const T dij = (i == j) ? T(1) : T(0);
-        const T Aij = Q[QA + 3 * i + j], gij = Q[QG + 3 * i + j], GAij = Q[QGA + 3 * i + j];
-        const T cpi = Q[QCP + i], upi = Q[QUP + i];
-        const T mth = mu * th, rtc = rho * Q[QTC] * th;
-        D[0][0] = rho * Aij - tauM * rho * GAij;
-        for (int l = 0; l < 3; ++l) D[0][1 + l] = dij * Q[QV0 + l] + gij * Q[QW0 + l];
-        for (int k = 0; k < 3; ++k) {
-            const T Akj = Q[QA + 3 * k + j];
-            D[1 + k][0] = Aij * Q[QY + k] + Akj * cpi + GAij * Q[QX + k] - ((k == j) ? th * upi : T(0));
-            for (int l = 0; l < 3; ++l) {
-                T v = dij * Q[QS9 + 3 * k + l] + gij * Q[QZ9 + 3 * k + l];
-                if (k == j) v += th * cpi * Q[QUT + l];
-                if (i == j && k == l) v += mth;
-                if (k == j && i == l) v += mth;
-                if (k == i && l == j) v += rtc;
-                D[1 + k][1 + l] = v;
-            }
+    const T dij = (i == j) ? T(1) : T(0);
+    const T Aij = Q[QA + 3 * i + j], gij = Q[QG + 3 * i + j], GAij = Q[QGA + 3 * i + j];
+    const T cpi = Q[QCP + i], upi = Q[QUP + i];
+    const T mth = mu * th, rtc = rho * Q[QTC] * th;
+    D[0][0] = rho * Aij - tauM * rho * GAij;
+    for (int l = 0; l < 3; ++l) D[0][1 + l] = dij * Q[QV0 + l] + gij * Q[QW0 + l];
+    for (int k = 0; k < 3; ++k) {
+        const T Akj = Q[QA + 3 * k + j];
+        D[1 + k][0] = Aij * Q[QY + k] + Akj * cpi + GAij * Q[QX + k] - ((k == j) ? th * upi : T(0));
+        for (int l = 0; l < 3; ++l) {
+            T v = dij * Q[QS9 + 3 * k + l] + gij * Q[QZ9 + 3 * k + l];
+            if (k == j) v += th * cpi * Q[QUT + l];
+            if (i == j && k == l) v += mth;
+            if (k == j && i == l) v += mth;
+            if (k == i && l == j) v += rtc;
+            D[1 + k][1 + l] = v;
         }
-    } else if (i < 3) {  // momentum test, pressure trial
-        const T cmi = Q[QCM + i];
-        D[0][0] = T(0);
-        for (int l = 0; l < 3; ++l) D[0][1 + l] = -tauM * Q[QG + 3 * i + l];
-        for (int k = 0; k < 3; ++k) {
-            D[1 + k][0] = (k == i) ? T(-1) : T(0);
-            for (int l = 0; l < 3; ++l) {
-                T v = Q[QXM + k] * Q[QG + 3 * i + l];
-                if (l == i) v += Q[QYM + k];
-                if (k == l) v += cmi;
-                D[1 + k][1 + l] = v;
-            }
-        }
-    } else if (j < 3) {  // continuity test, velocity trial
-        D[0][0] = T(0);
-        for (int l = 0; l < 3; ++l) D[0][1 + l] = (l == j) ? th : T(0);
-        for (int k = 0; k < 3; ++k) {
-            D[1 + k][0] = tauM * Q[QA + 3 * k + j];
-            for (int l = 0; l < 3; ++l) D[1 + k][1 + l] = (k == j) ? tauM * th * Q[QUT + l] : T(0);
-        }
-    } else {  // continuity test, pressure trial
-        const T v = tauM / rho;
-        for (int k = 0; k < 4; ++k)
-            for (int l = 0; l < 4; ++l) D[k][l] = (k == l && k > 0) ? v : T(0);
     }
     for (int k = 0; k < 4; ++k)
         for (int l = 0; l < 4; ++l) D[k][l] *= W;
@@ -471,7 +447,7 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item, S
                     for (int k = 0; k < 4; ++k)
                         for (int l = 0; l < 4; ++l) D[k][l] = T(0);
                 } else if (mv) {
-                    dblock<T>(sQ[pb + p], i, j, rho, mu, th, D);
+                    dblock_mv<T>(sQ[pb + p], i, j, rho, mu, th, D);
                 } else {
                     dblock_simple<T>(sQ[pb + p], i, j, rho, th, D);
                 }
