@@ -328,95 +328,111 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item, S
             }
         }
         __syncthreads();
-        // ---- phase 3: point quantities (lane = p)
-        if (lane < np) {
-            const int p = lane;
-            T ut[3], at[3], gu[3][3], gp[3];
-            for (int c = 0; c < 3; ++c) {
-                ut[c] = th * SI(p, c, 0) + (T(1) - th) * SI(p, 4 + c, 0);
-                at[c] = (SI(p, c, 0) - SI(p, 4 + c, 0)) * idt;
-                for (int m = 0; m < 3; ++m) gu[c][m] = th * SI(p, c, 1 + m) + (T(1) - th) * SI(p, 4 + c, 1 + m);
-                gp[c] = SI(p, 3, 1 + c);
-            }
-            const T pr = SI(p, 3, 0);
-            T conv[3], rM[3];
-            for (int c = 0; c < 3; ++c) {
-                conv[c] = ut[0] * gu[c][0] + ut[1] * gu[c][1] + ut[2] * gu[c][2];
-                rM[c] = rho * (at[c] + conv[c]) + gp[c];
-            }
-            const T div = gu[0][0] + gu[1][1] + gu[2][2];
-            const T uGu = gG * (ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
-            const T tauM = rsq<T>(tau0 + uGu);
-            const T tauC = h2_12 / tauM;
-            T up[3];
-            for (int c = 0; c < 3; ++c) up[c] = -tauM * rM[c];
-            const T pp = -rho * tauC * div;
-            const T upg = gG * (up[0] * up[0] + up[1] * up[1] + up[2] * up[2]);
-            const T tb = upg > T(0) ? rsq<T>(upg) : T(0);
-            T *q = sQ[p];
-            const T W = q[QW];
-            T sv[3];
-            for (int c = 0; c < 3; ++c) sv[c] = up[0] * gu[c][0] + up[1] * gu[c][1] + up[2] * gu[c][2];
-            // (a) the point state and the residual coefficients r^i[k] (times W)
-            q[QTM] = tauM;
-            q[QTC] = tauC;
-            q[QTB] = tb;
-            for (int c = 0; c < 3; ++c) {
-                q[QUT + c] = ut[c];
-                q[QUP + c] = up[c];
-                q[QSV + c] = sv[c];
-                for (int m = 0; m < 3; ++m) q[QG + 3 * c + m] = gu[c][m];
-            }
-            for (int c = 0; c < 3; ++c) {
-                q[QRC + 4 * c] = W * (rho * at[c] + rho * conv[c] + sv[c]);
-                for (int k = 0; k < 3; ++k)
-                    q[QRC + 4 * c + 1 + k] =
-                        W * (mu * (gu[c][k] + gu[k][c]) - (k == c ? pr + pp : T(0)) - ut[k] * up[c] -
-                             up[k] * up[c] * irho + tb * up[k] * sv[c]);
-            }
-            q[QRC + 12] = W * div;
-            for (int k = 0; k < 3; ++k) q[QRC + 13 + k] = -W * up[k] * irho;
-        }
-        // (b) the factors of the D blocks, from the stored point state: the
-        // round trip through LDS bounds the registers the point phase holds
-        __asm__ volatile("" ::: "memory");
-        if (lane < np) {
-            const int p = lane;
-            T *q = sQ[p];
-            T ut[3], up[3], sv[3], gu[3][3];
-            for (int c = 0; c < 3; ++c) {
-                ut[c] = q[QUT + c];
-                up[c] = q[QUP + c];
-                sv[c] = q[QSV + c];
-                for (int m = 0; m < 3; ++m) gu[c][m] = q[QG + 3 * c + m];
-            }
-            const T tauM = q[QTM], tb = q[QTB];
-            const T tr = tauM * rho, tbtr = tb * tauM * rho, tbt = tb * tauM, tir = tauM * irho;
-            for (int c = 0; c < 3; ++c) {
-                q[QY + c] = tr * ut[c] + tauM * up[c];
-                q[QX + c] = -tbtr * up[c];
-                q[QCP + c] = tauM * up[c] - tbtr * sv[c];
-                q[QV0 + c] = th * (rho * ut[c] + up[c]);
-                q[QW0 + c] = -th * tr * ut[c];
-                q[QYM + c] = tauM * ut[c] + tir * up[c];
-                q[QCM + c] = tir * up[c] - tbt * sv[c];
-                q[QXM + c] = -tbt * up[c];
-                for (int m = 0; m < 3; ++m) {
-                    q[QA + 3 * c + m] = (c == m ? idt : T(0)) + th * gu[c][m];
-                    T v = T(0);
-                    for (int k = 0; k < 3; ++k) v += gu[c][k] * ((k == m ? idt : T(0)) + th * gu[k][m]);
-                    q[QGA + 3 * c + m] = v;
-                    q[QS9 + 3 * c + m] = th * (tr * ut[c] * ut[m] + tauM * up[c] * ut[m] + tb * up[c] * up[m]);
-                    q[QZ9 + 3 * c + m] = -tbtr * th * up[c] * ut[m];
+        // ---- phase 3: point quantities, lane = (p, r). (a) Lanes r = 0..3 of
+        // point p evaluate the point state; lane r < 3 writes row / component
+        // c = r of it and momentum row c of the residual coefficients r^i[k]
+        // (times W), lane r = 3 the scalars and the continuity row.
+        {
+            const int p = lane >> 3, r = lane & 7;
+            if (p < np && r < 4) {
+                T ut[3], gu[3][3], up[3];
+                for (int c = 0; c < 3; ++c) {
+                    ut[c] = th * SI(p, c, 0) + (T(1) - th) * SI(p, 4 + c, 0);
+                    for (int m = 0; m < 3; ++m)
+                        gu[c][m] = th * SI(p, c, 1 + m) + (T(1) - th) * SI(p, 4 + c, 1 + m);
+                }
+                T rM[3];
+                for (int c = 0; c < 3; ++c) {
+                    const T atc = (SI(p, c, 0) - SI(p, 4 + c, 0)) * idt;
+                    const T conv = ut[0] * gu[c][0] + ut[1] * gu[c][1] + ut[2] * gu[c][2];
+                    rM[c] = rho * (atc + conv) + SI(p, 3, 1 + c);
+                }
+                const T div = gu[0][0] + gu[1][1] + gu[2][2];
+                const T s0 = tau0 + gG * (ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
+                const T tauM = rsq<T>(s0);
+                const T tauC = h2_12 * s0 * tauM;  // (h^2/12) / tau_M
+                for (int c = 0; c < 3; ++c) up[c] = -tauM * rM[c];
+                const T pp = -rho * tauC * div;
+                const T upg = gG * (up[0] * up[0] + up[1] * up[1] + up[2] * up[2]);
+                const T tb = upg > T(0) ? rsq<T>(upg) : T(0);
+                T *q = sQ[p];
+                const T W = q[QW];
+                if (r < 3) {
+                    const int c = r;
+                    T guc[3], gcol[3];
+                    for (int m = 0; m < 3; ++m) {
+                        guc[m] = th * SI(p, c, 1 + m) + (T(1) - th) * SI(p, 4 + c, 1 + m);
+                        gcol[m] = th * SI(p, m, 1 + c) + (T(1) - th) * SI(p, 4 + m, 1 + c);
+                    }
+                    const T utc = th * SI(p, c, 0) + (T(1) - th) * SI(p, 4 + c, 0);
+                    const T atc = (SI(p, c, 0) - SI(p, 4 + c, 0)) * idt;
+                    const T convc = ut[0] * guc[0] + ut[1] * guc[1] + ut[2] * guc[2];
+                    const T upc = -tauM * (rho * (atc + convc) + SI(p, 3, 1 + c));
+                    const T svc = up[0] * guc[0] + up[1] * guc[1] + up[2] * guc[2];
+                    const T pr = SI(p, 3, 0);
+                    q[QUT + c] = utc;
+                    q[QUP + c] = upc;
+                    q[QSV + c] = svc;
+                    for (int m = 0; m < 3; ++m) q[QG + 3 * c + m] = guc[m];
+                    q[QRC + 4 * c] = W * (rho * atc + rho * convc + svc);
+                    for (int k = 0; k < 3; ++k)
+                        q[QRC + 4 * c + 1 + k] =
+                            W * (mu * (guc[k] + gcol[k]) - (k == c ? pr + pp : T(0)) - ut[k] * upc -
+                                 up[k] * upc * irho + tb * up[k] * svc);
+                } else {
+                    q[QTM] = tauM;
+                    q[QTC] = tauC;
+                    q[QTB] = tb;
+                    q[QRC + 12] = W * div;
+                    for (int k = 0; k < 3; ++k) q[QRC + 13 + k] = -W * up[k] * irho;
                 }
             }
-            if (MODE == 2) {
-                // balance a power of two between the two fp16 operands: a product is
-                // about W (2/h)^2 100 (mass coefficient rho/dt ~ 100 for the workloads)
-                const float x = (float)((double)q[QW] * 4.0 / (hd * hd) * 100.0);
-                int ex;
-                frexpf(x, &ex);
-                sSc[p] = ldexpf(1.0f, ex / 2);
+        }
+        // (b) the factors of the D blocks from the stored point state, lane
+        // (p, r): r < 3 the matrix rows c = r, 3 <= r < 6 the vector
+        // components c = r - 3. The round trip through LDS bounds the registers
+        // the point phase holds.
+        __syncthreads();
+        {
+            const int p = lane >> 3, r = lane & 7;
+            if (p < np && r < 6) {
+                const T *qc = sQ[p];
+                T *q = sQ[p];
+                const T tauM = qc[QTM], tb = qc[QTB];
+                const T tr = tauM * rho, tbtr = tb * tauM * rho, tbt = tb * tauM, tir = tauM * irho;
+                if (r < 3) {
+                    const int c = r;
+                    const T utc = qc[QUT + c], upc = qc[QUP + c];
+                    for (int m = 0; m < 3; ++m) {
+                        const T utm = qc[QUT + m], upm = qc[QUP + m];
+                        q[QA + 3 * c + m] = (c == m ? idt : T(0)) + th * qc[QG + 3 * c + m];
+                        T v = T(0);
+                        for (int k = 0; k < 3; ++k)
+                            v += qc[QG + 3 * c + k] * ((k == m ? idt : T(0)) + th * qc[QG + 3 * k + m]);
+                        q[QGA + 3 * c + m] = v;
+                        q[QS9 + 3 * c + m] = th * (tr * utc * utm + tauM * upc * utm + tb * upc * upm);
+                        q[QZ9 + 3 * c + m] = -tbtr * th * upc * utm;
+                    }
+                } else {
+                    const int c = r - 3;
+                    const T utc = qc[QUT + c], upc = qc[QUP + c], svc = qc[QSV + c];
+                    q[QY + c] = tr * utc + tauM * upc;
+                    q[QX + c] = -tbtr * upc;
+                    q[QCP + c] = tauM * upc - tbtr * svc;
+                    q[QV0 + c] = th * (rho * utc + upc);
+                    q[QW0 + c] = -th * tr * utc;
+                    q[QYM + c] = tauM * utc + tir * upc;
+                    q[QCM + c] = tir * upc - tbt * svc;
+                    q[QXM + c] = -tbt * upc;
+                }
+                if (MODE == 2 && r == 0) {
+                    // balance a power of two between the two fp16 operands: a product is
+                    // about W (2/h)^2 100 (mass coefficient rho/dt ~ 100 for the workloads)
+                    const float x = (float)((double)qc[QW] * 4.0 / (hd * hd) * 100.0);
+                    int ex;
+                    frexpf(x, &ex);
+                    sSc[p] = ldexpf(1.0f, ex / 2);
+                }
             }
         }
         __syncthreads();
