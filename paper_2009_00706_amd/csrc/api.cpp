@@ -779,6 +779,7 @@ static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *re
     for (int k = 0; k < 7; ++k) a.f[k] = fp[k];
     a.rho = c->prm.rho; a.mu = c->prm.mu; a.dt = c->prm.dt; a.theta = c->prm.theta;
     a.c_t = c->prm.c_t; a.c_i = c->prm.c_i; a.root_len = c->root_len;
+    vmsk::derive_constants(a);
     a.vals = vals;
     a.resid = resid;
     a.em = c->d_em;
@@ -1057,6 +1058,7 @@ vmsk::AsmArgs base_args(vms_ctx *c) {
     a.depth = c->prm.quad_depth;
     a.rho = c->prm.rho; a.mu = c->prm.mu; a.dt = c->prm.dt; a.theta = c->prm.theta;
     a.c_t = c->prm.c_t; a.c_i = c->prm.c_i; a.root_len = c->root_len;
+    vmsk::derive_constants(a);
     return a;
 }
 

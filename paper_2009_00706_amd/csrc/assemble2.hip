@@ -198,6 +198,20 @@ __device__ inline void split2h(float x, _Float16 &h, _Float16 &l) {
     h = (_Float16)x;
     l = (_Float16)(x - (float)h);
 }
+// the same on pairs (one packed conversion per pair)
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef _Float16 v2h __attribute__((ext_vector_type(2)));
+__device__ inline void split3x2(v2f x, v2bf &h, v2bf &m, v2bf &l) {
+    h = __builtin_convertvector(x, v2bf);
+    const v2f r1 = x - __builtin_convertvector(h, v2f);
+    m = __builtin_convertvector(r1, v2bf);
+    l = __builtin_convertvector(r1 - __builtin_convertvector(m, v2f), v2bf);
+}
+__device__ inline void split2hx2(v2f x, v2h &h, v2h &l) {
+    h = __builtin_convertvector(x, v2h);
+    l = __builtin_convertvector(x - __builtin_convertvector(h, v2f), v2h);
+}
 
 // LDS of one work item. Arrays are flat with padded strides so that the
 // accesses of the phases below spread over the banks (64-bit accesses by 16
@@ -207,13 +221,6 @@ __device__ inline void split2h(float x, _Float16 &h, _Float16 &l) {
 //   I(p, f, k)       interpolated fields, field stride 5, point stride 35
 //   D(p, i, j, k, l) coefficient blocks, block stride 17, point stride 276
 constexpr int LU = 9, LB = 40, LI = 35, LDB = 17, LDP = 16 * LDB + 4;
-// element-matrix staging: block (a, b) of master slots, entry e = 4 i + j
-// (test component i, trial component j), padded strides; EMS_SIZE entries
-#define EMS(av, b, e) ((av) * 164 + (b) * 20 + (e))
-constexpr int EMS_SIZE = 7 * 164 + 7 * 20 + 16;
-// half-record staging (test components i = 2h, 2h + 1; e' = 4 (i & 1) + j)
-#define EMH(av, b, e) ((av) * 84 + (b) * 10 + (e))
-constexpr int EMH_SIZE = 7 * 84 + 7 * 10 + 8;
 // PD = points whose D blocks are held at once (FP64: 4, mixed: 8)
 template <typename T, int PD>
 struct Smem {
@@ -225,7 +232,6 @@ struct Smem {
     union {  // the interpolated fields are dead once the point quantities exist
         T sI[CP * LI];
         T sD[PD * LDP];  // weight folded in
-        T sE[PD == 8 ? EMS_SIZE : EMH_SIZE];  // element-matrix staging after the last chunk
     };
     T sSc[CP];       // fp16 form: per-point power-of-two balance
     int sM[8];
@@ -256,7 +262,7 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item, S
     const int e = a.items[item];
     const bool hang = a.has_hang[e] != 0;
     const double hd = ldexp(a.root_len, -(int)a.level[e]);
-    const double two_over_h = 2.0 / hd;
+    const double two_over_h = ldexp(a.two_over_root, (int)a.level[e]);
     const T h = (T)hd;
     if (lane < 8) sM[lane] = a.masters[8 * (int64_t)e + lane];
     {
@@ -271,13 +277,13 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item, S
     }
     const int npts = SUB ? a.pt_cnt[item] : 8;
     const T rho = (T)a.rho, mu = (T)a.mu, th = (T)a.theta;
-    const T idt = (T)(1.0 / a.dt), irho = (T)(1.0 / a.rho);
+    const T idt = (T)a.idt, irho = (T)a.irho;
     // G = (2/h)^2 I: u.G.u = gG |u|^2; tau_M^-2 = c_t/dt^2 + gG |u|^2 + c_i nu^2 G:G;
     // tau_C = 1/(tau_M tr G) = (h^2/12)/tau_M
-    const double gGd = 4.0 / (hd * hd), nud = a.mu / a.rho;
+    const double gGd = two_over_h * two_over_h;
     const T gG = (T)gGd;
-    const T tau0 = (T)(a.c_t / (a.dt * a.dt) + a.c_i * nud * nud * 3.0 * gGd * gGd);
-    const T h2_12 = (T)(hd * hd / 12.0);
+    const T tau0 = (T)(a.tau_a + a.tau_b * gGd * gGd);
+    const T h2_12 = (T)(hd * hd * (1.0 / 12.0));
     // fp16 form: basis rows scaled by h/2 (values and scaled gradients in [-1, 1])
     const T bscale = MODE == 2 ? (T)(0.5 * hd) : T(1);
 
@@ -289,6 +295,10 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item, S
         accf[t] = v4f{0, 0, 0, 0};
     }
     T R = T(0);  // lanes < 32: residual of (a = lane & 7, i = lane >> 3)
+    // FP64 with the matrix: the residual is a ninth MFMA column block (columns
+    // i < 4 carry r^i[k]); rows a = 4 r + lane / 16, column i = lane % 16
+    constexpr bool RES_MFMA = MODE == 0 && MAT;
+    v4d accr = v4d{0, 0, 0, 0};
     // sub-cell entry of the lane's point (lane = (p, s)), loaded one chunk ahead
     const int64_t eoff = SUB ? a.pt_off[item] : 0;
     uint32_t en_cur = (SUB && (lane >> 3) < npts) ? a.entries[eoff + (lane >> 3)] : 0u;
@@ -440,7 +450,7 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item, S
                 if (MODE == 2 && r == 0) {
                     // balance a power of two between the two fp16 operands: a product is
                     // about W (2/h)^2 100 (mass coefficient rho/dt ~ 100 for the workloads)
-                    const float x = (float)((double)qc[QW] * 4.0 / (hd * hd) * 100.0);
+                    const float x = (float)((double)qc[QW] * gGd * 100.0);
                     int ex;
                     frexpf(x, &ex);
                     sSc[p] = ldexpf(1.0f, ex / 2);
@@ -490,6 +500,8 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item, S
 #pragma unroll 1
                 for (int p = 0; p < nd; ++p) {
                     const double A = arow < 8 ? (double)SB(pb + p, k, arow) : 0.0;
+                    const double rc = arow < 4 ? (double)sQ[pb + p][QRC + 4 * (arow & 3) + k] : 0.0;
+                    accr = __builtin_amdgcn_mfma_f64_16x16x4f64(A, rc, accr, 0, 0, 0);
                     double Bv[2][4];
                     for (int bh = 0; bh < 2; ++bh)
                         for (int m = 0; m < 4; ++m) Bv[bh][m] = (double)SB(pb + p, m, 4 * bh + bb);
@@ -523,7 +535,7 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item, S
                 float fs[2] = {1.f, 1.f};
                 if (MODE == 2)
                     for (int pp = 0; pp < 2; ++pp)
-                        fs[pp] = (float)(1.0 / (double)bscale) / (float)sSc[2 * g + pp];
+                        fs[pp] = (float)two_over_h / (float)sSc[2 * g + pp];
                 if (MODE == 1) {
                     v8bf Ahm, Alo;
                     for (int t = 0; t < 8; ++t) {
@@ -534,16 +546,23 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item, S
                     }
                     for (int i = 0; i < 4; ++i) {
                         v8bf F1[2], F2[2], F3[2];
-                        for (int t = 0; t < 8; ++t) {
+                        for (int t = 0; t < 8; t += 2) {
                             const int pp = t >> 2, p = 2 * g + pp, k = t & 3;
-                            float d[4];
-                            for (int m = 0; m < 4; ++m) d[m] = (float)SD(p, i, jc, k, m);
+                            float d[2][4];
+                            for (int m = 0; m < 4; ++m) {
+                                d[0][m] = (float)SD(p, i, jc, k, m);
+                                d[1][m] = (float)SD(p, i, jc, k + 1, m);
+                            }
                             for (int bh = 0; bh < 2; ++bh) {
-                                const float F = d[0] * Bc[pp][bh][0] + d[1] * Bc[pp][bh][1] +
-                                                d[2] * Bc[pp][bh][2] + d[3] * Bc[pp][bh][3];
-                                __bf16 x1, x2, x3;
-                                split3(F, x1, x2, x3);
-                                F1[bh][t] = x1; F2[bh][t] = x2; F3[bh][t] = x3;
+                                v2f F;
+                                for (int e = 0; e < 2; ++e)
+                                    F[e] = d[e][0] * Bc[pp][bh][0] + d[e][1] * Bc[pp][bh][1] +
+                                           d[e][2] * Bc[pp][bh][2] + d[e][3] * Bc[pp][bh][3];
+                                v2bf x1, x2, x3;
+                                split3x2(F, x1, x2, x3);
+                                F1[bh][t] = x1[0]; F1[bh][t + 1] = x1[1];
+                                F2[bh][t] = x2[0]; F2[bh][t + 1] = x2[1];
+                                F3[bh][t] = x3[0]; F3[bh][t + 1] = x3[1];
                             }
                         }
                         for (int bh = 0; bh < 2; ++bh) {
@@ -564,17 +583,23 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item, S
                     }
                     for (int i = 0; i < 4; ++i) {
                         v8h F1[2], F2[2];
-                        for (int t = 0; t < 8; ++t) {
+                        for (int t = 0; t < 8; t += 2) {
                             const int pp = t >> 2, p = 2 * g + pp, k = t & 3;
-                            float d[4];
-                            for (int m = 0; m < 4; ++m) d[m] = (float)SD(p, i, jc, k, m);
+                            float d[2][4];
+                            for (int m = 0; m < 4; ++m) {
+                                d[0][m] = (float)SD(p, i, jc, k, m);
+                                d[1][m] = (float)SD(p, i, jc, k + 1, m);
+                            }
                             for (int bh = 0; bh < 2; ++bh) {
                                 // undo the basis scaling and the balance on this operand
-                                const float F = (d[0] * Bc[pp][bh][0] + d[1] * Bc[pp][bh][1] +
-                                                 d[2] * Bc[pp][bh][2] + d[3] * Bc[pp][bh][3]) * fs[pp];
-                                _Float16 x1, x2;
-                                split2h(F, x1, x2);
-                                F1[bh][t] = x1; F2[bh][t] = x2;
+                                v2f F;
+                                for (int e = 0; e < 2; ++e)
+                                    F[e] = (d[e][0] * Bc[pp][bh][0] + d[e][1] * Bc[pp][bh][1] +
+                                            d[e][2] * Bc[pp][bh][2] + d[e][3] * Bc[pp][bh][3]) * fs[pp];
+                                v2h x1, x2;
+                                split2hx2(F, x1, x2);
+                                F1[bh][t] = x1[0]; F1[bh][t + 1] = x1[1];
+                                F2[bh][t] = x2[0]; F2[bh][t + 1] = x2[1];
                             }
                         }
                         for (int bh = 0; bh < 2; ++bh) {
@@ -589,7 +614,7 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item, S
             }  // batches of PD points
         }
         // residual: lanes < 32, (a = lane & 7, i = lane >> 3)
-        if (lane < 32) {
+        if (!RES_MFMA && lane < 32) {
             const int av = lane & 7, i = lane >> 3;
             for (int p = 0; p < np; ++p)
                 R += SB(p, 0, av) * sQ[p][QRC + 4 * i] + SB(p, 1, av) * sQ[p][QRC + 4 * i + 1] +
@@ -599,48 +624,45 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item, S
         __syncthreads();
     }
 
-    // ---- element matrix out: accumulators -> LDS (block-major, padded) -> one
-    // coalesced 1024-entry record per work item; the CSR is summed from these
-    // records by the gather kernel (no atomics, fixed summation order)
+    // ---- element matrix out: one 1024-entry record per work item, block-major
+    // (block (a, b) of master slots, entry 4 i + j), stored from the
+    // accumulators; the CSR is summed from these records by the gather kernel
+    // (no atomics, fixed summation order)
     if (MAT) {
-        T *stage = sm.sE;  // shares the D area, free after the last chunk
         const int col = lane & 15, bb = col >> 2, jc = col & 3;
         T *dst = (T *)a.em + (a.slot0 + item) * 1024;
         if (MODE == 0) {
-            // two halves of the record: test components i = 2h, 2h + 1
-            for (int h = 0; h < 2; ++h) {
-                __syncthreads();
-                for (int t = 4 * h; t < 4 * h + 4; ++t) {
-                    const int i = t >> 1, b = 4 * (t & 1) + bb;
-                    for (int r = 0; r < 2; ++r) {
-                        const int av = 4 * r + (lane >> 4);  // output row = 4 r + lane / 16
-                        stage[EMH(av, b, 4 * (i & 1) + jc)] = (T)accd[t][r];
-                    }
-                }
-                __syncthreads();
-                for (int v = lane; v < 512; v += 64) {
-                    const int blk = v >> 3, e = v & 7;
-                    dst[blk * 16 + 8 * h + e] = stage[EMH(blk >> 3, blk & 7, e)];
+            for (int t = 0; t < 8; ++t) {
+                const int i = t >> 1, b = 4 * (t & 1) + bb;
+                for (int r = 0; r < 2; ++r) {
+                    const int av = 4 * r + (lane >> 4);
+                    dst[(av * 8 + b) * 16 + 4 * i + jc] = (T)accd[t][r];
                 }
             }
         } else {
-            __syncthreads();
             // rows 8..15 carry the second split term: fold them onto rows 0..7
             for (int t = 0; t < 8; ++t) {
                 v4f v = accf[t];
                 for (int r = 0; r < 4; ++r) v[r] += __shfl_down(v[r], 32, 64);
-                if (lane >= 32) continue;
-                const int i = t >> 1, b = 4 * (t & 1) + bb;
-                for (int r = 0; r < 4; ++r) {
-                    const int av = 4 * (lane >> 4) + r;  // output row = 4 (lane / 16) + r
-                    stage[EMS(av, b, 4 * i + jc)] = (T)v[r];
+                if (lane < 32) {
+                    const int i = t >> 1, b = 4 * (t & 1) + bb;
+                    for (int r = 0; r < 4; ++r) {
+                        const int av = 4 * (lane >> 4) + r;  // output row = 4 (lane / 16) + r
+                        dst[(av * 8 + b) * 16 + 4 * i + jc] = (T)v[r];
+                    }
                 }
             }
-            __syncthreads();
-            for (int v = lane; v < 1024; v += 64) dst[v] = stage[EMS(v >> 7, (v >> 4) & 7, v & 15)];
         }
     }
-    if (lane < 32 && a.resid) {
+    if (RES_MFMA) {
+        if ((lane & 15) < 4 && a.resid) {
+            const int i = lane & 15;
+            for (int r = 0; r < 2; ++r) {
+                const int av = 4 * r + (lane >> 4);
+                if (sM[av] >= 0) atomicAdd(a.resid + 4 * (int64_t)sM[av] + i, (double)accr[r]);
+            }
+        }
+    } else if (lane < 32 && a.resid) {
         const int av = lane & 7, i = lane >> 3;
         if (sM[av] >= 0) atomicAdd(a.resid + 4 * (int64_t)sM[av] + i, (double)R);
     }

@@ -81,6 +81,9 @@ struct AsmArgs {
     const double *f[7];       // ux uy uz p ux0 uy0 uz0
     // parameters
     double rho, mu, dt, theta, c_t, c_i, root_len;
+    // derived by derive_constants: 1/dt, 1/rho, 2/root_len, and the two terms of
+    // tau_M^-2 = c_t/dt^2 + c_i nu^2 G:G = tau_a + tau_b g^2 for G = g I, g = (2/h)^2
+    double idt, irho, two_over_root, tau_a, tau_b;
     // outputs: element-matrix records (1024 entries per work item, record
     // slot0 + item) and the residual (atomic additions)
     void *vals;
@@ -88,6 +91,14 @@ struct AsmArgs {
     void *em;
     int64_t slot0;
 };
+inline void derive_constants(AsmArgs &a) {
+    const double nu = a.mu / a.rho;
+    a.idt = 1.0 / a.dt;
+    a.irho = 1.0 / a.rho;
+    a.two_over_root = 2.0 / a.root_len;
+    a.tau_a = a.c_t / (a.dt * a.dt);
+    a.tau_b = 3.0 * a.c_i * nu * nu;
+}
 void launch_assemble_f64(hipStream_t s, const AsmArgs &a, bool sub, bool mat);
 
 // one unit of the persistent batched assembly: items [first, first + count) of
