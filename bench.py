@@ -85,6 +85,10 @@ def node_xyz(vms, ctx, tree):
         float(1 << tree.max_level) * tree.root_len + np.asarray(tree.origin)
 
 
+# the sources of the element kernel: the recorded traffic holds for this text only
+KERNEL_SOURCES = ("assemble2.hip", "kernels.h", "geom.h")
+
+
 def traffic_for(path, workload, precision):
     """HBM bytes per launch of the dominant kernel from the recorded counter runs
     (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration); None when no
@@ -94,7 +98,8 @@ def traffic_for(path, workload, precision):
         return None
     try:
         tr = json.load(open(path))
-        src = open(os.path.join(ROOT, "paper_2009_00706_amd", "csrc", "assemble2.hip"), "rb").read()
+        src = b"".join(open(os.path.join(ROOT, "paper_2009_00706_amd", "csrc", f), "rb").read()
+                       for f in KERNEL_SOURCES)
     except (OSError, ValueError):
         return None
     sha = hashlib.sha256(src).hexdigest()[:16]
