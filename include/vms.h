@@ -163,6 +163,30 @@ int vms_assemble(vms_ctx *ctx, const vms_fields *f, void *csr_vals, double *resi
  * reduced in FP64 on the device. */
 int vms_apply(vms_ctx *ctx, const vms_fields *f, double *resid, double *norm2);
 
+/* Matrix-free Jacobian action: the product a Newton-Krylov solver asks for
+ * when no matrix is assembled (the matrix-free route of the introduction's
+ * matrix-assembly bullet, the footnote to the elemental matrix assembly of
+ * §"Matrix Assembly on Distributed Octrees", and the conclusion).
+ * y = J(U) x with J the Jacobian that vms_assemble writes at the fields f
+ * (tau_M, tau_C and taubar frozen at f): at every quadrature point the
+ * residual integrand of eq. (vms) with eq. (uprime) and eq. (pprime) is
+ * differentiated along x, then contracted with the basis like the residual;
+ * no element matrix and no CSR value is formed. x, y: DEVICE, n_rows doubles
+ * (dof 4 node + c), y overwritten; rows of inactive nodes get y = x (their
+ * identity blocks). FP64 contexts evaluate in FP64, mixed ones in FP32 with
+ * FP64 accumulation of y. Timing (vms_last_timing): relabel 0, zeroing, OUT
+ * elements, INTERCEPTED elements, identity rows. Errors: VMS_EINVAL (null
+ * argument), VMS_EHIP. */
+int vms_apply_jacobian(vms_ctx *ctx, const vms_fields *f, const double *x, double *y);
+
+/* y = A x with A the matrix of the context's CSR pattern (layouts of
+ * vms_export) and csr_vals its values (DEVICE, nnz entries, double for
+ * VMS_FP64 contexts else float, e.g. from vms_assemble); x, y DEVICE, n_rows
+ * doubles, y overwritten, FP64 accumulation in a fixed order (bitwise
+ * reproducible). The Krylov product with the assembled Jacobian of
+ * Alg. 2. Errors: VMS_EINVAL (null argument), VMS_EHIP. */
+int vms_spmv(vms_ctx *ctx, const void *csr_vals, const double *x, double *y);
+
 /* Exact in-out labels of n points against a surface (Alg. 5's question,
  * answered exactly): px, py, pz DEVICE arrays of n doubles, labels DEVICE
  * uint8 (1 IN or on the surface, 0 OUT). mode VMS_INOUT_EXACT, or

@@ -57,6 +57,8 @@ def lib():
         p = C.c_void_p
         L.or_assemble.restype = C.c_int64
         L.or_assemble.argtypes = [p, C.c_int64] + [p] * 7 + [p] * 7 + [p] * 4 + [C.c_int64, C.c_int64]
+        L.or_apply_jacobian.restype = None
+        L.or_apply_jacobian.argtypes = [p, C.c_int64] + [p] * 7 + [p] * 7 + [p] * 2
         L.or_element.restype = None
         L.or_element.argtypes = [p, C.c_double, C.c_int, p, p, C.c_int, p, p, p, p, p]
         L.or_element_frozen.restype = None
@@ -289,6 +291,30 @@ def assemble(tree, ms, fields, prm=None, mk=None, sub=None, depth=3, vals=True, 
                 k = ms.row_ptr[r] + np.searchsorted(ms.col_idx[ms.row_ptr[r]:ms.row_ptr[r + 1]], r)
                 V[k] = 1.0
     return V, R
+
+
+def jacobian_apply(tree, ms, fields, x, prm=None, mk=None, sub=None, depth=3):
+    """y = J x in FP64 without forming J: the derivative of the residual along
+    x with the stabilisation parameters frozen at the state (the reading of the
+    Jacobian), by one complex-step evaluation per element. Rows of inactive
+    nodes get y = x (their identity blocks, as in ``assemble``)."""
+    prm = prm or params()
+    E = tree.n
+    mk = np.zeros(E, np.uint8) if mk is None else mk
+    off, xi, w = point_lists(tree, mk, sub, depth)
+    h = element_h(tree)
+    f = {k: _c(fields[k], np.float64) for k in ("ux", "uy", "uz", "p", "ux0", "uy0", "uz0")}
+    x = _c(x, np.float64)
+    y = np.zeros(4 * ms.n_nodes)
+    lib().or_apply_jacobian(C.byref(prm), E, _p(_c(ms.nm, np.int32)), _p(_c(ms.masters, np.int32)),
+                            _p(_c(ms.C, np.float64)), _p(_c(h, np.float64)), _p(off),
+                            _p(_c(xi, np.float64)), _p(_c(w, np.float64)), _p(f["ux"]), _p(f["uy"]),
+                            _p(f["uz"]), _p(f["p"]), _p(f["ux0"]), _p(f["uy0"]), _p(f["uz0"]), _p(x),
+                            _p(y))
+    inact = np.nonzero(~ms.node_active)[0]
+    for c in range(4):
+        y[4 * inact + c] = x[4 * inact + c]
+    return y
 
 
 def element(prm, h, xi, w, Cmat, Um, U0m):

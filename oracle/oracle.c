@@ -294,6 +294,64 @@ int64_t or_assemble(const or_params *P, int64_t n_el, const int32_t *el_nm,
     return 0;
 }
 
+/* Jacobian action y += J x, J the Jacobian of the residual with the
+ * stabilisation parameters frozen at the state: the derivative of the
+ * residual along x by one complex-step evaluation per element (the
+ * directional derivative that defines the product, independent of the
+ * column-by-column Jacobian above). x and y are indexed by dof 4 node + c. */
+void or_apply_jacobian(const or_params *P, int64_t n_el, const int32_t *el_nm,
+                       const int32_t *el_master, const double *el_C, const double *el_h,
+                       const int64_t *pt_off, const double *pt_xi, const double *pt_w,
+                       const double *ux, const double *uy, const double *uz, const double *pr,
+                       const double *ux0, const double *uy0, const double *uz0, const double *x,
+                       double *y) {
+    const double eps = 1e-30;
+    for (int64_t e = 0; e < n_el; ++e) {
+        const int nm = el_nm[e];
+        const int npt = (int)(pt_off[e + 1] - pt_off[e]);
+        if (npt == 0 || nm == 0) continue;
+        const int32_t *ms = el_master + 8 * e;
+        const double *C = el_C + 64 * e; /* C[a * 8 + s] */
+        double Uv[8][4], U0v[8][3], Xv[8][4];
+        for (int a = 0; a < 8; ++a) {
+            for (int c = 0; c < 4; ++c) {
+                double su = 0, sx = 0;
+                for (int t = 0; t < nm; ++t) {
+                    const int32_t n = ms[t];
+                    const double un = c == 0 ? ux[n] : c == 1 ? uy[n] : c == 2 ? uz[n] : pr[n];
+                    su += C[a * 8 + t] * un;
+                    sx += C[a * 8 + t] * x[4 * (int64_t)n + c];
+                }
+                Uv[a][c] = su;
+                Xv[a][c] = sx;
+            }
+            for (int c = 0; c < 3; ++c) {
+                double s0 = 0;
+                for (int t = 0; t < nm; ++t) {
+                    const int32_t n = ms[t];
+                    s0 += C[a * 8 + t] * (c == 0 ? ux0[n] : c == 1 ? uy0[n] : uz0[n]);
+                }
+                U0v[a][c] = s0;
+            }
+        }
+        taus *tau = (taus *)malloc(sizeof(taus) * npt);
+        element_taus(P, el_h[e], npt, pt_xi + 3 * pt_off[e], (const double(*)[4])Uv,
+                     (const double(*)[3])U0v, tau);
+        cplx Ucv[8][4], Rv[8][4];
+        for (int a = 0; a < 8; ++a)
+            for (int c = 0; c < 4; ++c) Ucv[a][c] = Uv[a][c] + I * eps * Xv[a][c];
+        element_residual(P, el_h[e], npt, pt_xi + 3 * pt_off[e], pt_w + pt_off[e], tau, Ucv,
+                         (const double(*)[3])U0v, Rv);
+        free(tau);
+        for (int s = 0; s < nm; ++s)
+            for (int c = 0; c < 4; ++c) {
+                cplx v = 0;
+                for (int a = 0; a < 8; ++a) v += C[a * 8 + s] * Rv[a][c];
+                y[4 * (int64_t)ms[s] + c] += cimag(v) / eps;
+            }
+    }
+}
+
 /* Single-element entry for tests: residual and Jacobian in master space. */
 void or_element(const or_params *P, double h, int npt, const double *xi, const double *w, int nm,
                 const double *C, const double *Um, const double *U0m, double *Rm, double *Jm) {

@@ -219,9 +219,14 @@ struct vms_ctx {
     std::vector<int32_t> sub_item_el;  // element of each item (host copy)
     int32_t *d_sub_el = nullptr, *d_sub_cnt = nullptr;
     int64_t *d_sub_off = nullptr;
-    // identity rows of inactive nodes
+    // identity rows of inactive nodes: their CSR places and the node ids
     int64_t n_ones = 0;
     int64_t *d_ones = nullptr;
+    int64_t n_inact = 0;
+    int32_t *d_inact = nullptr;
+    // node-level CSR (block rows, block columns) for the product with the matrix
+    int64_t *d_nrow_ptr = nullptr;
+    int32_t *d_ncol = nullptr;
     // element-matrix records (one per work item: OUT elements first, then the
     // sub-cell items) and, per CSR block, the list of record blocks summed into it
     int64_t n_slots = 0, n_blocks = 0;
@@ -397,6 +402,19 @@ int run_subquad(vms_ctx *c, bool first) {
     vmsk::launch_subquad(c->stream, c->surf.S, g, a, 1);
     HIPCHK(c, hipGetLastError());
     return VMS_OK;
+}
+
+// element data and parameters of the assembly kernels (no work list, no fields)
+vmsk::AsmArgs base_args(vms_ctx *c) {
+    vmsk::AsmArgs a{};
+    a.masters = c->d_masters;
+    a.ccode = c->d_ccode;
+    a.has_hang = c->d_hang;
+    a.level = c->d_level;
+    a.depth = c->prm.quad_depth;
+    vmsk::set_params(a, c->prm.rho, c->prm.mu, c->prm.dt, c->prm.theta, c->prm.c_t, c->prm.c_i,
+                     c->root_len);
+    return a;
 }
 
 }  // namespace
@@ -643,16 +661,19 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
         if (c->markers[e] == 0) stdl.push_back((int32_t)e);
     c->n_std = (int64_t)stdl.size();
     std::vector<int64_t> ones;
+    std::vector<int32_t> inact;
     for (int64_t n = 0; n < m.n_nodes; ++n) {
         if (m.node_active[n]) continue;
-        int64_t deg = m.nrow_ptr[n + 1] - m.nrow_ptr[n];
+        inact.push_back((int32_t)n);
         for (int cc = 0; cc < 4; ++cc) ones.push_back(m.row_ptr[4 * n + cc] + 4 * (int64_t)m.diag_pos[n] + cc);
-        (void)deg;
     }
     c->n_ones = (int64_t)ones.size();
+    c->n_inact = (int64_t)inact.size();
     if (upload(c, &c->d_masters, m.masters) || upload(c, &c->d_ccode, m.ccode) ||
         upload(c, &c->d_hang, m.has_hang) || upload(c, &c->d_level, c->level) ||
-        upload(c, &c->d_std, stdl) || upload(c, &c->d_ones, ones))
+        upload(c, &c->d_std, stdl) || upload(c, &c->d_ones, ones) ||
+        upload(c, &c->d_inact, inact) || upload(c, &c->d_nrow_ptr, m.nrow_ptr) ||
+        upload(c, &c->d_ncol, m.ncol))
         return bail(VMS_ENOMEM);
     rc = build_gather(c, stdl);
     if (rc) return bail(rc);
@@ -770,17 +791,8 @@ static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *re
     const bool fp64 = c->prm.precision == VMS_FP64;
     const int64_t nrows = 4 * c->mesh.n_nodes;
     if (resid) vmsk::launch_fill_f64(c->stream, resid, nrows, 0.0);
-    vmsk::AsmArgs a{};
-    a.masters = c->d_masters;
-    a.ccode = c->d_ccode;
-    a.has_hang = c->d_hang;
-    a.level = c->d_level;
-    a.depth = c->prm.quad_depth;
+    vmsk::AsmArgs a = base_args(c);
     for (int k = 0; k < 7; ++k) a.f[k] = fp[k];
-    a.rho = c->prm.rho; a.mu = c->prm.mu; a.dt = c->prm.dt; a.theta = c->prm.theta;
-    a.c_t = c->prm.c_t; a.c_i = c->prm.c_i; a.root_len = c->root_len;
-    vmsk::derive_constants(a);
-    a.vals = vals;
     a.resid = resid;
     a.em = c->d_em;
     a.slot0 = 0;
@@ -845,6 +857,54 @@ int vms_apply(vms_ctx *c, const vms_fields *f, double *resid, double *norm2) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
         *norm2 = std::sqrt(s);
     }
+    return VMS_OK;
+}
+
+int vms_apply_jacobian(vms_ctx *c, const vms_fields *f, const double *x, double *y) {
+    if (!c || !f || !x || !y) return fail(c, VMS_EINVAL, "null argument");
+    const double *fp[7] = {f->ux, f->uy, f->uz, f->p, f->ux0, f->uy0, f->uz0};
+    for (const double *p : fp)
+        if (!p) return fail(c, VMS_EINVAL, "null field pointer");
+    if (c->timing) {
+        HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+        HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+    }
+    const bool fp64 = c->prm.precision == VMS_FP64;
+    vmsk::launch_fill_f64(c->stream, y, 4 * c->mesh.n_nodes, 0.0);
+    vmsk::AsmArgs a = base_args(c);
+    for (int k = 0; k < 7; ++k) a.f[k] = fp[k];
+    a.resid = y;
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
+    a.n_items = c->n_std;
+    a.items = c->d_std;
+    vmsk::launch_jacobian_action(c->stream, a, false, fp64, x);
+    HIPCHK(c, hipGetLastError());
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
+    if (c->n_sub_items) {
+        a.n_items = c->n_sub_items;
+        a.items = c->d_sub_el;
+        a.pt_off = c->d_sub_off;
+        a.pt_cnt = c->d_sub_cnt;
+        a.entries = c->d_entries;
+        vmsk::launch_jacobian_action(c->stream, a, true, fp64, x);
+        HIPCHK(c, hipGetLastError());
+    }
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[4], c->stream));
+    vmsk::launch_copy_rows(c->stream, x, y, c->d_inact, c->n_inact);
+    HIPCHK(c, hipGetLastError());
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[5], c->stream));
+    return VMS_OK;
+}
+
+int vms_spmv(vms_ctx *c, const void *csr_vals, const double *x, double *y) {
+    if (!c || !csr_vals || !x || !y) return fail(c, VMS_EINVAL, "null argument");
+    if (c->prm.precision == VMS_FP64)
+        vmsk::launch_bspmv_f64(c->stream, c->d_nrow_ptr, c->d_ncol, (const double *)csr_vals, x, y,
+                               c->mesh.n_nodes);
+    else
+        vmsk::launch_bspmv_f32(c->stream, c->d_nrow_ptr, c->d_ncol, (const float *)csr_vals, x, y,
+                               c->mesh.n_nodes);
+    HIPCHK(c, hipGetLastError());
     return VMS_OK;
 }
 
@@ -1019,6 +1079,7 @@ struct vms_batch {
     int precision = 0;
     int tile = 4, groups_per_cu = 8, n_cu = 256;
     std::vector<vmsk::AsmArgs> h_std, h_sub;
+    std::vector<void *> h_vals;  // CSR values of each tree
     vmsk::AsmArgs *d_std = nullptr, *d_sub = nullptr;
     vmsk::BatchUnit *d_units = nullptr;
     int64_t n_units = 0, n_sub_units = 0, units_cap = 0;
@@ -1047,19 +1108,6 @@ int bfail(vms_batch *b, int code, const std::string &m) {
     if (b) b->err = m;
     set_global_err(m);
     return code;
-}
-
-vmsk::AsmArgs base_args(vms_ctx *c) {
-    vmsk::AsmArgs a{};
-    a.masters = c->d_masters;
-    a.ccode = c->d_ccode;
-    a.has_hang = c->d_hang;
-    a.level = c->d_level;
-    a.depth = c->prm.quad_depth;
-    a.rho = c->prm.rho; a.mu = c->prm.mu; a.dt = c->prm.dt; a.theta = c->prm.theta;
-    a.c_t = c->prm.c_t; a.c_i = c->prm.c_i; a.root_len = c->root_len;
-    vmsk::derive_constants(a);
-    return a;
 }
 
 int batch_units(vms_batch *b) {
@@ -1093,7 +1141,7 @@ int batch_tables(vms_batch *b, const vms_fields *f, void *const *vals, double *c
         if (!vals[t]) return bfail(b, VMS_EINVAL, "null csr_vals");
         vmsk::AsmArgs a = base_args(c);
         for (int k = 0; k < 7; ++k) a.f[k] = fp[k];
-        a.vals = vals[t];
+        b->h_vals[t] = vals[t];
         a.resid = resid ? resid[t] : nullptr;
         a.em = c->d_em;
         a.slot0 = 0;
@@ -1127,7 +1175,7 @@ void batch_enqueue(vms_batch *b, bool timed) {
     vmsk::launch_assemble_batch(b->stream, b->precision, b->d_std, b->d_sub, b->d_units, b->n_sub_units,
                                 b->n_units, b->d_counter, b->n_cu * b->groups_per_cu);
     if (timed) (void)hipEventRecord(b->ev[2], b->stream);
-    for (size_t t = 0; t < b->ctx.size(); ++t) gather_csr(b->ctx[t], b->stream, b->h_std[t].vals);
+    for (size_t t = 0; t < b->ctx.size(); ++t) gather_csr(b->ctx[t], b->stream, b->h_vals[t]);
     if (timed) (void)hipEventRecord(b->ev[3], b->stream);
     b->timed = timed;
 }
@@ -1162,6 +1210,7 @@ int vms_batch_create(vms_batch **out, vms_ctx *const *ctxs, int n, void *stream)
         }
     b->h_std.resize(n);
     b->h_sub.resize(n);
+    b->h_vals.assign(n, nullptr);
     if (b->buf.alloc(&b->d_std, (size_t)n) || b->buf.alloc(&b->d_sub, (size_t)n) ||
         b->buf.alloc(&b->d_counter, 2)) {
         delete b;

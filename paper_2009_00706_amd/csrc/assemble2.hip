@@ -218,35 +218,44 @@ __device__ inline void split2hx2(v2f x, v2h &h, v2h &l) {
 // lanes and 32-bit accesses by 32 lanes touch distinct banks):
 //   U(f, s)          fields at the master slots, row stride 9
 //   B(p, k, s)       constrained basis rows, point stride 40
-//   I(p, f, k)       interpolated fields, field stride 5, point stride 35
+//   I(p, f, k)       interpolated fields, field stride 5, point stride 5 NF
 //   D(p, i, j, k, l) coefficient blocks, block stride 17, point stride 276
-constexpr int LU = 9, LB = 40, LI = 35, LDB = 17, LDP = 16 * LDB + 4;
-// PD = points whose D blocks are held at once (FP64: 4, mixed: 8)
-template <typename T, int PD>
+// NF fields: the state (u, p, u_prev: 7), plus the direction (x_u, x_p: 4) in
+// the Jacobian action.
+constexpr int LU = 9, LB = 40, LDB = 17, LDP = 16 * LDB + 4;
+// PD = points whose D blocks are held at once (FP64: 4, mixed: 8); no D area
+// without the matrix
+template <typename T, int PD, bool MAT, int NF>
 struct Smem {
     static constexpr int CP = 8;
-    T sU[7 * LU];
+    T sU[NF * LU];
     T sC[8][8];
     T sB[CP * LB];
     T sQ[CP][NQ2];
     union {  // the interpolated fields are dead once the point quantities exist
-        T sI[CP * LI];
-        T sD[PD * LDP];  // weight folded in
+        T sI[CP * NF * 5];
+        T sD[MAT ? PD * LDP : 1];  // weight folded in
     };
     T sSc[CP];       // fp16 form: per-point power-of-two balance
     int sM[8];
 };
 #define SU(f, s) sU[(f) * LU + (s)]
 #define SB(p, k, s) sB[(p) * LB + (k) * 8 + (s)]
-#define SI(p, f, k) sI[(p) * LI + (f) * 5 + (k)]
+#define SI(p, f, k) sI[(p) * (NF * 5) + (f) * 5 + (k)]
 #define SD(p, i, j, k, l) sD[(p) * LDP + ((i) * 4 + (j)) * LDB + (k) * 4 + (l)]
 
 
 // One work item (an element, or a run of sub-cell points of one element) by
-// one 64-lane workgroup.
-template <typename T, int MODE, bool SUB, bool MAT, int PD>
-__device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item, Smem<T, PD> &sm) {
+// one 64-lane workgroup. JV: the Jacobian action along the direction xd
+// (DEVICE, 4 n_nodes doubles, dof 4 node + c) instead of the residual, no
+// matrix.
+template <typename T, int MODE, bool SUB, bool MAT, int PD, bool JV = false>
+__device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
+                                         Smem<T, PD, MAT, JV ? 11 : 7> &sm,
+                                         const double *xd = nullptr) {
     constexpr int CP = 8;  // points per chunk (one lane group of 8 per point)
+    constexpr int NF = JV ? 11 : 7;
+    static_assert(!(JV && MAT), "the Jacobian action has no matrix");
     static_assert(MODE == 0 || PD == 8, "the mixed forms take 8 points per MFMA k-step");
     static_assert(PD == 4 || PD == 8, "D blocks of 4 or 8 points at a time");
     auto &sU = sm.sU;
@@ -271,9 +280,11 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item, S
         sC[v][s] = code == 3u ? T(1) : (code == 2u ? T(0.5) : (code == 1u ? T(0.25) : T(0)));
     }
     __syncthreads();
-    if (lane < 56) {
-        const int f = lane >> 3, s = lane & 7, m = sM[s];
-        SU(f, s) = m >= 0 ? (T)field_in(a, f)[m] : T(0);
+    for (int idx = lane; idx < NF * 8; idx += 64) {
+        const int f = idx >> 3, s = idx & 7, m = sM[s];
+        double v = 0.0;
+        if (m >= 0) v = f < 7 ? field_in(a, f)[m] : xd[4 * (int64_t)m + (f - 7)];
+        SU(f, s) = (T)v;
     }
     const int npts = SUB ? a.pt_cnt[item] : 8;
     const T rho = (T)a.rho, mu = (T)a.mu, th = (T)a.theta;
@@ -343,10 +354,11 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item, S
             }
         }
         __syncthreads();
-        // ---- phase 2: interpolation of the 7 nodal fields (lane = (p, field))
-        for (int idx = lane; idx < CP * 8; idx += 64) {
-            const int p = idx >> 3, f = idx & 7;
-            if (p < np && f < 7) {
+        // ---- phase 2: interpolation of the nodal fields (lane = (p, field))
+        constexpr int FL = NF > 8 ? 16 : 8;
+        for (int idx = lane; idx < CP * FL; idx += 64) {
+            const int p = idx / FL, f = idx % FL;
+            if (p < np && f < NF) {
                 T v[4] = {T(0), T(0), T(0), T(0)};
                 for (int s = 0; s < 8; ++s) {
                     const T u = SU(f, s);
@@ -360,7 +372,79 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item, S
         // point p evaluate the point state; lane r < 3 writes row / component
         // c = r of it and momentum row c of the residual coefficients r^i[k]
         // (times W), lane r = 3 the scalars and the continuity row.
-        {
+        if constexpr (JV) {
+            // Jacobian action: the same coefficients differentiated along the
+            // direction (fields 7..10: x_u, x_p at the new step) with tau_M,
+            // tau_C and taubar frozen at the state; d(u_theta) = theta x_u,
+            // d(a_t) = x_u / dt, d(p) = x_p
+            const int p = lane >> 3, r = lane & 7;
+            if (p < np && r < 4) {
+                T ut[3], gu[3][3], dut[3], dgu[3][3], dat[3];
+                for (int c = 0; c < 3; ++c) {
+                    ut[c] = th * SI(p, c, 0) + (T(1) - th) * SI(p, 4 + c, 0);
+                    dut[c] = th * SI(p, 7 + c, 0);
+                    dat[c] = SI(p, 7 + c, 0) * idt;
+                    for (int m = 0; m < 3; ++m) {
+                        gu[c][m] = th * SI(p, c, 1 + m) + (T(1) - th) * SI(p, 4 + c, 1 + m);
+                        dgu[c][m] = th * SI(p, 7 + c, 1 + m);
+                    }
+                }
+                T up[3], dup[3];
+                for (int c = 0; c < 3; ++c) {
+                    const T atc = (SI(p, c, 0) - SI(p, 4 + c, 0)) * idt;
+                    const T conv = ut[0] * gu[c][0] + ut[1] * gu[c][1] + ut[2] * gu[c][2];
+                    const T dconv = dut[0] * gu[c][0] + dut[1] * gu[c][1] + dut[2] * gu[c][2] +
+                                    ut[0] * dgu[c][0] + ut[1] * dgu[c][1] + ut[2] * dgu[c][2];
+                    up[c] = rho * (atc + conv) + SI(p, 3, 1 + c);
+                    dup[c] = rho * (dat[c] + dconv) + SI(p, 10, 1 + c);
+                }
+                const T s0 = tau0 + gG * (ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
+                const T tauM = rsq<T>(s0);
+                const T tauC = h2_12 * s0 * tauM;
+                for (int c = 0; c < 3; ++c) {
+                    up[c] *= -tauM;
+                    dup[c] *= -tauM;
+                }
+                const T ddiv = dgu[0][0] + dgu[1][1] + dgu[2][2];
+                const T dpp = -rho * tauC * ddiv;
+                const T upg = gG * (up[0] * up[0] + up[1] * up[1] + up[2] * up[2]);
+                const T tb = upg > T(0) ? rsq<T>(upg) : T(0);
+                T *q = sQ[p];
+                const T W = q[QW];
+                if (r < 3) {
+                    // row c = r: its lane-indexed quantities come from LDS again
+                    const int c = r;
+                    T guc[3], dguc[3], dgcol[3];
+                    for (int m = 0; m < 3; ++m) {
+                        guc[m] = th * SI(p, c, 1 + m) + (T(1) - th) * SI(p, 4 + c, 1 + m);
+                        dguc[m] = th * SI(p, 7 + c, 1 + m);
+                        dgcol[m] = th * SI(p, 7 + m, 1 + c);
+                    }
+                    const T atc = (SI(p, c, 0) - SI(p, 4 + c, 0)) * idt;
+                    const T datc = SI(p, 7 + c, 0) * idt;
+                    const T convc = ut[0] * guc[0] + ut[1] * guc[1] + ut[2] * guc[2];
+                    const T dconvc = dut[0] * guc[0] + dut[1] * guc[1] + dut[2] * guc[2] +
+                                     ut[0] * dguc[0] + ut[1] * dguc[1] + ut[2] * dguc[2];
+                    const T upc = -tauM * (rho * (atc + convc) + SI(p, 3, 1 + c));
+                    const T dupc = -tauM * (rho * (datc + dconvc) + SI(p, 10, 1 + c));
+                    T sv = T(0), dsv = T(0);
+                    for (int m = 0; m < 3; ++m) {
+                        sv += up[m] * guc[m];
+                        dsv += dup[m] * guc[m] + up[m] * dguc[m];
+                    }
+                    const T dpr = SI(p, 10, 0);
+                    q[QRC + 4 * c] = W * (rho * datc + rho * dconvc + dsv);
+                    for (int k = 0; k < 3; ++k)
+                        q[QRC + 4 * c + 1 + k] =
+                            W * (mu * (dguc[k] + dgcol[k]) - (k == c ? dpr + dpp : T(0)) -
+                                 dut[k] * upc - ut[k] * dupc - (dup[k] * upc + up[k] * dupc) * irho +
+                                 tb * (dup[k] * sv + up[k] * dsv));
+                } else {
+                    q[QRC + 12] = W * ddiv;
+                    for (int k = 0; k < 3; ++k) q[QRC + 13 + k] = -W * dup[k] * irho;
+                }
+            }
+        } else {
             const int p = lane >> 3, r = lane & 7;
             if (p < np && r < 4) {
                 T ut[3], gu[3][3], up[3];
@@ -420,8 +504,8 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item, S
         // (p, r): r < 3 the matrix rows c = r, 3 <= r < 6 the vector
         // components c = r - 3. The round trip through LDS bounds the registers
         // the point phase holds.
-        __syncthreads();
-        {
+        if (MAT) {
+            __syncthreads();
             const int p = lane >> 3, r = lane & 7;
             if (p < np && r < 6) {
                 const T *qc = sQ[p];
@@ -681,8 +765,16 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item, S
 
 template <typename T, int MODE, bool SUB, bool MAT>
 __global__ VMS_ASM_BOUNDS(MODE) void k_asm2(AsmArgs a) {
-    __shared__ Smem<T, MODE == 0 ? 4 : 8> sm;
+    __shared__ Smem<T, MODE == 0 ? 4 : 8, MAT, 7> sm;
     asm_item<T, MODE, SUB, MAT, MODE == 0 ? 4 : 8>(a, blockIdx.x, sm);
+}
+
+// Jacobian action y = J x along x (the residual output of a receives y)
+template <typename T, bool SUB>
+__global__ VMS_ASM_BOUNDS(1) void k_asm2_jv(AsmArgs a, const double *x) {
+    constexpr int MODE = sizeof(T) == 8 ? 0 : 1;
+    __shared__ Smem<T, MODE == 0 ? 4 : 8, false, 11> sm;
+    asm_item<T, MODE, SUB, false, MODE == 0 ? 4 : 8, true>(a, blockIdx.x, sm, x);
 }
 
 // Persistent form over many contexts: every workgroup takes units from a
@@ -693,7 +785,7 @@ template <typename T, int MODE, bool SUB>
 __global__ VMS_ASM_BOUNDS(MODE) void k_asm_batch(const AsmArgs *args, const BatchUnit *units,
                                                  int64_t first, int64_t last,
                                                  unsigned long long *counter) {
-    __shared__ Smem<T, MODE == 0 ? 4 : 8> sm;
+    __shared__ Smem<T, MODE == 0 ? 4 : 8, true, 7> sm;
     __shared__ int64_t su;
     __shared__ AsmArgs sa;  // the unit's tree, read from LDS where used
     for (;;) {
@@ -809,6 +901,18 @@ void launch_assemble_mixed(hipStream_t s, const AsmArgs &a, bool sub, bool mat, 
     if (fp16) VMS_L(2);
     else VMS_L(1);
 #undef VMS_L
+}
+
+void launch_jacobian_action(hipStream_t s, const AsmArgs &a, bool sub, bool fp64, const double *x) {
+    if (a.n_items <= 0) return;
+    dim3 grid((unsigned)a.n_items), block(64);
+    if (fp64) {
+        if (sub) hipLaunchKernelGGL((k_asm2_jv<double, true>), grid, block, 0, s, a, x);
+        else hipLaunchKernelGGL((k_asm2_jv<double, false>), grid, block, 0, s, a, x);
+    } else {
+        if (sub) hipLaunchKernelGGL((k_asm2_jv<float, true>), grid, block, 0, s, a, x);
+        else hipLaunchKernelGGL((k_asm2_jv<float, false>), grid, block, 0, s, a, x);
+    }
 }
 
 }  // namespace vmsk

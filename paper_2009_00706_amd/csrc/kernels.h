@@ -79,25 +79,29 @@ struct AsmArgs {
     int32_t depth;
     // fields
     const double *f[7];       // ux uy uz p ux0 uy0 uz0
-    // parameters
-    double rho, mu, dt, theta, c_t, c_i, root_len;
-    // derived by derive_constants: 1/dt, 1/rho, 2/root_len, and the two terms of
+    // parameters: rho, mu, theta, the root edge, and derived by set_params:
+    // 1/dt, 1/rho, 2/root_len and the two terms of
     // tau_M^-2 = c_t/dt^2 + c_i nu^2 G:G = tau_a + tau_b g^2 for G = g I, g = (2/h)^2
+    double rho, mu, theta, root_len;
     double idt, irho, two_over_root, tau_a, tau_b;
     // outputs: element-matrix records (1024 entries per work item, record
     // slot0 + item) and the residual (atomic additions)
-    void *vals;
     double *resid;
     void *em;
     int64_t slot0;
 };
-inline void derive_constants(AsmArgs &a) {
-    const double nu = a.mu / a.rho;
-    a.idt = 1.0 / a.dt;
-    a.irho = 1.0 / a.rho;
-    a.two_over_root = 2.0 / a.root_len;
-    a.tau_a = a.c_t / (a.dt * a.dt);
-    a.tau_b = 3.0 * a.c_i * nu * nu;
+inline void set_params(AsmArgs &a, double rho, double mu, double dt, double theta, double c_t,
+                       double c_i, double root_len) {
+    const double nu = mu / rho;
+    a.rho = rho;
+    a.mu = mu;
+    a.theta = theta;
+    a.root_len = root_len;
+    a.idt = 1.0 / dt;
+    a.irho = 1.0 / rho;
+    a.two_over_root = 2.0 / root_len;
+    a.tau_a = c_t / (dt * dt);
+    a.tau_b = 3.0 * c_i * nu * nu;
 }
 void launch_assemble_f64(hipStream_t s, const AsmArgs &a, bool sub, bool mat);
 
@@ -128,5 +132,17 @@ void launch_set_ones_f64(hipStream_t s, double *vals, const int64_t *idx, int64_
 void launch_set_ones_f32(hipStream_t s, float *vals, const int64_t *idx, int64_t n);
 // sum of squares, FP64, into out[0] (zeroed by the caller)
 void launch_norm2(hipStream_t s, const double *v, int64_t n, double *out);
+// Jacobian action along x: FP64 point work if fp64, else FP32; a.resid
+// receives y (atomic additions, zeroed by the caller)
+void launch_jacobian_action(hipStream_t s, const AsmArgs &a, bool sub, bool fp64, const double *x);
+// y[4 n + c] = x[4 n + c] for the listed nodes (identity rows)
+void launch_copy_rows(hipStream_t s, const double *x, double *y, const int32_t *nodes, int64_t n);
+// y = A x for the CSR of 4x4 node blocks: node row n has blocks
+// [nrow_ptr[n], nrow_ptr[n + 1]) with node columns ncol[b]; its four dof rows
+// are stored one after the other from 16 nrow_ptr[n], 4 deg entries each
+void launch_bspmv_f64(hipStream_t s, const int64_t *nrow_ptr, const int32_t *ncol, const double *vals,
+                      const double *x, double *y, int64_t n_nodes);
+void launch_bspmv_f32(hipStream_t s, const int64_t *nrow_ptr, const int32_t *ncol, const float *vals,
+                      const double *x, double *y, int64_t n_nodes);
 
 }  // namespace vmsk

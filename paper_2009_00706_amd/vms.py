@@ -23,7 +23,8 @@ VMS_RELABEL = 1
 (VMS_EXPORT_NODE_XYZ, VMS_EXPORT_ROW_PTR, VMS_EXPORT_COL_IDX, VMS_EXPORT_MARKERS,
  VMS_EXPORT_VERTEX_LAB, VMS_EXPORT_SUBGP, VMS_EXPORT_MASTERS) = range(1, 8)
 
-EXPORTED = ["vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply", "inout_classify",
+EXPORTED = ["vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply",
+            "vms_apply_jacobian", "vms_spmv", "inout_classify",
             "inout_prepare", "inout_classify_prepared", "inout_release", "vms_stats",
             "vms_mesh_create", "vms_mesh_sizes", "vms_mesh_export", "vms_mesh_destroy",
             "vms_set_timing", "vms_last_timing", "vms_mlp_create", "vms_mlp_get_params",
@@ -78,6 +79,8 @@ def lib():
         L.vms_export.argtypes = [p, u32, p]
         L.vms_assemble.argtypes = [p, C.POINTER(Fields), p, p, u32]
         L.vms_apply.argtypes = [p, C.POINTER(Fields), p, p]
+        L.vms_apply_jacobian.argtypes = [p, C.POINTER(Fields), p, p]
+        L.vms_spmv.argtypes = [p, p, p, p]
         L.inout_classify.argtypes = [C.POINTER(Surface), p, p, p, i64, p, u32, p, p]
         L.inout_prepare.argtypes = [C.POINTER(Surface), p, C.POINTER(p)]
         L.inout_classify_prepared.argtypes = [p, p, p, p, i64, p, u32, p]
@@ -280,6 +283,17 @@ def vms_apply(ctx, fields, resid, want_norm=False):
     return nrm.value if want_norm else None
 
 
+def vms_apply_jacobian(ctx, fields, x, y):
+    """y = J(fields) x, matrix-free (device tensors of n_rows doubles)."""
+    fs = _fields(fields)
+    _check(lib().vms_apply_jacobian(ctx, C.byref(fs), _ptr(x), _ptr(y)), ctx)
+
+
+def vms_spmv(ctx, vals, x, y):
+    """y = A x with the context's CSR pattern and values vals (device tensors)."""
+    _check(lib().vms_spmv(ctx, _ptr(vals), _ptr(x), _ptr(y)), ctx)
+
+
 def inout_classify(surf, px, py, pz, labels, mode=VMS_INOUT_EXACT, mlp=None, stream=None):
     s = make_surface(surf.verts, surf.tris)
     rc = lib().inout_classify(C.byref(s), _ptr(px), _ptr(py), _ptr(pz), px.numel(), _ptr(labels),
@@ -476,6 +490,20 @@ class Assembler:
 
     def apply(self, want_norm=False):
         return vms_apply(self.ctx, self.fields, self.resid, want_norm)
+
+    def jacobian_action(self, x, y=None):
+        """y = J x without the matrix (x: device float64 tensor of n_rows)."""
+        if y is None:
+            y = self.torch.empty_like(x)
+        vms_apply_jacobian(self.ctx, self.fields, x, y)
+        return y
+
+    def spmv(self, x, y=None):
+        """y = A x with the values of the last assemble."""
+        if y is None:
+            y = self.torch.empty_like(x)
+        vms_spmv(self.ctx, self.vals, x, y)
+        return y
 
     def export(self, what):
         return vms_export(self.ctx, what, self.n_oct)

@@ -570,3 +570,62 @@ def test_unsigned_distance_closed_forms_and_brute_force(oracle):
            for t in ico.tris]
     inr = min(abs(np.dot(n / np.linalg.norm(n), ico.verts[t[0]] - c)) for n, t in zip(nrm, ico.tris))
     assert abs(oracle.unsigned_distance(ico, c[None])[0] - inr) <= 1e-15
+
+
+# ---------------------------------------------------------------------------
+# Jacobian action (the matrix-free product): the directional derivative of the
+# residual, one complex-step evaluation per element
+# ---------------------------------------------------------------------------
+
+
+def test_jacobian_action_equals_assembled_jacobian_times_x(oracle):
+    """On a cut, hanging mesh with sub-cell points: the derivative of the
+    residual along x equals the column-by-column Jacobian times x (two
+    independent complex-step formulations), inactive rows included (y = x)."""
+    c = tuple(0.5 + o for o in I.BODY_OFFSET)
+    t = I.sphere_refined_octree(c, 0.25, 2, 4, 1.0)
+    s = I.icosphere(2, 0.25, c)
+    ms0 = oracle.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level)
+    mk, _, _ = oracle.markers(t, ms0, s)
+    ms = oracle.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level, active=mk != oracle.IN)
+    assert ms.n_hanging > 0 and (~ms.node_active).sum() > 0
+    sub = oracle.subquad(t, s, np.nonzero(mk == oracle.INTERCEPTED)[0], 2)
+    xyz = ms.node_xyz_int.astype(np.float64) / float(1 << t.max_level)
+    f = I.make_fields(xyz, 11)
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=4 * ms.n_nodes)
+    V, _ = oracle.assemble(t, ms, f, mk=mk, sub=sub, depth=2, resid=False)
+    rid = np.repeat(np.arange(4 * ms.n_nodes), np.diff(ms.row_ptr))
+    y_ref = np.zeros(4 * ms.n_nodes)
+    np.add.at(y_ref, rid, V * x[ms.col_idx])
+    y = oracle.jacobian_apply(t, ms, f, x, mk=mk, sub=sub, depth=2)
+    assert np.linalg.norm(y - y_ref) <= 1e-13 * np.linalg.norm(y_ref)
+    inact = np.nonzero(~ms.node_active)[0]
+    assert np.array_equal(y[4 * inact], x[4 * inact])
+
+
+def test_jacobian_action_rest_state_closed_form(oracle):
+    """u = u_prev = 0, p = 0 on a uniform mesh, x = a constant velocity c: the
+    fine scales vanish and only the mass term survives, so interior momentum
+    rows are rho h^3 / dt c exactly (the node's basis integrates to h^3) and
+    interior continuity rows are 0 (the integral of grad N_a over its support)."""
+    lev, rho, dt = 3, 1.3, 0.02
+    t = I.uniform_octree(lev)
+    ms = oracle.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level)
+    n = ms.n_nodes
+    z = np.zeros(n)
+    f = {"ux": z, "uy": z, "uz": z, "p": z, "ux0": z, "uy0": z, "uz0": z}
+    cvel = np.array([0.7, -1.1, 0.4])
+    x = np.zeros(4 * n)
+    for k in range(3):
+        x[k::4] = cvel[k]
+    prm = oracle.params(rho=rho, mu=0.05, dt=dt)
+    y = oracle.jacobian_apply(t, ms, f, x, prm=prm)
+    h = 1.0 / (1 << lev)
+    ijk = ms.node_xyz_int // (1 << (t.max_level - lev))
+    interior = np.all((ijk > 0) & (ijk < (1 << lev)), axis=1)
+    assert interior.sum() == ((1 << lev) - 1) ** 3
+    for k in range(3):
+        np.testing.assert_allclose(y[4 * np.nonzero(interior)[0] + k], rho * h ** 3 / dt * cvel[k],
+                                   rtol=1e-13)
+    assert np.abs(y[4 * np.nonzero(interior)[0] + 3]).max() < 1e-15
