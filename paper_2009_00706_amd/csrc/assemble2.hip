@@ -236,7 +236,7 @@ struct Smem {
         T sI[CP * NF * 5];
         T sD[MAT ? PD * LDP : 1];  // weight folded in
     };
-    T sSc[CP];       // fp16 form: per-point power-of-two balance
+    T sSc[CP];       // fp16 form: per-point bound of the contraction operands
     int sM[8];
 };
 #define SU(f, s) sU[(f) * LU + (s)]
@@ -295,8 +295,10 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
     const T gG = (T)gGd;
     const T tau0 = (T)(a.tau_a + a.tau_b * gGd * gGd);
     const T h2_12 = (T)(hd * hd * (1.0 / 12.0));
-    // fp16 form: basis rows scaled by h/2 (values and scaled gradients in [-1, 1])
-    const T bscale = MODE == 2 ? (T)(0.5 * hd) : T(1);
+    // fp16 form: gradient rows of the basis scaled by h/2 (all rows within
+    // [-1, 1]); s16 = exponent of the product scale (accumulators carry 2^s16)
+    const float hhalf = (float)(0.5 * hd), gh = (float)two_over_h;
+    int s16 = INT_MAX;
 
     // stage-2 accumulators and residual
     v4d accd[8];
@@ -350,7 +352,7 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
             for (int k = 0; k < 4; ++k) SB(p, k, s) = b[k];
             if (s == 0) {
                 sQ[p][QW] = (T)w;
-                sSc[p] = T(1);
+                sSc[p] = T(0);
             }
         }
         __syncthreads();
@@ -531,14 +533,6 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
                     q[QCM + c] = tir * upc - tbt * svc;
                     q[QXM + c] = -tbt * upc;
                 }
-                if (MODE == 2 && r == 0) {
-                    // balance a power of two between the two fp16 operands: a product is
-                    // about W (2/h)^2 100 (mass coefficient rho/dt ~ 100 for the workloads)
-                    const float x = (float)((double)qc[QW] * gGd * 100.0);
-                    int ex;
-                    frexpf(x, &ex);
-                    sSc[p] = ldexpf(1.0f, ex / 2);
-                }
             }
         }
         __syncthreads();
@@ -575,6 +569,20 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
                 }
                 for (int k = 0; k < 4; ++k)
                     for (int l = 0; l < 4; ++l) SD(p, i, j, k, l) = D[k][l];
+                if constexpr (MODE == 2) {
+                    // bound of the point's stage-1 operands: row k is sum_l D[k][l] B[l][b]
+                    // with |B| <= 1 for values and <= 2/h for gradients, times 2/h
+                    // for gradient rows (their basis rows carry h/2)
+                    if (p < nd) {
+                        float bnd = 0.f;
+                        for (int k = 0; k < 4; ++k) {
+                            float v = fabsf((float)D[k][0]);
+                            for (int l = 1; l < 4; ++l) v += gh * fabsf((float)D[k][l]);
+                            bnd = fmaxf(bnd, k > 0 ? gh * v : v);
+                        }
+                        atomicMax((int *)&sSc[pb + p], __float_as_int(bnd));  // non-negative floats
+                    }
+                }
             }
             __syncthreads();
             // ---- phase 5: stage 1 (VALU) and stage 2 (MFMA)
@@ -604,11 +612,37 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
                 const int g = lane >> 4, row = lane & 15;
                 const int ar = row & 7;
                 const bool hi_rows = row < 8;
+                // fp16: powers of two put the chunk's largest product near 2^12 and
+                // balance it between the two operands of each point (A about 2^ea, F
+                // about 2^(s16 - ea)): both split terms stay in the normal fp16 range.
+                // A later chunk with larger products lowers s16 and rescales the
+                // accumulators (exact).
+                int ea[2] = {0, 0};
+                if constexpr (MODE == 2) {
+                    float bm = 0.f;
+                    for (int q = 0; q < CP; ++q) bm = fmaxf(bm, (float)sSc[q]);
+                    if (bm > 0.f) {
+                        const int sc = 12 - ilogbf(bm);
+                        if (s16 == INT_MAX) {
+                            s16 = sc;
+                        } else if (sc < s16) {
+                            const float f = ldexpf(1.0f, sc - s16);
+                            for (int t = 0; t < 8; ++t)
+                                for (int r = 0; r < 4; ++r) accf[t][r] *= f;
+                            s16 = sc;
+                        }
+                    }
+                    const int sv = s16 == INT_MAX ? 0 : s16;
+                    for (int pp = 0; pp < 2; ++pp) {
+                        const float bp = (float)sSc[2 * g + pp];
+                        ea[pp] = bp > 0.f ? ((ilogbf(bp) + sv) >> 1) : 0;
+                    }
+                }
                 float Av[8];
                 for (int t = 0; t < 8; ++t) {
                     const int p = 2 * g + (t >> 2), k = t & 3;
-                    float v = (float)SB(p, k, ar) * (float)bscale;
-                    if (MODE == 2) v *= (float)sSc[p];
+                    float v = (float)SB(p, k, ar);
+                    if (MODE == 2) v *= ldexpf(k == 0 ? 1.0f : hhalf, ea[t >> 2]);
                     Av[t] = v;
                 }
                 // basis values of the lane's two points at its two columns b
@@ -616,10 +650,11 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
                 for (int pp = 0; pp < 2; ++pp)
                     for (int bh = 0; bh < 2; ++bh)
                         for (int m = 0; m < 4; ++m) Bc[pp][bh][m] = (float)SB(2 * g + pp, m, 4 * bh + bb);
-                float fs[2] = {1.f, 1.f};
-                if (MODE == 2)
-                    for (int pp = 0; pp < 2; ++pp)
-                        fs[pp] = (float)two_over_h / (float)sSc[2 * g + pp];
+                float fs[2][4];
+                for (int pp = 0; pp < 2; ++pp)
+                    for (int k = 0; k < 4; ++k)
+                        fs[pp][k] = MODE == 2 ? ldexpf(k == 0 ? 1.0f : gh, (s16 == INT_MAX ? 0 : s16) - ea[pp])
+                                              : 1.0f;
                 if (MODE == 1) {
                     v8bf Ahm, Alo;
                     for (int t = 0; t < 8; ++t) {
@@ -679,7 +714,7 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
                                 v2f F;
                                 for (int e = 0; e < 2; ++e)
                                     F[e] = (d[e][0] * Bc[pp][bh][0] + d[e][1] * Bc[pp][bh][1] +
-                                            d[e][2] * Bc[pp][bh][2] + d[e][3] * Bc[pp][bh][3]) * fs[pp];
+                                            d[e][2] * Bc[pp][bh][2] + d[e][3] * Bc[pp][bh][3]) * fs[pp][k + e];
                                 v2h x1, x2;
                                 split2hx2(F, x1, x2);
                                 F1[bh][t] = x1[0]; F1[bh][t + 1] = x1[1];
@@ -725,9 +760,10 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
             }
         } else {
             // rows 8..15 carry the second split term: fold them onto rows 0..7
+            const float unscale = (MODE == 2 && s16 != INT_MAX) ? ldexpf(1.0f, -s16) : 1.0f;
             for (int t = 0; t < 8; ++t) {
                 v4f v = accf[t];
-                for (int r = 0; r < 4; ++r) v[r] += __shfl_down(v[r], 32, 64);
+                for (int r = 0; r < 4; ++r) v[r] = (v[r] + __shfl_down(v[r], 32, 64)) * unscale;
                 if (lane < 32) {
                     const int i = t >> 1, b = 4 * (t & 1) + bb;
                     for (int r = 0; r < 4; ++r) {
