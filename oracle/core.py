@@ -57,6 +57,8 @@ def lib():
         p = C.c_void_p
         L.or_assemble.restype = C.c_int64
         L.or_assemble.argtypes = [p, C.c_int64] + [p] * 7 + [p] * 7 + [p] * 4 + [C.c_int64, C.c_int64]
+        L.or_surface_assemble.restype = C.c_int64
+        L.or_surface_assemble.argtypes = ([p, p, C.c_int64] + [p] * 10 + [p] * 7 + [p] * 4)
         L.or_apply_jacobian.restype = None
         L.or_apply_jacobian.argtypes = [p, C.c_int64] + [p] * 7 + [p] * 7 + [p] * 2
         L.or_element.restype = None
@@ -291,6 +293,113 @@ def assemble(tree, ms, fields, prm=None, mk=None, sub=None, depth=3, vals=True, 
                 k = ms.row_ptr[r] + np.searchsorted(ms.col_idx[ms.row_ptr[r]:ms.row_ptr[r + 1]], r)
                 V[k] = 1.0
     return V, R
+
+
+# Surface quadrature of the weak boundary terms: three points per triangle at
+# barycentric coordinates (2/3, 1/6, 1/6) and permutations, a third of the
+# area each (exact for quadratics).
+SURF_BARY = ((2.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0), (1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0),
+             (1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0))
+
+
+def surface_points(tree, surf, mk):
+    """Surface Gauss points of eq. (weakbc), each in the leaf octant that
+    contains it (half-open boxes at the finest resolution); points in IN
+    octants or outside the domain are dropped. The normal is that of the fluid
+    domain: minus the body's outward normal. Returns el, xi, w, n, tri sorted
+    by element (stable in triangle, then point order)."""
+    v = _c(surf.verts, np.float64)
+    t = _c(surf.tris, np.int64)
+    a, b, c = v[t[:, 0]], v[t[:, 1]], v[t[:, 2]]
+    e1, e2 = b - a, c - a
+    cr = np.stack([e1[:, 1] * e2[:, 2] - e1[:, 2] * e2[:, 1],
+                   e1[:, 2] * e2[:, 0] - e1[:, 0] * e2[:, 2],
+                   e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0]], 1)
+    ln = np.sqrt(cr[:, 0] * cr[:, 0] + cr[:, 1] * cr[:, 1] + cr[:, 2] * cr[:, 2])
+    nf = -cr / ln[:, None]
+    wt = 0.5 * ln / 3.0
+    nt = t.shape[0]
+    x = np.zeros((nt, 3, 3))
+    for k, (l0, l1, l2) in enumerate(SURF_BARY):
+        x[:, k] = (l0 * a + l1 * b) + l2 * c
+    x = x.reshape(-1, 3)
+    tri = np.repeat(np.arange(nt), 3)
+    w = np.repeat(wt, 3)
+    n = np.repeat(nf, 3, axis=0)
+    M = tree.max_level
+    o = np.asarray(tree.origin, np.float64)
+    sc = float(1 << M) / tree.root_len
+    q = np.floor((x - o) * sc).astype(np.int64)
+    inside = np.all((q >= 0) & (q < (1 << M)), axis=1)
+    el = np.full(x.shape[0], -1, np.int64)
+    A = np.stack([tree.ax, tree.ay, tree.az], 1).astype(np.int64)
+    lev = np.asarray(tree.level, np.int64)
+    for L in np.unique(lev):
+        sel = np.nonzero(lev == L)[0]
+        keys = A[sel, 0] | (A[sel, 1] << 21) | (A[sel, 2] << 42)
+        order = np.argsort(keys)
+        ks = keys[order]
+        m = (q >> (M - L)) << (M - L)
+        pk = m[:, 0] | (m[:, 1] << 21) | (m[:, 2] << 42)
+        pos = np.clip(np.searchsorted(ks, pk), 0, ks.size - 1)
+        hit = inside & (ks[pos] == pk)
+        el[hit] = sel[order[pos[hit]]]
+    keep = el >= 0
+    keep[keep] = mk[el[keep]] != IN
+    el, x, w, n, tri = el[keep], x[keep], w[keep], n[keep], tri[keep]
+    side = tree.side().astype(np.float64)
+    h = tree.root_len * (side[el] / float(1 << M))
+    lo = o + tree.root_len * (A[el].astype(np.float64) / float(1 << M))
+    xi = 2.0 * (x - lo) / h[:, None] - 1.0
+    order = np.argsort(el, kind="stable")
+    return {"el": el[order], "xi": xi[order], "w": w[order], "n": n[order], "tri": tri[order],
+            "xyz": x[order]}
+
+
+def weak_bc_tau(tree, surf, sp, mu, c_b):
+    """tau_B = c_b mu / h_b per element of the surface points, h_b the largest
+    distance from the element's fluid (OUT) corners to the surface, at least
+    0.01 h (the remark after eq. (weakbc))."""
+    els = np.unique(sp["el"])
+    h = element_h(tree)[els]
+    A = np.stack([tree.ax, tree.ay, tree.az], 1)[els].astype(np.float64)
+    o = np.asarray(tree.origin, np.float64)
+    lo = o + tree.root_len * A / float(1 << tree.max_level)
+    off = np.array([[(v >> k) & 1 for k in range(3)] for v in range(8)], np.float64)
+    cx = (lo[:, None, :] + h[:, None, None] * off[None]).reshape(-1, 3)
+    lab, _ = label_points(surf, cx)
+    d = unsigned_distance(surf, cx)
+    d = np.where(lab == 0, d, 0.0).reshape(-1, 8).max(1)
+    hb = np.maximum(d, 0.01 * h)
+    return els, c_b * mu / hb
+
+
+def weak_bc(tree, ms, surf, mk, fields, c_b=4.0, g=(0.0, 0.0, 0.0), prm=None, vals=True,
+            resid=True):
+    """Weak boundary terms of eq. (weakbc) (surface terms only), FP64: CSR
+    values of ``ms`` and residual, the Jacobian by complex step with tau_B and
+    the inflow indicator frozen."""
+    prm = prm or params()
+    sp = surface_points(tree, surf, mk)
+    els, tau = weak_bc_tau(tree, surf, sp, prm.mu, c_b)
+    cnt = np.bincount(np.searchsorted(els, sp["el"]), minlength=els.size)
+    off = np.zeros(els.size + 1, np.int64)
+    off[1:] = np.cumsum(cnt)
+    V = np.zeros(ms.nnz) if vals else None
+    R = np.zeros(4 * ms.n_nodes) if resid else None
+    f = {k: _c(fields[k], np.float64) for k in ("ux", "uy", "uz", "p", "ux0", "uy0", "uz0")}
+    gg = _c(np.asarray(g, np.float64), np.float64)
+    rc = lib().or_surface_assemble(C.byref(prm), _p(gg), els.size, _p(_c(els, np.int32)),
+                                   _p(_c(ms.nm, np.int32)), _p(_c(ms.masters, np.int32)),
+                                   _p(_c(ms.C, np.float64)), _p(_c(element_h(tree), np.float64)),
+                                   _p(off), _p(_c(sp["xi"], np.float64)), _p(_c(sp["w"], np.float64)),
+                                   _p(_c(sp["n"], np.float64)), _p(_c(tau, np.float64)),
+                                   _p(f["ux"]), _p(f["uy"]), _p(f["uz"]), _p(f["p"]), _p(f["ux0"]),
+                                   _p(f["uy0"]), _p(f["uz0"]), _p(ms.row_ptr), _p(ms.col_idx),
+                                   _p(V), _p(R))
+    if rc != 0:
+        raise RuntimeError(f"pattern misses an entry of surface item {-rc - 1}")
+    return V, R, sp
 
 
 def jacobian_apply(tree, ms, fields, x, prm=None, mk=None, sub=None, depth=3):

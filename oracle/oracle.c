@@ -352,6 +352,161 @@ void or_apply_jacobian(const or_params *P, int64_t n_el, const int32_t *el_nm,
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Weak (Nitsche) boundary terms of eq. (weakbc) at surface points           */
+/* ------------------------------------------------------------------------ */
+
+/* tau_B (tangential, normal) and the prescribed velocity g on the surface */
+typedef struct { double tauT, tauN, g[3]; } or_wbc;
+
+/* Surface residual of one element at npt surface points: reference
+ * coordinates xi, area weights ws, unit normal n of the fluid domain (into
+ * the body) and the inflow indicator chi (1 where u_theta . n < 0 at the real
+ * state, frozen like the taus). Velocity terms use u_theta, the pressure the
+ * new step, as in the volume terms. For w = N_a e_i and q = N_a:
+ *   -w.(-p n + 2 mu eps(u) n)   = N_a (p n_i - mu sum_k (d_k u_i + d_i u_k) n_k)
+ *   -(2 mu eps(w) n).(u - g)    = -mu ((u - g)_i dN_a/dn + n_i grad N_a . (u - g))
+ *   -(q n).(u - g)              = -N_a n . (u - g)
+ *   -w.rho (u.n)(u - g) (inflow) = -chi rho (u . n) (u - g)_i N_a
+ *   tangential and normal penalties: N_a (tauT ((u-g)_i - n_i (u-g).n) + tauN n_i (u-g).n) */
+static void surface_residual(const or_params *P, const or_wbc *B, double h, int npt,
+                             const double *xi, const double *ws, const double *nrm,
+                             const double *chi, cplx Uv[8][4], const double U0v[8][3],
+                             cplx Rv[8][4]) {
+    const double rho = P->rho, mu = P->mu, th = P->theta;
+    for (int a = 0; a < 8; ++a)
+        for (int c = 0; c < 4; ++c) Rv[a][c] = 0;
+    for (int q = 0; q < npt; ++q) {
+        double N[8], dN[8][3];
+        basis(xi + 3 * q, h, N, dN);
+        const double *n = nrm + 3 * q;
+        const double W = ws[q];
+        cplx ut[3] = {0, 0, 0}, gu[3][3] = {{0}}, p = 0;
+        for (int a = 0; a < 8; ++a) {
+            for (int i = 0; i < 3; ++i) {
+                cplx uth = th * Uv[a][i] + (1.0 - th) * U0v[a][i];
+                ut[i] += N[a] * uth;
+                for (int j = 0; j < 3; ++j) gu[i][j] += dN[a][j] * uth;
+            }
+            p += N[a] * Uv[a][3];
+        }
+        cplx v[3], vn = 0, un = 0;
+        for (int i = 0; i < 3; ++i) {
+            v[i] = ut[i] - B->g[i];
+            vn += v[i] * n[i];
+            un += ut[i] * n[i];
+        }
+        for (int a = 0; a < 8; ++a) {
+            double dnNa = 0;
+            cplx gNv = 0;
+            for (int k = 0; k < 3; ++k) {
+                dnNa += dN[a][k] * n[k];
+                gNv += dN[a][k] * v[k];
+            }
+            for (int i = 0; i < 3; ++i) {
+                cplx epsn = 0;
+                for (int k = 0; k < 3; ++k) epsn += (gu[i][k] + gu[k][i]) * n[k];
+                cplx r = N[a] * (p * n[i] - mu * epsn);
+                r += -mu * (v[i] * dnNa + n[i] * gNv);
+                r += -chi[q] * rho * un * v[i] * N[a];
+                r += N[a] * (B->tauT * (v[i] - n[i] * vn) + B->tauN * n[i] * vn);
+                Rv[a][i] += W * r;
+            }
+            Rv[a][3] += W * (-N[a] * vn);
+        }
+    }
+}
+
+/* Surface terms of the items (one element each, points [pt_off[k],
+ * pt_off[k+1])), residual and complex-step Jacobian (tau_B and the inflow
+ * indicator frozen at the real state), added into the CSR (+=). tau_b holds
+ * each item's tau_B (tangential = normal). Returns 0 or -(k+1) if an entry is
+ * missing from the pattern. */
+int64_t or_surface_assemble(const or_params *P, const double *g, int64_t n_items,
+                            const int32_t *item_el, const int32_t *el_nm,
+                            const int32_t *el_master, const double *el_C, const double *el_h,
+                            const int64_t *pt_off, const double *pt_xi, const double *pt_w,
+                            const double *pt_n, const double *tau_b, const double *ux,
+                            const double *uy, const double *uz, const double *pr,
+                            const double *ux0, const double *uy0, const double *uz0,
+                            const int64_t *row_ptr, const int32_t *col, double *vals,
+                            double *resid) {
+    const double eps = 1e-30;
+    for (int64_t k = 0; k < n_items; ++k) {
+        const int32_t e = item_el[k];
+        const int nm = el_nm[e];
+        const int npt = (int)(pt_off[k + 1] - pt_off[k]);
+        if (npt == 0 || nm == 0) continue;
+        const int32_t *ms = el_master + 8 * e;
+        const double *C = el_C + 64 * (int64_t)e; /* C[a * 8 + s] */
+        const double *xi = pt_xi + 3 * pt_off[k], *ws = pt_w + pt_off[k], *nr = pt_n + 3 * pt_off[k];
+        or_wbc B = {tau_b[k], tau_b[k], {g[0], g[1], g[2]}};
+        double Uv[8][4], U0v[8][3];
+        for (int a = 0; a < 8; ++a) {
+            for (int c = 0; c < 4; ++c) {
+                double su = 0;
+                for (int t = 0; t < nm; ++t) {
+                    const int32_t n = ms[t];
+                    su += C[a * 8 + t] * (c == 0 ? ux[n] : c == 1 ? uy[n] : c == 2 ? uz[n] : pr[n]);
+                }
+                Uv[a][c] = su;
+            }
+            for (int c = 0; c < 3; ++c) {
+                double s0 = 0;
+                for (int t = 0; t < nm; ++t) {
+                    const int32_t n = ms[t];
+                    s0 += C[a * 8 + t] * (c == 0 ? ux0[n] : c == 1 ? uy0[n] : uz0[n]);
+                }
+                U0v[a][c] = s0;
+            }
+        }
+        /* inflow indicator from the real state */
+        double *chi = (double *)malloc(sizeof(double) * npt);
+        for (int q = 0; q < npt; ++q) {
+            double N[8], dN[8][3], un = 0;
+            basis(xi + 3 * q, el_h[e], N, dN);
+            for (int i = 0; i < 3; ++i) {
+                double u = 0;
+                for (int a = 0; a < 8; ++a) u += N[a] * (P->theta * Uv[a][i] + (1.0 - P->theta) * U0v[a][i]);
+                un += u * nr[3 * q + i];
+            }
+            chi[q] = un < 0.0 ? 1.0 : 0.0;
+        }
+        const int nd = nm * 4;
+        double Rm[32], Jm[1024];
+        cplx Ucv[8][4], Rv[8][4];
+        for (int colx = -1; colx < nd; ++colx) {
+            for (int a = 0; a < 8; ++a)
+                for (int c = 0; c < 4; ++c) {
+                    cplx s = Uv[a][c];
+                    if (colx >= 0 && (colx % 4) == c) s += I * eps * C[a * 8 + colx / 4];
+                    Ucv[a][c] = s;
+                }
+            surface_residual(P, &B, el_h[e], npt, xi, ws, nr, chi, Ucv, (const double(*)[3])U0v, Rv);
+            for (int s = 0; s < nm; ++s)
+                for (int c = 0; c < 4; ++c) {
+                    cplx v = 0;
+                    for (int a = 0; a < 8; ++a) v += C[a * 8 + s] * Rv[a][c];
+                    if (colx < 0) Rm[s * 4 + c] = creal(v);
+                    else Jm[(s * 4 + c) * nd + colx] = cimag(v) / eps;
+                }
+        }
+        free(chi);
+        for (int r = 0; r < nd; ++r) {
+            int64_t grow = 4 * (int64_t)ms[r / 4] + (r % 4);
+            if (resid) resid[grow] += Rm[r];
+            if (!vals) continue;
+            for (int c = 0; c < nd; ++c) {
+                int32_t gcol = 4 * ms[c / 4] + (c % 4);
+                int64_t kk = csr_find(row_ptr, col, grow, gcol);
+                if (kk < 0) return -(k + 1);
+                vals[kk] += Jm[r * nd + c];
+            }
+        }
+    }
+    return 0;
+}
+
 /* Single-element entry for tests: residual and Jacobian in master space. */
 void or_element(const or_params *P, double h, int npt, const double *xi, const double *w, int nm,
                 const double *C, const double *Um, const double *U0m, double *Rm, double *Jm) {

@@ -629,3 +629,106 @@ def test_jacobian_action_rest_state_closed_form(oracle):
         np.testing.assert_allclose(y[4 * np.nonzero(interior)[0] + k], rho * h ** 3 / dt * cvel[k],
                                    rtol=1e-13)
     assert np.abs(y[4 * np.nonzero(interior)[0] + 3]).max() < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# Weak (Nitsche) boundary terms, eq. (weakbc): surface points and terms
+# ---------------------------------------------------------------------------
+
+
+def _cut_setup(oracle, r=0.2, lmin=3, lmax=5, beta=1.5, sub=2):
+    c = tuple(0.5 + o for o in I.BODY_OFFSET)
+    t = I.sphere_refined_octree(c, r, lmin, lmax, beta)
+    s = I.icosphere(sub, r, c)
+    ms0 = oracle.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level)
+    mk, _, _ = oracle.markers(t, ms0, s)
+    ms = oracle.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level, active=mk != oracle.IN)
+    return t, s, mk, ms
+
+
+def _fields_const(n, u, p=0.0):
+    f = {"ux": np.full(n, u[0]), "uy": np.full(n, u[1]), "uz": np.full(n, u[2]), "p": np.full(n, p)}
+    f.update({"ux0": f["ux"].copy(), "uy0": f["uy"].copy(), "uz0": f["uz"].copy()})
+    return f
+
+
+def test_surface_points_lie_in_their_leaves(oracle):
+    t, s, mk, ms = _cut_setup(oracle)
+    sp = oracle.surface_points(t, s, mk)
+    assert sp["el"].size == 3 * s.tris.shape[0]   # the sphere lies inside the domain, no IN leaf holds a point
+    assert np.all(np.abs(sp["xi"]) <= 1.0)
+    h = oracle.element_h(t)[sp["el"]]
+    lo = np.stack([t.ax, t.ay, t.az], 1)[sp["el"]] / float(1 << t.max_level)
+    assert np.all((sp["xyz"] >= lo) & (sp["xyz"] < lo + h[:, None]))
+    area = 0.5 * np.linalg.norm(np.cross(s.verts[s.tris[:, 1]] - s.verts[s.tris[:, 0]],
+                                         s.verts[s.tris[:, 2]] - s.verts[s.tris[:, 0]]), axis=1).sum()
+    assert abs(sp["w"].sum() - area) <= 1e-14 * area
+    np.testing.assert_allclose(np.linalg.norm(sp["n"], axis=1), 1.0, rtol=1e-15)
+
+
+def test_weak_bc_zero_for_state_equal_to_g(oracle):
+    """u = g (constant), p = 0: every term of the surface integrals vanishes."""
+    t, s, mk, ms = _cut_setup(oracle)
+    g = (0.3, -0.2, 0.1)
+    _, R, _ = oracle.weak_bc(t, ms, s, mk, _fields_const(ms.n_nodes, g), g=g, vals=False)
+    assert np.abs(R).max() < 1e-17
+
+
+def test_weak_bc_closed_surface_pressure_identity(oracle):
+    """u = g = 0, p = 1: the momentum rows summed over all nodes give the
+    integral of p n over a closed surface, which is zero (the basis is a
+    partition of unity; sum of area times normal over a closed polyhedron);
+    the continuity rows vanish."""
+    t, s, mk, ms = _cut_setup(oracle)
+    _, R, sp = oracle.weak_bc(t, ms, s, mk, _fields_const(ms.n_nodes, (0, 0, 0), 1.0), vals=False)
+    area = sp["w"].sum()
+    for i in range(3):
+        assert abs(R[i::4].sum()) <= 1e-14 * area
+        # a single term is not small: the sum is a cancellation
+        assert np.abs(R[i::4]).max() > 1e-4 * area
+    assert np.abs(R[3::4]).max() == 0.0
+
+
+def test_weak_bc_inflow_flux_through_a_box(oracle):
+    """Axis-aligned box, u = u_prev = (1, 0, 0), p = 0, mu = 0, no penalty:
+    only the inflow term remains, on the face where the flow enters the fluid
+    (x = hi, fluid normal -x); the x-momentum rows summed over all nodes are
+    rho times that face's area, the other rows sum to zero."""
+    lo = np.array([37, 43, 51]) / 128.0
+    hi = np.array([91, 85, 77]) / 128.0
+    s = I.box_surface(lo, hi)
+    t = I.uniform_octree(4)
+    ms0 = oracle.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level)
+    mk, _, _ = oracle.markers(t, ms0, s)
+    ms = oracle.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level, active=mk != oracle.IN)
+    rho = 1.7
+    prm = oracle.params(rho=rho, mu=0.0)
+    _, R, _ = oracle.weak_bc(t, ms, s, mk, _fields_const(ms.n_nodes, (1.0, 0.0, 0.0)), c_b=0.0,
+                             prm=prm, vals=False)
+    a_yz = (hi[1] - lo[1]) * (hi[2] - lo[2])
+    assert abs(R[0::4].sum() - rho * a_yz) <= 1e-14 * rho * a_yz
+    for i in (1, 2, 3):
+        assert abs(R[i::4].sum()) <= 1e-15
+
+
+def test_weak_bc_jacobian_against_central_differences(oracle):
+    """The complex-step Jacobian of the surface terms against central
+    differences of the real residual along a random direction."""
+    t, s, mk, ms = _cut_setup(oracle)
+    xyz = ms.node_xyz_int.astype(np.float64) / float(1 << t.max_level)
+    f = I.make_fields(xyz, 21)
+    V, R, _ = oracle.weak_bc(t, ms, s, mk, f, c_b=4.0, g=(0.1, 0.0, -0.2))
+    rng = np.random.default_rng(2)
+    d = rng.normal(size=4 * ms.n_nodes)
+    rid = np.repeat(np.arange(4 * ms.n_nodes), np.diff(ms.row_ptr))
+    jd = np.zeros(4 * ms.n_nodes)
+    np.add.at(jd, rid, V * d[ms.col_idx])
+    eps = 1e-6
+
+    def res(sign):
+        g = dict(f)
+        for c, k in enumerate(("ux", "uy", "uz", "p")):
+            g[k] = f[k] + sign * eps * d[c::4]
+        return oracle.weak_bc(t, ms, s, mk, g, c_b=4.0, g=(0.1, 0.0, -0.2), vals=False)[1]
+    fd = (res(1) - res(-1)) / (2 * eps)
+    assert np.linalg.norm(fd - jd) <= 1e-7 * np.linalg.norm(jd)
