@@ -86,7 +86,10 @@ enum {
     VMS_EXPORT_SUBGP = 6,      /* int64 [n_subgp] element, int32 [n_subgp] key, uint8 [n_subgp]
                                   level, double [n_subgp][3] xyz; canonical order (elements
                                   ascending, depth-first, children and Gauss points x fastest) */
-    VMS_EXPORT_MASTERS = 7     /* int32 [n_oct][8] master nodes per element slot (-1 unused) */
+    VMS_EXPORT_MASTERS = 7,    /* int32 [n_oct][8] master nodes per element slot (-1 unused) */
+    VMS_EXPORT_SURFGP = 8      /* surface points of the weak boundary terms, n = stats[6]:
+                                  int64 [n] element, double [n][3] reference coordinates,
+                                  double [n] weight, double [n][3] unit normal of the fluid */
 };
 
 /* Linear octree leaves, HOST pointers (copied at vms_create). A leaf at level L
@@ -186,6 +189,26 @@ int vms_apply_jacobian(vms_ctx *ctx, const vms_fields *f, const double *x, doubl
  * reproducible). The Krylov product with the assembled Jacobian of
  * Alg. 2. Errors: VMS_EINVAL (null argument), VMS_EHIP. */
 int vms_spmv(vms_ctx *ctx, const void *csr_vals, const double *x, double *y);
+
+/* Weak (Nitsche) enforcement of u = g on the immersed surface, eq. (weakbc)
+ * with the remark after it (§"Weak Enforcement of Boundary Conditions"): once
+ * enabled, vms_assemble, vms_apply and vms_apply_jacobian add the surface
+ * integrals (consistency, adjoint consistency with the sign of eq. (weakbc),
+ * inflow term on u . n < 0, tangential and normal penalties) to the residual
+ * and the Jacobian. Surface quadrature: three points per triangle
+ * (barycentric 2/3, 1/6, 1/6 and permutations, a third of the area each),
+ * each in the leaf octant that contains it (half-open boxes at the finest
+ * resolution; points in IN octants dropped); n is the unit normal of the fluid
+ * domain (minus the body's outward normal); velocity terms at u_theta, the
+ * pressure at the new step. tau_T = tau_N = c_b mu / h_b per element, h_b the
+ * largest exact distance from the element's OUT corners to the surface, at
+ * least h/100. g: HOST double[3], the prescribed surface velocity (0 for no
+ * slip). The Jacobian freezes tau_B and the inflow indicator. Builds the
+ * surface points, h_b and the record lists on the first call (allocates;
+ * synchronises the stream); enable = 0 switches the terms off. Contexts with
+ * the terms on cannot join a vms_batch. Errors: VMS_EINVAL (no surface, c_b < 0
+ * or non-finite values), VMS_ENOMEM, VMS_EHIP. */
+int vms_set_weak_bc(vms_ctx *ctx, int enable, double c_b, const double *g);
 
 /* Exact in-out labels of n points against a surface (Alg. 5's question,
  * answered exactly): px, py, pz DEVICE arrays of n doubles, labels DEVICE
@@ -299,9 +322,10 @@ int vms_batch_autotune(vms_batch *b, const vms_fields *fields, void *const *vals
 int vms_batch_last_timing(vms_batch *b, float *ms);
 void vms_batch_destroy(vms_batch *b);
 
-/* Counters of a context (HOST out[6]): OUT elements, INTERCEPTED elements,
+/* Counters of a context (HOST out[7]): OUT elements, INTERCEPTED elements,
  * points labelled by the last sub-cell quadrature, degenerate directions
- * abandoned, hanging vertices, kept sub-cell points. */
+ * abandoned, hanging vertices, kept sub-cell points, surface points of the
+ * weak boundary terms (0 while they are off). */
 int vms_stats(vms_ctx *ctx, int64_t *out);
 
 /* Message of the last error on ctx (or of the last failed vms_create /

@@ -45,6 +45,15 @@ struct DevBuf {
         for (void *p : ptrs) (void)hipFree(p);
         ptrs.clear();
     }
+    void free(void *p) {
+        if (!p) return;
+        for (size_t i = 0; i < ptrs.size(); ++i)
+            if (ptrs[i] == p) {
+                (void)hipFree(p);
+                ptrs.erase(ptrs.begin() + (long)i);
+                return;
+            }
+    }
     template <typename T>
     hipError_t alloc(T **p, size_t n) {
         *p = nullptr;
@@ -219,6 +228,18 @@ struct vms_ctx {
     std::vector<int32_t> sub_item_el;  // element of each item (host copy)
     int32_t *d_sub_el = nullptr, *d_sub_cnt = nullptr;
     int64_t *d_sub_off = nullptr;
+    std::vector<int32_t> std_el;  // host copy of the OUT-element list
+    // weak boundary terms (eq. weakbc): surface Gauss points, one item per
+    // element holding points (records after the sub-cell items)
+    bool wbc = false;
+    double wbc_g[3] = {0, 0, 0};
+    int64_t n_surf_items = 0, n_surfgp = 0;
+    std::vector<int32_t> surf_item_el;
+    std::vector<int64_t> surf_pt_el;  // element of each point (export)
+    std::vector<double> surf_xi, surf_w, surf_n;
+    int32_t *d_surf_el = nullptr;
+    int64_t *d_surf_off = nullptr;
+    double *d_surf_xi = nullptr, *d_surf_w = nullptr, *d_surf_n = nullptr, *d_surf_tau = nullptr;
     // identity rows of inactive nodes: their CSR places and the node ids
     int64_t n_ones = 0;
     int64_t *d_ones = nullptr;
@@ -425,10 +446,16 @@ vmsk::AsmArgs base_args(vms_ctx *c) {
 static int build_gather(vms_ctx *c, const std::vector<int32_t> &stdl) {
     const vms::MeshHost &m = c->mesh;
     const std::vector<int32_t> &sub_el = c->sub_item_el;
-    c->n_slots = c->n_std + c->n_sub_items;
+    const std::vector<int32_t> &surf_el = c->surf_item_el;
+    const int64_t n_surf = c->wbc ? c->n_surf_items : 0;
+    c->n_slots = c->n_std + c->n_sub_items + n_surf;
     c->n_blocks = m.nrow_ptr[m.n_nodes];
     if (c->n_slots * 64 > INT32_MAX) return fail(c, VMS_EUNSUPPORTED, "too many element-matrix records");
-    auto el_of = [&](int64_t slot) { return slot < c->n_std ? stdl[slot] : sub_el[slot - c->n_std]; };
+    auto el_of = [&](int64_t slot) {
+        return slot < c->n_std ? stdl[slot]
+               : (slot < c->n_std + c->n_sub_items ? sub_el[slot - c->n_std]
+                                                   : surf_el[slot - c->n_std - c->n_sub_items]);
+    };
     std::vector<int64_t> off(c->n_blocks + 1, 0);
     for (int64_t sl = 0; sl < c->n_slots; ++sl) {
         const int64_t e = el_of(sl);
@@ -465,12 +492,198 @@ static int build_gather(vms_ctx *c, const std::vector<int32_t> &stdl) {
     }
     const size_t esz = c->prm.precision == VMS_FP64 ? 8 : 4;
     char *em = nullptr;
+    // a rebuild (weak boundary terms switched) replaces the previous lists
+    c->buf.free(c->d_cb_off);
+    c->buf.free(c->d_contrib);
+    c->buf.free(c->d_vbase);
+    c->buf.free(c->d_vstride);
+    c->buf.free(c->d_em);
+    c->d_em = nullptr;
     if (upload(c, &c->d_cb_off, off) || upload(c, &c->d_contrib, contrib) ||
         upload(c, &c->d_vbase, vbase) || upload(c, &c->d_vstride, vstride) ||
         c->buf.alloc(&em, (size_t)std::max<int64_t>(c->n_slots, 1) * 1024 * esz))
         return fail(c, VMS_ENOMEM, "device allocation failed (element-matrix records)");
     c->d_em = em;
     return VMS_OK;
+}
+
+// Surface Gauss points of the weak boundary terms (eq. weakbc): three per
+// triangle at barycentric (2/3, 1/6, 1/6) and permutations, a third of the
+// area each; each point belongs to the leaf octant that contains it (half-open
+// boxes at the finest resolution), points in IN octants are dropped; the
+// normal is that of the fluid domain (minus the body's outward normal).
+// tau_B = c_b mu / h_b per element, h_b the largest distance from the
+// element's OUT corners to the surface, at least h/100 (the remark after the
+// equation). Host arithmetic in a fixed order (no contraction) so that points,
+// weights and reference coordinates are reproducible bit for bit.
+#pragma clang fp contract(off)
+static int build_weak_bc(vms_ctx *c, double c_b) {
+    const SurfaceHost &H = c->surf;
+    const int64_t nt = (int64_t)H.tv.size() / 9, E = (int64_t)c->level.size();
+    const int M = c->max_level;
+    const double sc = std::ldexp(1.0, M) / c->root_len;
+    // leaves of each level, sorted by packed integer corner
+    std::vector<std::vector<std::pair<int64_t, int32_t>>> lv(32);
+    for (int64_t e = 0; e < E; ++e)
+        lv[c->level[e]].push_back({(int64_t)c->ax[e] | ((int64_t)c->ay[e] << 21) | ((int64_t)c->az[e] << 42),
+                                   (int32_t)e});
+    for (auto &v : lv) std::sort(v.begin(), v.end());
+    struct SP { int32_t e; double xi[3], w, n[3]; };
+    std::vector<SP> pts;
+    pts.reserve(3 * nt);
+    const double bary[3][3] = {{2.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0}, {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0},
+                               {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0}};
+    for (int64_t t = 0; t < nt; ++t) {
+        const double *A = &H.tv[9 * t], *B = A + 3, *Cc = A + 6;
+        double e1[3], e2[3];
+        for (int d = 0; d < 3; ++d) {
+            e1[d] = B[d] - A[d];
+            e2[d] = Cc[d] - A[d];
+        }
+        const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                              e1[0] * e2[1] - e1[1] * e2[0]};
+        const double ln = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+        const double w = 0.5 * ln / 3.0;
+        for (int k = 0; k < 3; ++k) {
+            double x[3];
+            int64_t q[3];
+            bool inside = true;
+            for (int d = 0; d < 3; ++d) {
+                const double s0 = bary[k][0] * A[d];
+                const double s1 = bary[k][1] * B[d];
+                const double s2 = bary[k][2] * Cc[d];
+                x[d] = (s0 + s1) + s2;
+                q[d] = (int64_t)std::floor((x[d] - c->origin[d]) * sc);
+                inside = inside && q[d] >= 0 && q[d] < ((int64_t)1 << M);
+            }
+            if (!inside) continue;
+            int32_t e = -1;
+            for (int L = 0; L <= M && e < 0; ++L) {
+                const auto &v = lv[L];
+                if (v.empty()) continue;
+                const int sh = M - L;
+                const int64_t key = ((q[0] >> sh) << sh) | (((q[1] >> sh) << sh) << 21) |
+                                    (((q[2] >> sh) << sh) << 42);
+                auto it = std::lower_bound(v.begin(), v.end(), std::make_pair(key, (int32_t)-1));
+                if (it != v.end() && it->first == key) e = it->second;
+            }
+            if (e < 0 || c->markers[e] == 1) continue;
+            SP p;
+            p.e = e;
+            const double h = c->root_len * ((double)((int64_t)1 << (M - c->level[e])) / (double)((int64_t)1 << M));
+            const int32_t Ae[3] = {c->ax[e], c->ay[e], c->az[e]};
+            for (int d = 0; d < 3; ++d) {
+                const double lo = c->origin[d] + c->root_len * ((double)Ae[d] / (double)((int64_t)1 << M));
+                p.xi[d] = 2.0 * (x[d] - lo) / h - 1.0;
+                p.n[d] = -cr[d] / ln;
+            }
+            p.w = w;
+            pts.push_back(p);
+        }
+    }
+    std::stable_sort(pts.begin(), pts.end(), [](const SP &a, const SP &b) { return a.e < b.e; });
+    // items and h_b from the exact distance of the OUT corners
+    std::vector<int32_t> item_el;
+    std::vector<int64_t> off;
+    for (size_t i = 0; i < pts.size(); ++i)
+        if (i == 0 || pts[i].e != pts[i - 1].e) {
+            item_el.push_back(pts[i].e);
+            off.push_back((int64_t)i);
+        }
+    off.push_back((int64_t)pts.size());
+    const int64_t ni = (int64_t)item_el.size(), np = (int64_t)pts.size();
+    std::vector<double> cx, cy, cz;
+    std::vector<int64_t> citem;
+    for (int64_t k = 0; k < ni; ++k) {
+        const int32_t e = item_el[k];
+        const double h = c->root_len * ((double)((int64_t)1 << (M - c->level[e])) / (double)((int64_t)1 << M));
+        const int32_t Ae[3] = {c->ax[e], c->ay[e], c->az[e]};
+        for (int v = 0; v < 8; ++v) {
+            if (c->corner_lab[8 * (int64_t)e + v] != 0) continue;
+            double p[3];
+            for (int d = 0; d < 3; ++d) {
+                const double lo = c->origin[d] + c->root_len * ((double)Ae[d] / (double)((int64_t)1 << M));
+                p[d] = lo + h * (double)((v >> d) & 1);
+            }
+            cx.push_back(p[0]);
+            cy.push_back(p[1]);
+            cz.push_back(p[2]);
+            citem.push_back(k);
+        }
+    }
+    std::vector<double> dist(cx.size(), 0.0), hmax(ni, 0.0);
+    for (int64_t k = 0; k < ni; ++k)
+        hmax[k] = c->root_len * ((double)((int64_t)1 << (M - c->level[item_el[k]])) / (double)((int64_t)1 << M));
+    if (!cx.empty()) {
+        double trunc = 0.0;
+        for (double v : hmax) trunc = std::max(trunc, 4.0 * v);
+        DevBuf tmp;
+        double *dx, *dy, *dz, *dd;
+        const int64_t n = (int64_t)cx.size();
+        if (tmp.alloc(&dx, n) || tmp.alloc(&dy, n) || tmp.alloc(&dz, n) || tmp.alloc(&dd, n))
+            return fail(c, VMS_ENOMEM, "device allocation failed (surface distances)");
+        if (hipMemcpyAsync(dx, cx.data(), n * 8, hipMemcpyHostToDevice, c->stream) ||
+            hipMemcpyAsync(dy, cy.data(), n * 8, hipMemcpyHostToDevice, c->stream) ||
+            hipMemcpyAsync(dz, cz.data(), n * 8, hipMemcpyHostToDevice, c->stream))
+            return fail(c, VMS_EHIP, "device copy failed (surface distances)");
+        int rc = vmsm_sdf(c->stream, H.S, H.tv, H.lo, H.hi, dx, dy, dz, n, trunc, dd);
+        if (rc) return fail(c, rc, "surface distance kernel failed");
+        if (hipMemcpyAsync(dist.data(), dd, n * 8, hipMemcpyDeviceToHost, c->stream) ||
+            hipStreamSynchronize(c->stream))
+            return fail(c, VMS_EHIP, "device copy failed (surface distances)");
+    }
+    std::vector<double> hb(ni, 0.0), tau(ni);
+    for (size_t i = 0; i < dist.size(); ++i) hb[citem[i]] = std::max(hb[citem[i]], std::fabs(dist[i]));
+    for (int64_t k = 0; k < ni; ++k) tau[k] = c_b * c->prm.mu / std::max(hb[k], 0.01 * hmax[k]);
+    c->n_surf_items = ni;
+    c->n_surfgp = np;
+    c->surf_item_el = item_el;
+    c->surf_pt_el.resize(np);
+    c->surf_xi.resize(3 * np);
+    c->surf_w.resize(np);
+    c->surf_n.resize(3 * np);
+    for (int64_t i = 0; i < np; ++i) {
+        c->surf_pt_el[i] = pts[i].e;
+        c->surf_w[i] = pts[i].w;
+        for (int d = 0; d < 3; ++d) {
+            c->surf_xi[3 * i + d] = pts[i].xi[d];
+            c->surf_n[3 * i + d] = pts[i].n[d];
+        }
+    }
+    for (void *p : {(void *)c->d_surf_el, (void *)c->d_surf_off, (void *)c->d_surf_xi, (void *)c->d_surf_w,
+                    (void *)c->d_surf_n, (void *)c->d_surf_tau})
+        c->buf.free(p);
+    if (upload(c, &c->d_surf_el, item_el) || upload(c, &c->d_surf_off, off) ||
+        upload(c, &c->d_surf_xi, c->surf_xi) || upload(c, &c->d_surf_w, c->surf_w) ||
+        upload(c, &c->d_surf_n, c->surf_n) || upload(c, &c->d_surf_tau, tau))
+        return VMS_ENOMEM;
+    return VMS_OK;
+}
+#pragma clang fp contract(on)
+
+static vmsk::SurfArgs surf_args(vms_ctx *c, const double *const fp[7], double *resid) {
+    vmsk::SurfArgs s{};
+    s.masters = c->d_masters;
+    s.ccode = c->d_ccode;
+    s.has_hang = c->d_hang;
+    s.level = c->d_level;
+    s.n_items = c->n_surf_items;
+    s.items = c->d_surf_el;
+    s.pt_off = c->d_surf_off;
+    s.xi = c->d_surf_xi;
+    s.w = c->d_surf_w;
+    s.n = c->d_surf_n;
+    s.tau = c->d_surf_tau;
+    for (int k = 0; k < 7; ++k) s.f[k] = fp[k];
+    s.rho = c->prm.rho;
+    s.mu = c->prm.mu;
+    s.theta = c->prm.theta;
+    s.root_len = c->root_len;
+    for (int k = 0; k < 3; ++k) s.g[k] = c->wbc_g[k];
+    s.resid = resid;
+    s.em = c->d_em;
+    s.slot0 = c->n_std + c->n_sub_items;
+    return s;
 }
 
 // CSR values = sums of the element-matrix records, then identity blocks
@@ -675,6 +888,7 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
         upload(c, &c->d_inact, inact) || upload(c, &c->d_nrow_ptr, m.nrow_ptr) ||
         upload(c, &c->d_ncol, m.ncol))
         return bail(VMS_ENOMEM);
+    c->std_el = stdl;
     rc = build_gather(c, stdl);
     if (rc) return bail(rc);
     if (hipStreamSynchronize(c->stream) != hipSuccess) {
@@ -727,6 +941,18 @@ int vms_export(vms_ctx *c, uint32_t what, void *dst) {
         case VMS_EXPORT_MASTERS:
             std::memcpy(dst, m.masters.data(), 8 * E * 4);
             return VMS_OK;
+        case VMS_EXPORT_SURFGP: {
+            // int64 element, 3 doubles xi, weight, 3 doubles normal per point
+            const int64_t n = c->wbc ? c->n_surfgp : 0;
+            char *o = (char *)dst;
+            if (n) {
+                std::memcpy(o, c->surf_pt_el.data(), 8 * n);
+                std::memcpy(o + 8 * n, c->surf_xi.data(), 24 * n);
+                std::memcpy(o + 32 * n, c->surf_w.data(), 8 * n);
+                std::memcpy(o + 40 * n, c->surf_n.data(), 24 * n);
+            }
+            return VMS_OK;
+        }
         case VMS_EXPORT_SUBGP: {
             const int64_t n = c->n_subgp;
             std::vector<uint32_t> ent(n);
@@ -816,6 +1042,11 @@ static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *re
         else vmsk::launch_assemble_mixed(c->stream, a, true, mat, c->prm.precision == VMS_MIXED_FP16);
         HIPCHK(c, hipGetLastError());
     }
+    if (c->wbc && c->n_surf_items) {
+        // weak boundary terms: records after the sub-cell items
+        vmsk::launch_surface(c->stream, surf_args(c, fp, resid), mat ? 0 : 1, fp64, nullptr);
+        HIPCHK(c, hipGetLastError());
+    }
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[4], c->stream));
     if (mat) {
         gather_csr(c, c->stream, vals);
@@ -889,6 +1120,10 @@ int vms_apply_jacobian(vms_ctx *c, const vms_fields *f, const double *x, double 
         vmsk::launch_jacobian_action(c->stream, a, true, fp64, x);
         HIPCHK(c, hipGetLastError());
     }
+    if (c->wbc && c->n_surf_items) {
+        vmsk::launch_surface(c->stream, surf_args(c, fp, y), 2, true, x);
+        HIPCHK(c, hipGetLastError());
+    }
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[4], c->stream));
     vmsk::launch_copy_rows(c->stream, x, y, c->d_inact, c->n_inact);
     HIPCHK(c, hipGetLastError());
@@ -908,6 +1143,24 @@ int vms_spmv(vms_ctx *c, const void *csr_vals, const double *x, double *y) {
     return VMS_OK;
 }
 
+int vms_set_weak_bc(vms_ctx *c, int enable, double c_b, const double *g) {
+    if (!c) return fail(nullptr, VMS_EINVAL, "null context");
+    if (!enable) {
+        if (!c->wbc) return VMS_OK;
+        c->wbc = false;
+        return build_gather(c, c->std_el);
+    }
+    if (!c->has_surf) return fail(c, VMS_EINVAL, "weak boundary terms need a surface");
+    if (!g || !std::isfinite(c_b) || c_b < 0 || !std::isfinite(g[0]) || !std::isfinite(g[1]) ||
+        !std::isfinite(g[2]))
+        return fail(c, VMS_EINVAL, "bad weak-boundary parameters (c_b >= 0, finite g)");
+    int rc = build_weak_bc(c, c_b);
+    if (rc) return rc;
+    for (int k = 0; k < 3; ++k) c->wbc_g[k] = g[k];
+    c->wbc = true;
+    return build_gather(c, c->std_el);
+}
+
 int vms_stats(vms_ctx *c, int64_t *out) {
     if (!c || !out) return fail(c, VMS_EINVAL, "null argument");
     out[0] = c->n_std;
@@ -916,6 +1169,7 @@ int vms_stats(vms_ctx *c, int64_t *out) {
     out[3] = (int64_t)c->n_degenerate;
     out[4] = c->mesh.n_hanging;
     out[5] = c->n_subgp;
+    out[6] = c->wbc ? c->n_surfgp : 0;
     return VMS_OK;
 }
 
@@ -1194,6 +1448,11 @@ int vms_batch_create(vms_batch **out, vms_ctx *const *ctxs, int n, void *stream)
         b->ctx.push_back(ctxs[i]);
     }
     b->precision = (int)ctxs[0]->prm.precision;
+    for (vms_ctx *c : b->ctx)
+        if (c->wbc) {
+            delete b;
+            return bfail(nullptr, VMS_EUNSUPPORTED, "the batched form has no weak boundary terms");
+        }
     for (vms_ctx *c : b->ctx)
         if ((int)c->prm.precision != b->precision) {
             delete b;

@@ -132,6 +132,28 @@ void launch_set_ones_f64(hipStream_t s, double *vals, const int64_t *idx, int64_
 void launch_set_ones_f32(hipStream_t s, float *vals, const int64_t *idx, int64_t n);
 // sum of squares, FP64, into out[0] (zeroed by the caller)
 void launch_norm2(hipStream_t s, const double *v, int64_t n, double *out);
+// Weak (Nitsche) boundary terms at surface points: items [0, n_items), item
+// k = element items[k] with points [pt_off[k], pt_off[k+1]) (reference
+// coordinates xi, area weights w, unit normals n of the fluid domain), tau_B
+// per item; records at slot0 + k (block-major like the volume records)
+struct SurfArgs {
+    const int32_t *masters;
+    const uint32_t *ccode;
+    const uint8_t *has_hang;
+    const uint8_t *level;
+    int64_t n_items;
+    const int32_t *items;
+    const int64_t *pt_off;
+    const double *xi, *w, *n, *tau;
+    const double *f[7];
+    double rho, mu, theta, root_len, g[3];
+    double *resid;
+    void *em;
+    int64_t slot0;
+};
+// mode 0: records (+ residual if resid), 1: residual only, 2: Jacobian action
+// along x into resid; fp64 selects FP64 records (else FP32)
+void launch_surface(hipStream_t s, const SurfArgs &a, int mode, bool fp64, const double *x);
 // Jacobian action along x: FP64 point work if fp64, else FP32; a.resid
 // receives y (atomic additions, zeroed by the caller)
 void launch_jacobian_action(hipStream_t s, const AsmArgs &a, bool sub, bool fp64, const double *x);

@@ -20,11 +20,12 @@ VMS_OK, VMS_EINVAL, VMS_EMESH, VMS_EHIP, VMS_ENOMEM, VMS_EOVERFLOW, VMS_EUNSUPPO
 VMS_FP64, VMS_MIXED_BF16, VMS_MIXED_FP16 = 0, 1, 2
 VMS_INOUT_EXACT, VMS_INOUT_LEARNED = 0, 1
 VMS_RELABEL = 1
+VMS_EXPORT_SURFGP = 8
 (VMS_EXPORT_NODE_XYZ, VMS_EXPORT_ROW_PTR, VMS_EXPORT_COL_IDX, VMS_EXPORT_MARKERS,
  VMS_EXPORT_VERTEX_LAB, VMS_EXPORT_SUBGP, VMS_EXPORT_MASTERS) = range(1, 8)
 
 EXPORTED = ["vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply",
-            "vms_apply_jacobian", "vms_spmv", "inout_classify",
+            "vms_apply_jacobian", "vms_spmv", "vms_set_weak_bc", "inout_classify",
             "inout_prepare", "inout_classify_prepared", "inout_release", "vms_stats",
             "vms_mesh_create", "vms_mesh_sizes", "vms_mesh_export", "vms_mesh_destroy",
             "vms_set_timing", "vms_last_timing", "vms_mlp_create", "vms_mlp_get_params",
@@ -81,6 +82,7 @@ def lib():
         L.vms_apply.argtypes = [p, C.POINTER(Fields), p, p]
         L.vms_apply_jacobian.argtypes = [p, C.POINTER(Fields), p, p]
         L.vms_spmv.argtypes = [p, p, p, p]
+        L.vms_set_weak_bc.argtypes = [p, C.c_int, C.c_double, p]
         L.inout_classify.argtypes = [C.POINTER(Surface), p, p, p, i64, p, u32, p, p]
         L.inout_prepare.argtypes = [C.POINTER(Surface), p, C.POINTER(p)]
         L.inout_classify_prepared.argtypes = [p, p, p, p, i64, p, u32, p]
@@ -232,10 +234,16 @@ def vms_sizes(ctx):
 
 
 def vms_stats(ctx):
-    v = (C.c_int64 * 6)()
+    v = (C.c_int64 * 7)()
     _check(lib().vms_stats(ctx, v), ctx)
     return {"n_out": v[0], "n_intercepted": v[1], "n_labelled": v[2], "n_degenerate": v[3],
-            "n_hanging": v[4], "n_subgp": v[5]}
+            "n_hanging": v[4], "n_subgp": v[5], "n_surfgp": v[6]}
+
+
+def vms_set_weak_bc(ctx, enable=True, c_b=4.0, g=(0.0, 0.0, 0.0)):
+    """Weak (Nitsche) boundary terms on the immersed surface (see include/vms.h)."""
+    gg = (C.c_double * 3)(*[float(x) for x in g])
+    _check(lib().vms_set_weak_bc(ctx, int(bool(enable)), float(c_b), gg), ctx)
 
 
 def vms_export(ctx, what, n_oct=None):
@@ -252,6 +260,14 @@ def vms_export(ctx, what, n_oct=None):
         out = np.zeros((n_oct, 8), np.uint8)
     elif what == VMS_EXPORT_MASTERS:
         out = np.zeros((n_oct, 8), np.int32)
+    elif what == VMS_EXPORT_SURFGP:
+        n = vms_stats(ctx)["n_surfgp"]
+        raw = np.zeros(n * 64 + 8, np.uint8)
+        _check(lib().vms_export(ctx, what, raw.ctypes.data), ctx)
+        return {"el": raw[:8 * n].view(np.int64).copy(),
+                "xi": raw[8 * n:32 * n].view(np.float64).reshape(n, 3).copy(),
+                "w": raw[32 * n:40 * n].view(np.float64).copy(),
+                "n": raw[40 * n:64 * n].view(np.float64).reshape(n, 3).copy()}
     elif what == VMS_EXPORT_SUBGP:
         n = sz["n_subgp"]
         raw = np.zeros(n * 37 + 8, np.uint8)
@@ -497,6 +513,9 @@ class Assembler:
             y = self.torch.empty_like(x)
         vms_apply_jacobian(self.ctx, self.fields, x, y)
         return y
+
+    def set_weak_bc(self, enable=True, c_b=4.0, g=(0.0, 0.0, 0.0)):
+        vms_set_weak_bc(self.ctx, enable, c_b, g)
 
     def spmv(self, x, y=None):
         """y = A x with the values of the last assemble."""
