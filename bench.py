@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned in-out comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1500, help="elements in the oracle sample")
+    ap.add_argument("--cost-model", default="precision", choices=["precision", "small", "none"],
+                    help="workload on which the eq. (Wpart) cost model predicts the kernel time")
     ap.add_argument("--no-jv", action="store_true",
                     help="skip the Jacobian-product section (matrix-free action and CSR product)")
     ap.add_argument("--copy-calib", type=int, default=0,
@@ -265,6 +267,80 @@ def jacobian_products(torch, vms, tree, surf, f, prec, reps=20):
                     "assembled values; assembly_ms = one steady-state vms_assemble"}
 
 
+def weak_bc_cost(torch, vms, tree, surf, f, prec, reps=20):
+    """Cost of the weak (Nitsche) boundary terms of eq. (weakbc): steady-state
+    assembly with and without them (HIP events on the context stream)."""
+    asm = vms.Assembler(tree, surf, vms.make_params(quad_depth=3, precision=prec))
+    asm.set_fields(f)
+    vms.vms_set_timing(asm.ctx, True)
+
+    def timed():
+        for _ in range(3):
+            asm.assemble()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        st = np.zeros(5)
+        a.record(asm.stream)
+        for _ in range(reps):
+            asm.assemble()
+        b.record(asm.stream)
+        b.synchronize()
+        for _ in range(reps):
+            asm.assemble()
+            st += np.array(vms.vms_last_timing(asm.ctx))
+        return a.elapsed_time(b) / reps, st / reps
+
+    t0, s0 = timed()
+    asm.set_weak_bc(True, 4.0, (0.0, 0.0, 0.0))
+    n_s = vms.vms_stats(asm.ctx)["n_surfgp"]
+    t1, s1 = timed()
+    asm.close()
+    return {"surface_points": int(n_s), "assembly_ms_without": t0, "assembly_ms_with": t1,
+            "surface_kernel_ms": float(s1[3] - s0[3]), "stage_ms_without": s0.tolist(),
+            "stage_ms_with": s1.tolist(),
+            "note": "steady-state vms_assemble (no relabel); the surface kernel runs after the "
+                    "INTERCEPTED items, its time is the difference of that stage; c_b = 4, g = 0"}
+
+
+def cost_model(torch, vms, st, wb, workload_name):
+    """eq. (Wpart) measured on this GPU: T_v (per volume quadrature point, both
+    assembly kernels) and T_s (per surface point of the weak boundary terms)
+    from the calibration workload, then the assembly-kernel time of another
+    workload predicted from its element weights, 8 T_v sum_e W(e), and
+    measured."""
+    from paper_2009_00706_amd import inputs as I
+    s0, s1 = np.array(wb["stage_ms_without"]), np.array(wb["stage_ms_with"])
+    n_v = 8 * st["n_out"] + st["n_subgp"]
+    t_v = (s0[2] + s0[3]) * 1e-3 / n_v
+    t_s = (s1[3] - s0[3]) * 1e-3 / max(wb["surface_points"], 1)
+    r = t_s / t_v
+    tree, surf = I.sphere_workload(lmin=6, lmax=10, beta=3.0) if workload_name == "precision" \
+        else I.sphere_workload(lmin=4, lmax=7, beta=4.0)
+    asm = vms.Assembler(tree, surf, vms.make_params(quad_depth=3))
+    mh_xyz = asm.export(vms.VMS_EXPORT_NODE_XYZ).T.astype(np.float64) / float(1 << tree.max_level)
+    asm.set_fields(I.make_fields(mh_xyz * tree.root_len + np.asarray(tree.origin), 1001))
+    asm.set_weak_bc(True, 4.0, (0.0, 0.0, 0.0))
+    vms.vms_set_timing(asm.ctx, True)
+    for _ in range(3):
+        asm.assemble()
+    stg = np.zeros(5)
+    for _ in range(10):
+        asm.assemble()
+        stg += np.array(vms.vms_last_timing(asm.ctx))
+    stg /= 10
+    w = vms.vms_element_weights(asm.ctx, tree.n, r)
+    asm.close()
+    pred = 8.0 * t_v * w.sum() * 1e3
+    meas = stg[2] + stg[3]
+    return {"T_v_ns": t_v * 1e9, "T_s_ns": t_s * 1e9, "ts_over_tv": r,
+            "calibration": "this workload, FP64: both assembly kernels without, and the surface "
+                           "kernel with, the weak boundary terms",
+            "prediction": {"workload": ("sphere r=0.1, levels 6-10 (" if workload_name == "precision"
+                                        else "sphere r=0.1, levels 4-7 (") + f"{tree.n} octants), "
+                                        "FP64, weak boundary terms on",
+                           "sum_weights": float(w.sum()), "predicted_ms": pred, "measured_ms": meas,
+                           "rel_error": (pred - meas) / meas}}
+
+
 def roofline(k_ms, n_pts, peak, traffic, kname):
     achieved = FLOP_PER_POINT * n_pts / (k_ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
@@ -342,6 +418,10 @@ def main_single(args):
                              "this FP64 GPU result (itself within 1e-12 of the CPU reference)")
     if not args.no_jv:
         out["jacobian_action"] = jacobian_products(torch, vms, tree, surf, f, prec)
+    if surf is not None and not args.no_jv:
+        out["weak_bc"] = weak_bc_cost(torch, vms, tree, surf, f, prec)
+        if prec == vms.VMS_FP64 and args.cost_model != "none":
+            out["cost_model"] = cost_model(torch, vms, st, out["weak_bc"], args.cost_model)
     if surf is not None and not args.no_learned:
         out["learned_inout"] = learned_inout(torch, vms, tree, surf)
     if not args.no_cpu_baseline:

@@ -210,6 +210,16 @@ int vms_spmv(vms_ctx *ctx, const void *csr_vals, const double *x, double *y);
  * or non-finite values), VMS_ENOMEM, VMS_EHIP. */
 int vms_set_weak_bc(vms_ctx *ctx, int enable, double c_b, const double *g);
 
+/* Element weights of eq. (Wpart) (§"Estimation of Weight for the INTERCEPTED
+ * Elements"): w[e] = n_Vgp(e)/n_Tgp + ts_over_tv n_Sgp(e)/n_Tgp with n_Tgp = 8
+ * (trilinear elements), n_Vgp the element's volume quadrature points (8 for
+ * OUT, its kept sub-cell points for INTERCEPTED, 0 for IN) and n_Sgp its
+ * surface points of the weak boundary terms (0 while they are off). OUT
+ * elements weigh 1, IN elements 0. ts_over_tv is the measured ratio of the
+ * cost of a surface point to that of a volume point. w: HOST, n_oct doubles,
+ * octree order. Errors: VMS_EINVAL (null argument, negative ratio). */
+int vms_element_weights(vms_ctx *ctx, double ts_over_tv, double *w);
+
 /* Exact in-out labels of n points against a surface (Alg. 5's question,
  * answered exactly): px, py, pz DEVICE arrays of n doubles, labels DEVICE
  * uint8 (1 IN or on the surface, 0 OUT). mode VMS_INOUT_EXACT, or

@@ -402,6 +402,20 @@ def weak_bc(tree, ms, surf, mk, fields, c_b=4.0, g=(0.0, 0.0, 0.0), prm=None, va
     return V, R, sp
 
 
+def element_weights(tree, mk, sub, sp, ts_over_tv):
+    """eq. (Wpart): W(e) = n_Vgp(e)/n_Tgp + (T_s/T_v) n_Sgp(e)/n_Tgp with
+    n_Tgp = 8 for trilinear elements; n_Vgp = 8 for OUT, the kept sub-cell
+    points for INTERCEPTED, 0 for IN; n_Sgp the element's surface points
+    (``sp`` from ``surface_points``, or None)."""
+    nv = np.where(mk == OUT, 8, 0).astype(np.int64)
+    if sub is not None and sub["el"].size:
+        np.add.at(nv, sub["el"], 1)
+    ns = np.zeros(tree.n, np.int64)
+    if sp is not None and sp["el"].size:
+        np.add.at(ns, sp["el"], 1)
+    return nv.astype(np.float64) / 8.0 + ts_over_tv * (ns.astype(np.float64) / 8.0)
+
+
 def jacobian_apply(tree, ms, fields, x, prm=None, mk=None, sub=None, depth=3):
     """y = J x in FP64 without forming J: the derivative of the residual along
     x with the stabilisation parameters frozen at the state (the reading of the

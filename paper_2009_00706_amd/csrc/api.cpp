@@ -1161,6 +1161,19 @@ int vms_set_weak_bc(vms_ctx *c, int enable, double c_b, const double *g) {
     return build_gather(c, c->std_el);
 }
 
+int vms_element_weights(vms_ctx *c, double ts_over_tv, double *w) {
+    if (!c || !w) return fail(c, VMS_EINVAL, "null argument");
+    if (!std::isfinite(ts_over_tv) || ts_over_tv < 0) return fail(c, VMS_EINVAL, "ts_over_tv must be >= 0");
+    const int64_t E = (int64_t)c->markers.size();
+    std::vector<int64_t> nv(E, 0), ns(E, 0);
+    for (int64_t e = 0; e < E; ++e) nv[e] = c->markers[e] == 0 ? 8 : 0;
+    for (int64_t i = 0; i < c->n_sq && i < (int64_t)c->sq_cnt.size(); ++i) nv[c->sq_el[i]] = c->sq_cnt[i];
+    if (c->wbc)
+        for (int64_t e : c->surf_pt_el) ++ns[e];
+    for (int64_t e = 0; e < E; ++e) w[e] = (double)nv[e] / 8.0 + ts_over_tv * ((double)ns[e] / 8.0);
+    return VMS_OK;
+}
+
 int vms_stats(vms_ctx *c, int64_t *out) {
     if (!c || !out) return fail(c, VMS_EINVAL, "null argument");
     out[0] = c->n_std;

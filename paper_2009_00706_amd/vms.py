@@ -25,7 +25,8 @@ VMS_EXPORT_SURFGP = 8
  VMS_EXPORT_VERTEX_LAB, VMS_EXPORT_SUBGP, VMS_EXPORT_MASTERS) = range(1, 8)
 
 EXPORTED = ["vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply",
-            "vms_apply_jacobian", "vms_spmv", "vms_set_weak_bc", "inout_classify",
+            "vms_apply_jacobian", "vms_spmv", "vms_set_weak_bc", "vms_element_weights",
+            "inout_classify",
             "inout_prepare", "inout_classify_prepared", "inout_release", "vms_stats",
             "vms_mesh_create", "vms_mesh_sizes", "vms_mesh_export", "vms_mesh_destroy",
             "vms_set_timing", "vms_last_timing", "vms_mlp_create", "vms_mlp_get_params",
@@ -83,6 +84,7 @@ def lib():
         L.vms_apply_jacobian.argtypes = [p, C.POINTER(Fields), p, p]
         L.vms_spmv.argtypes = [p, p, p, p]
         L.vms_set_weak_bc.argtypes = [p, C.c_int, C.c_double, p]
+        L.vms_element_weights.argtypes = [p, C.c_double, p]
         L.inout_classify.argtypes = [C.POINTER(Surface), p, p, p, i64, p, u32, p, p]
         L.inout_prepare.argtypes = [C.POINTER(Surface), p, C.POINTER(p)]
         L.inout_classify_prepared.argtypes = [p, p, p, p, i64, p, u32, p]
@@ -238,6 +240,13 @@ def vms_stats(ctx):
     _check(lib().vms_stats(ctx, v), ctx)
     return {"n_out": v[0], "n_intercepted": v[1], "n_labelled": v[2], "n_degenerate": v[3],
             "n_hanging": v[4], "n_subgp": v[5], "n_surfgp": v[6]}
+
+
+def vms_element_weights(ctx, n_oct, ts_over_tv):
+    """Per-element weights of eq. (Wpart) (host array of n_oct doubles)."""
+    w = np.zeros(n_oct, np.float64)
+    _check(lib().vms_element_weights(ctx, float(ts_over_tv), w.ctypes.data), ctx)
+    return w
 
 
 def vms_set_weak_bc(ctx, enable=True, c_b=4.0, g=(0.0, 0.0, 0.0)):

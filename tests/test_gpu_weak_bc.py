@@ -151,3 +151,18 @@ def test_weak_bc_full_size_properties(vms):
     asm.assemble()
     assert torch.equal(asm.vals, plain)
     asm.close()
+
+
+def test_element_weights_match_reference(vms, oracle, reference):
+    """eq. (Wpart) weights from the library equal the reference's, bit for
+    bit, with the surface terms off and on."""
+    tree, surf, ms, mk, sub, f, V, R, sp = reference
+    asm = vms.Assembler(tree, surf, vms.make_params(quad_depth=3))
+    r = 3.7
+    w0 = vms.vms_element_weights(asm.ctx, tree.n, r)
+    assert np.array_equal(w0, oracle.element_weights(tree, mk, sub, None, r))
+    asm.set_weak_bc(True, CB, G)
+    w1 = vms.vms_element_weights(asm.ctx, tree.n, r)
+    assert np.array_equal(w1, oracle.element_weights(tree, mk, sub, sp, r))
+    assert np.all(w1[mk == 0] == 1.0) and np.all(w1[mk == 1] == 0.0)
+    asm.close()

@@ -732,3 +732,15 @@ def test_weak_bc_jacobian_against_central_differences(oracle):
         return oracle.weak_bc(t, ms, s, mk, g, c_b=4.0, g=(0.1, 0.0, -0.2), vals=False)[1]
     fd = (res(1) - res(-1)) / (2 * eps)
     assert np.linalg.norm(fd - jd) <= 1e-7 * np.linalg.norm(jd)
+
+
+def test_element_weights_reduce_to_one_and_zero(oracle):
+    """eq. (Wpart) reduces to 1 for OUT and 0 for IN elements (the text after
+    it); the weights of the INTERCEPTED ones add up to the point counts."""
+    t, s, mk, ms = _cut_setup(oracle)
+    sub = oracle.subquad(t, s, np.nonzero(mk == oracle.INTERCEPTED)[0], 3)
+    sp = oracle.surface_points(t, s, mk)
+    w = oracle.element_weights(t, mk, sub, sp, 2.5)
+    assert np.all(w[mk == oracle.OUT] == 1.0) and np.all(w[mk == oracle.IN] == 0.0)
+    cut = mk == oracle.INTERCEPTED
+    assert abs(8.0 * w[cut].sum() - (sub["el"].size + 2.5 * sp["el"].size)) < 1e-9
