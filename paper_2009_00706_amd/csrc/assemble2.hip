@@ -589,8 +589,9 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
             const int col = lane & 15, bb = col >> 2, jc = col & 3;
             if (MODE == 0) {
                 const int k = lane >> 4, arow = lane & 15;
-#pragma unroll 1
-                for (int p = 0; p < nd; ++p) {
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    if (p >= nd) break;
                     const double A = arow < 8 ? (double)SB(pb + p, k, arow) : 0.0;
                     const double rc = arow < 4 ? (double)sQ[pb + p][QRC + 4 * (arow & 3) + k] : 0.0;
                     accr = __builtin_amdgcn_mfma_f64_16x16x4f64(A, rc, accr, 0, 0, 0);
