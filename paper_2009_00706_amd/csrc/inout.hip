@@ -92,11 +92,15 @@ constexpr int SQ_KEYS = 4096;    // key space 8^(D+1) at depth 3
 constexpr int SQ_BTMAX = 64;     // background triangles staged in LDS
 
 // Exact label of P by local segments to the element corners V, with the
-// element's background triangles read from LDS (tv: 9 doubles, tb: box).
+// element's background triangles read from LDS (tv: 9 doubles, tb: box);
+// corners tried from v0 (the one nearest P: shortest segment, fewest
+// triangle boxes crossed) in the order v0 ^ j.
 __device__ static int local_label_lds(const SurfDev &S, const double *P, const double (*V)[3],
                                       const uint8_t *vlab, const double (*tv)[9],
-                                      const double (*tb)[6], int nbt, unsigned long long *ndeg) {
-    for (int v = 0; v < 8; ++v) {
+                                      const double (*tb)[6], int nbt, unsigned long long *ndeg,
+                                      int v0) {
+    for (int j = 0; j < 8; ++j) {
+        const int v = v0 ^ j;
         int cnt = 0;
         bool deg = false;
         const double *Q = V[v];
@@ -198,8 +202,13 @@ __global__ __launch_bounds__(64) void k_subquad(SurfDev S, GeoArgs g, SubqArgs a
                 for (int ax = 0; ax < 3; ++ax)
                     P[ax] = point_coord(g.origin[ax], g.root_len, scF, A[ax], S_l,
                                         ((gp >> ax) & 1) ? VMS_GP : VMS_GM);
-                lab = staged ? local_label_lds(S, P, V, vl, tv, tb, nbt, a.ndeg)
-                             : local_label(S, P, V, vl, bt, nbt, a.ndeg);
+                // the corner nearest P: the element octant of P's sub-cell (a
+                // sub-cell of level 1 or deeper never straddles the element's midplanes)
+                int v0 = 0;
+                for (int ax = 0; ax < 3; ++ax)
+                    if (2 * (A[ax] - A0[ax]) + S_l > SE) v0 |= 1 << ax;
+                lab = staged ? local_label_lds(S, P, V, vl, tv, tb, nbt, a.ndeg, v0)
+                             : local_label(S, P, V, vl, bt, nbt, a.ndeg, v0);
                 ++nlab;
             }
             // labels of the 8 points of each cell in this chunk

@@ -10,7 +10,8 @@
 //   * local_label: label(V) XOR parity(P -> V) for a corner V of the element
 //     holding P, against the element's background triangles B_T (every
 //     triangle whose box meets the closed element, so every triangle the
-//     segment can cross). Corners are tried in order; ray_label is the last
+//     segment can cross). Corners are tried starting from a given one (the
+//     nearest, for short segments) in the order v0 ^ j; ray_label is the last
 //     resort.
 #pragma once
 #include "geom.h"
@@ -96,8 +97,9 @@ __device__ static int ray_label(const SurfDev &S, const double *P, unsigned long
 
 __device__ static int local_label(const SurfDev &S, const double *P, const double (*V)[3],
                            const uint8_t *vlab, const int32_t *bt, int nbt,
-                           unsigned long long *ndeg) {
-    for (int v = 0; v < 8; ++v) {
+                           unsigned long long *ndeg, int v0 = 0) {
+    for (int j = 0; j < 8; ++j) {
+        const int v = v0 ^ j;
         int cnt = 0;
         bool deg = false;
         for (int i = 0; i < nbt; ++i) {
