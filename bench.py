@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="sphere", choices=["sphere", "uniform16", "batch64"])
+    ap.add_argument("--workload", default="sphere", choices=["sphere", "uniform16", "precision", "batch64"])
     ap.add_argument("--precision", default=None, choices=["fp64", "bf16", "fp16"])
     ap.add_argument("--n-trees", type=int, default=64)
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16/FP16 comparison")
@@ -78,6 +78,12 @@ def workload(name):
         return I.uniform_octree(4), None, {
             "workload": "uniform 16^3 octants on the unit cube (4096 OUT elements, 4913 nodes)",
             "octants": 4096}
+    if name == "precision":
+        tree, surf = I.sphere_workload(lmin=6, lmax=10, beta=3.0)
+        return tree, surf, {
+            "workload": "immersed sphere r=0.1 (icosphere 4, 5120 triangles), octree levels 6-10 "
+                        f"refined at the surface ({tree.n} octants), sub-cell quadrature depth 3",
+            "octants": tree.n}
     tree, surf = I.sphere_workload()
     return tree, surf, {
         "workload": "immersed sphere r=0.1 (icosphere 4, 5120 triangles), octree levels 5-8 "
