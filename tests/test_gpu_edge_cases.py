@@ -1,0 +1,86 @@
+"""Degenerate cases of the method, GPU against the CPU reference.
+
+* A body that contains the whole domain: every element IN, no active node;
+  the matrix is the identity (diagonal blocks only), the residual zero, and
+  both Jacobian products return x.
+* A body smaller than one element: no corner is solid, so every element is
+  OUT (the marker rule of Alg. 4) and no sub-cell quadrature happens, but the
+  weak boundary terms still live on the body's surface points, inside one OUT
+  element: residual and Jacobian to 1e-12 against the reference.
+"""
+import numpy as np
+import pytest
+
+from paper_2009_00706_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vms():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2009_00706_amd import vms as V
+    V.lib()
+    return V
+
+
+def node_xyz(asm, tree):
+    return asm.export(1).T.astype(np.float64) / float(1 << tree.max_level) * tree.root_len + \
+        np.asarray(tree.origin)
+
+
+def test_body_containing_the_domain(vms, oracle):
+    import torch
+    t = I.uniform_octree(2)
+    s = I.box_surface(np.array([-0.1, -0.1, -0.1]), np.array([1.1, 1.1, 1.1]))
+    asm = vms.Assembler(t, s, vms.make_params(quad_depth=3))
+    assert np.all(asm.export(vms.VMS_EXPORT_MARKERS) == 1)
+    ms = oracle.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level, active=np.zeros(t.n, bool))
+    assert asm.sizes["nnz"] == ms.nnz == 16 * ms.n_nodes
+    assert np.array_equal(asm.export(vms.VMS_EXPORT_COL_IDX), ms.col_idx)
+    asm.set_fields(I.make_fields(node_xyz(asm, t), 3))
+    asm.assemble()
+    torch.cuda.synchronize()
+    rp = ms.row_ptr
+    rid = np.repeat(np.arange(rp.size - 1), np.diff(rp))
+    assert np.array_equal(asm.vals.cpu().numpy(), (ms.col_idx == rid).astype(np.float64))
+    assert asm.resid.abs().max().item() == 0.0
+    x = torch.as_tensor(np.random.default_rng(1).normal(size=asm.sizes["n_rows"]), device="cuda")
+    assert torch.equal(asm.jacobian_action(x), x)
+    assert torch.equal(asm.spmv(x), x)
+    asm.set_weak_bc(True, 4.0, (0.0, 0.0, 0.0))   # every surface point is outside the domain
+    assert vms.vms_stats(asm.ctx)["n_surfgp"] == 0
+    asm.close()
+
+
+def test_body_inside_one_element_weak_terms(vms, oracle):
+    import torch
+    t = I.uniform_octree(2)
+    s = I.icosphere(1, 0.05, (0.375 + 1e-6 * np.pi, 0.375 + 1e-6, 0.375 + 2e-6))
+    O = oracle
+    ms0 = O.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level)
+    mk, _, _ = O.markers(t, ms0, s)
+    assert np.all(mk == O.OUT)
+    ms = O.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level, active=mk != O.IN)
+    asm = vms.Assembler(t, s, vms.make_params(quad_depth=3))
+    assert np.array_equal(asm.export(vms.VMS_EXPORT_MARKERS), mk)
+    f = I.make_fields(node_xyz(asm, t), 3)
+    asm.set_fields(f)
+    asm.set_weak_bc(True, 4.0, (0.2, 0.0, 0.0))
+    g = asm.export(vms.VMS_EXPORT_SURFGP)
+    V, R = O.assemble(t, ms, f, mk=mk, depth=3)
+    Vs, Rs, sp = O.weak_bc(t, ms, s, mk, f, c_b=4.0, g=(0.2, 0.0, 0.0))
+    assert sp["el"].size == 3 * s.tris.shape[0] and np.unique(sp["el"]).size == 1
+    for k in ("el", "xi", "w", "n"):
+        assert np.array_equal(g[k], sp[k]), k
+    asm.assemble()
+    torch.cuda.synchronize()
+    vals, res = asm.vals.cpu().numpy(), asm.resid.cpu().numpy()
+    R_vol = R
+    V, R = V + Vs, R + Rs
+    assert np.linalg.norm(vals - V) <= 1e-12 * np.linalg.norm(V)
+    assert np.linalg.norm(res - R) <= 1e-12 * np.linalg.norm(R)
+    # the surface terms are there: far above the tolerance
+    assert np.linalg.norm(res - R_vol) > 1e-6 * np.linalg.norm(R)
+    asm.close()
