@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -14,6 +17,7 @@
 #include "geom.h"
 #include "kernels.h"
 #include "mesh.h"
+#include "par.h"
 #include "mlp.h"
 
 using vmsk::SurfDev;
@@ -456,40 +460,59 @@ static int build_gather(vms_ctx *c, const std::vector<int32_t> &stdl) {
                : (slot < c->n_std + c->n_sub_items ? sub_el[slot - c->n_std]
                                                    : surf_el[slot - c->n_std - c->n_sub_items]);
     };
+    // counted and filled on worker threads; each block's list is then sorted,
+    // which gives the ascending record order of a serial fill
     std::vector<int64_t> off(c->n_blocks + 1, 0);
-    for (int64_t sl = 0; sl < c->n_slots; ++sl) {
-        const int64_t e = el_of(sl);
-        for (int s = 0; s < 8; ++s) {
-            const int ms = m.masters[8 * e + s];
-            if (ms < 0) continue;
-            for (int t = 0; t < 8; ++t)
-                if (m.masters[8 * e + t] >= 0) ++off[m.nrow_ptr[ms] + m.el_kk[64 * e + 8 * s + t] + 1];
+    vms::parallel_for(c->n_slots, [&](int64_t b, int64_t f, int) {
+        for (int64_t sl = b; sl < f; ++sl) {
+            const int64_t e = el_of(sl);
+            for (int s = 0; s < 8; ++s) {
+                const int ms = m.masters[8 * e + s];
+                if (ms < 0) continue;
+                for (int t = 0; t < 8; ++t)
+                    if (m.masters[8 * e + t] >= 0)
+                        __atomic_fetch_add(&off[m.nrow_ptr[ms] + m.el_kk[64 * e + 8 * s + t] + 1], 1,
+                                           __ATOMIC_RELAXED);
+            }
         }
-    }
+    });
     for (int64_t b = 0; b < c->n_blocks; ++b) off[b + 1] += off[b];
     std::vector<int32_t> contrib(off[c->n_blocks]);
-    std::vector<int64_t> pos(off.begin(), off.end() - 1);
-    for (int64_t sl = 0; sl < c->n_slots; ++sl) {
-        const int64_t e = el_of(sl);
-        for (int s = 0; s < 8; ++s) {
-            const int ms = m.masters[8 * e + s];
-            if (ms < 0) continue;
-            for (int t = 0; t < 8; ++t)
-                if (m.masters[8 * e + t] >= 0)
-                    contrib[pos[m.nrow_ptr[ms] + m.el_kk[64 * e + 8 * s + t]]++] = (int32_t)(sl * 64 + 8 * s + t);
-        }
+    {
+        std::vector<int64_t> pos(off.begin(), off.end() - 1);
+        vms::parallel_for(c->n_slots, [&](int64_t b, int64_t f, int) {
+            for (int64_t sl = b; sl < f; ++sl) {
+                const int64_t e = el_of(sl);
+                for (int s = 0; s < 8; ++s) {
+                    const int ms = m.masters[8 * e + s];
+                    if (ms < 0) continue;
+                    for (int t = 0; t < 8; ++t)
+                        if (m.masters[8 * e + t] >= 0) {
+                            const int64_t at = __atomic_fetch_add(
+                                &pos[m.nrow_ptr[ms] + m.el_kk[64 * e + 8 * s + t]], 1, __ATOMIC_RELAXED);
+                            contrib[at] = (int32_t)(sl * 64 + 8 * s + t);
+                        }
+                }
+            }
+        });
     }
+    vms::parallel_for(c->n_blocks, [&](int64_t b, int64_t f, int) {
+        for (int64_t k = b; k < f; ++k)
+            if (off[k + 1] - off[k] > 1) std::sort(contrib.begin() + off[k], contrib.begin() + off[k + 1]);
+    });
     // CSR place of entry (i, j) of block b in node row n: 16 nrow_ptr[n] + 4 (b - nrow_ptr[n])
     // + i 4 deg(n) + j
     std::vector<int64_t> vbase(c->n_blocks);
     std::vector<int32_t> vstride(c->n_blocks);
-    for (int64_t n = 0; n < m.n_nodes; ++n) {
-        const int64_t b0 = m.nrow_ptr[n], deg = m.nrow_ptr[n + 1] - b0;
-        for (int64_t b = b0; b < m.nrow_ptr[n + 1]; ++b) {
-            vbase[b] = 16 * b0 + 4 * (b - b0);
-            vstride[b] = (int32_t)(4 * deg);
+    vms::parallel_for(m.n_nodes, [&](int64_t nb, int64_t nf, int) {
+        for (int64_t n = nb; n < nf; ++n) {
+            const int64_t b0 = m.nrow_ptr[n], deg = m.nrow_ptr[n + 1] - b0;
+            for (int64_t b = b0; b < m.nrow_ptr[n + 1]; ++b) {
+                vbase[b] = 16 * b0 + 4 * (b - b0);
+                vstride[b] = (int32_t)(4 * deg);
+            }
         }
-    }
+    });
     const size_t esz = c->prm.precision == VMS_FP64 ? 8 : 4;
     char *em = nullptr;
     // a rebuild (weak boundary terms switched) replaces the previous lists
@@ -715,6 +738,21 @@ void vms_destroy(vms_ctx *ctx) {
     delete ctx;
 }
 
+// Set-up stage times on stderr when the environment sets VMS_SETUP_LOG (the
+// host mesh work of a 10^7-octant tree takes tens of seconds).
+struct StageLog {
+    bool on = std::getenv("VMS_SETUP_LOG") != nullptr;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now(), t = t0;
+    void operator()(const char *what) {
+        if (!on) return;
+        const auto n = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[vms setup] %-28s %8.2f s (total %8.2f s)\n", what,
+                     std::chrono::duration<double>(n - t).count(), std::chrono::duration<double>(n - t0).count());
+        std::fflush(stderr);
+        t = n;
+    }
+};
+
 int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
                const vms_params *prm, void *stream) {
     if (!out) return fail(nullptr, VMS_EINVAL, "null output pointer");
@@ -759,8 +797,10 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
         rc = check_watertight(surf, err);
         if (rc) { c->err = err; return bail(rc); }
     }
+    StageLog stage;
     vms::TreeIn ti{E, c->ax.data(), c->ay.data(), c->az.data(), c->level.data(), tree->max_level};
     rc = vms::derive_mesh(ti, c->mesh, err);
+    stage("nodes and constraints");
     if (rc) { c->err = err; return bail(rc == -2 ? VMS_EMESH : VMS_EINVAL); }
     vms::MeshHost &m = c->mesh;
     if (c->buf.alloc(&c->d_counters, 2) || c->buf.alloc(&c->d_norm, 1) ||
@@ -821,6 +861,7 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
         }
     }
 
+    stage("corner labels and markers");
     // ---- intercepted elements: background triangles, sub-cell quadrature
     for (int64_t e = 0; e < E; ++e)
         if (c->markers[e] == 2) c->sq_el.push_back((int32_t)e);
@@ -842,8 +883,10 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
             upload(c, &c->d_bt_off, bt_off) || upload(c, &c->d_bt_ids, bt_ids) ||
             c->buf.alloc(&c->d_sq_cnt, c->n_sq))
             return bail(VMS_ENOMEM);
+        stage("background triangles");
         rc = run_subquad(c, true);
         if (rc) return bail(rc);
+        stage("sub-cell quadrature");
         // split every element's point list into work items of at most ITEM_PTS
         // points (partial element matrices are summed by the atomic scatter)
         const int ITEM_PTS = VMS_ITEM_PTS;
@@ -867,6 +910,7 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
     for (int64_t e = 0; e < E; ++e) active[e] = c->markers[e] != 1;
     rc = vms::build_pattern(m, active, err);
     if (rc) { c->err = err; return bail(rc == -6 ? VMS_EUNSUPPORTED : VMS_EINVAL); }
+    stage("CSR pattern");
 
     // ---- device element data and work lists
     std::vector<int32_t> stdl, cutl;
@@ -889,8 +933,10 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
         upload(c, &c->d_ncol, m.ncol))
         return bail(VMS_ENOMEM);
     c->std_el = stdl;
+    stage("element data upload");
     rc = build_gather(c, stdl);
     if (rc) return bail(rc);
+    stage("record gather lists");
     if (hipStreamSynchronize(c->stream) != hipSuccess) {
         c->err = "device synchronisation failed at create";
         return bail(VMS_EHIP);
@@ -930,7 +976,7 @@ int vms_export(vms_ctx *c, uint32_t what, void *dst) {
             std::memcpy(dst, m.row_ptr.data(), m.row_ptr.size() * 8);
             return VMS_OK;
         case VMS_EXPORT_COL_IDX:
-            std::memcpy(dst, m.col_idx.data(), m.col_idx.size() * 4);
+            vms::fill_col_idx(m, (int32_t *)dst);
             return VMS_OK;
         case VMS_EXPORT_MARKERS:
             std::memcpy(dst, c->markers.data(), E);
@@ -1326,7 +1372,7 @@ int vms_mesh_export(vms_mesh *h, uint32_t what, void *dst) {
             return VMS_OK;
         }
         case VMS_EXPORT_ROW_PTR: std::memcpy(dst, m.row_ptr.data(), m.row_ptr.size() * 8); return VMS_OK;
-        case VMS_EXPORT_COL_IDX: std::memcpy(dst, m.col_idx.data(), m.col_idx.size() * 4); return VMS_OK;
+        case VMS_EXPORT_COL_IDX: vms::fill_col_idx(m, (int32_t *)dst); return VMS_OK;
         case VMS_EXPORT_MASTERS: std::memcpy(dst, m.masters.data(), m.masters.size() * 4); return VMS_OK;
         default: return fail(nullptr, VMS_EINVAL, "unsupported export selector for a host mesh");
     }

@@ -26,8 +26,7 @@ struct MeshHost {
     // pattern
     std::vector<int64_t> nrow_ptr;    // node-level rows
     std::vector<int32_t> ncol;
-    std::vector<int64_t> row_ptr;     // dof-level CSR
-    std::vector<int32_t> col_idx;
+    std::vector<int64_t> row_ptr;     // dof-level CSR (its column indices: fill_col_idx)
     std::vector<int64_t> el_rowbase;  // [E][8] first entry of dof row 4 m_s
     std::vector<int32_t> el_rowlen;   // [E][8] entries per dof row of m_s (4 deg)
     std::vector<uint16_t> el_kk;      // [E][8][8] block index of m_t within row m_s
@@ -42,5 +41,7 @@ void unmorton3(uint64_t k, int64_t &x, int64_t &y, int64_t &z);
 int derive_mesh(const TreeIn &t, MeshHost &m, std::string &err);
 // active[e] != 0 for non-IN elements; 0 ok, -1 internal, -6 unsupported
 int build_pattern(MeshHost &m, const std::vector<uint8_t> &active, std::string &err);
+// dof-level column indices (nnz int32) of the pattern, written to dst
+void fill_col_idx(const MeshHost &m, int32_t *dst);
 
 }  // namespace vms

@@ -110,6 +110,13 @@ def balance_21(ax, ay, az, lev, M, ext):
 
     ext = (ex, ey, ez): the domain extent in max-level units (leaves tile
     [0,ex) x [0,ey) x [0,ez)).
+
+    A leaf at level L needs every leaf touching it at level >= L - 1. Such a
+    neighbour point either lies in a sibling or in a same-size neighbour of
+    the leaf's parent P (level L - 1), and a leaf coarser than P that covers a
+    point of that neighbour covers the whole neighbour, anchor included. So it
+    suffices to test, once per distinct parent, the leaves at the anchors of
+    its 26 neighbours (an eighth of the queries of a per-leaf test).
     """
     ax = ax.astype(np.int64); ay = ay.astype(np.int64); az = az.astype(np.int64)
     lev = lev.astype(np.int64)
@@ -118,15 +125,26 @@ def balance_21(ax, ay, az, lev, M, ext):
             if (i, j, k) != (0, 0, 0)]
     while True:
         ax, ay, az, lev, keys = _sort_leaves(ax, ay, az, lev)
-        side = np.int64(1) << (M - lev)
         split = np.zeros(ax.shape[0], dtype=bool)
+        has_parent = lev > 0
+        plev = lev[has_parent] - 1
+        pside = np.int64(1) << (M - plev)
+        pm = pside - 1
+        px, py, pz = ax[has_parent] & ~pm, ay[has_parent] & ~pm, az[has_parent] & ~pm
+        # distinct parents (sorted by level, then Morton key of the anchor)
+        pk = morton_key(px, py, pz)
+        o = np.lexsort((pk, plev))
+        first = np.ones(o.size, dtype=bool)
+        first[1:] = (pk[o][1:] != pk[o][:-1]) | (plev[o][1:] != plev[o][:-1])
+        u = o[first]
+        px, py, pz, plev, pside = px[u], py[u], pz[u], plev[u], pside[u]
         for (i, j, k) in dirs:
-            nx = ax + i * side
-            ny = ay + j * side
-            nz = az + k * side
+            nx = px + i * pside
+            ny = py + j * pside
+            nz = pz + k * pside
             ok = (nx >= 0) & (ny >= 0) & (nz >= 0) & (nx < ex) & (ny < ey) & (nz < ez)
             idx = _locate(keys, nx[ok], ny[ok], nz[ok])
-            bad = lev[idx] < (lev[ok] - 1)
+            bad = lev[idx] < plev[ok]
             split[idx[bad]] = True
         if not split.any():
             return ax, ay, az, lev
@@ -546,3 +564,38 @@ def two_boxes(n_face: int, domain=(8.0, 2.0, 2.0)):
     c1 = c0 + np.array([1.0 + 0.5, 0.0, 0.0])
     return merge_surfaces([rounded_box(half, 0.03, c0, n_face), rounded_box(half, 0.03, c1, n_face)])
 
+
+
+def rounded_box_distance(p, half, fillet, center):
+    """Signed distance of points (n, 3) to a box with rounded edges and corners
+    (negative inside): the inner box (half - fillet) grown by the fillet radius."""
+    q = np.abs(np.asarray(p, np.float64) - np.asarray(center)) - (np.asarray(half) - fillet)
+    outside = np.linalg.norm(np.maximum(q, 0.0), axis=1)
+    inside = np.minimum(q.max(axis=1), 0.0)
+    return outside + inside - fillet
+
+
+def two_box_workload(lmin=6, lmax=11, beta=13.0, n_face=91, domain=(8.0, 2.0, 2.0)):
+    """Two filleted bluff boxes (two_boxes) in an 8 x 2 x 2 domain, refined at
+    their surfaces from level lmin to lmax.
+
+    The octree root is the cube of side 8 that holds the domain; its leaves
+    cover only [0, 8) x [0, 2) x [0, 2) (the domain is a quarter of the root
+    in y and in z). Octants whose centre lies within beta*h of either box
+    surface are split, which at the default beta gives about 10^7 octants."""
+    assert domain[0] == 4 * domain[1] and domain[1] == domain[2]
+    M = lmax
+    half = (0.5, 0.125, 0.15)
+    c0 = np.array([3.0, domain[1] / 2, domain[2] / 2]) + np.asarray(BODY_OFFSET)
+    c1 = c0 + np.array([1.5, 0.0, 0.0])
+
+    def refine(cx, cy, cz, h, lev):
+        p = np.stack([cx, cy, cz], 1)
+        d = np.minimum(np.abs(rounded_box_distance(p, half, 0.03, c0)),
+                       np.abs(rounded_box_distance(p, half, 0.03, c1)))
+        return (d < beta * h) & (lev < M)
+
+    full = 1 << M
+    tree = refined_octree(M, lmin, refine, ext=(full, full >> 2, full >> 2), root_len=domain[0],
+                          meta={"body": "two_boxes", "beta": beta, "lmin": lmin, "lmax": lmax})
+    return tree, two_boxes(n_face, domain)
