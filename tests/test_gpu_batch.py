@@ -133,10 +133,17 @@ def test_batch_tree_against_reference(env, oracle):
     mk, _, _ = O.markers(tree, ms, surf)
     ms = O.derive_mesh(tree.ax, tree.ay, tree.az, tree.level, tree.max_level, active=mk != O.IN)
     sub = O.subquad(tree, surf, np.nonzero(mk == O.INTERCEPTED)[0], 3)
-    V, R = O.assemble(tree, ms, f, mk=mk, sub=sub, depth=3)
+    # the tree's fields are those of the reference's node positions
+    assert np.array_equal(vms.vms_export(ctxs[k], vms.VMS_EXPORT_NODE_XYZ).T, ms.node_xyz_int)
+    xyz = ms.node_xyz_int.astype(np.float64) / float(1 << tree.max_level) * tree.root_len
+    f_ref = I.make_fields(xyz + np.asarray(tree.origin), 2000 + k)
+    assert all(np.array_equal(f_ref[n], f[n]) for n in f)
+    V, R = O.assemble(tree, ms, f_ref, mk=mk, sub=sub, depth=3)
     v = vals[k].cpu().numpy()
     r = resid[k].cpu().numpy()
-    assert close_mat(v, V, masks[k], 1e-12)
+    act = np.repeat(np.repeat(ms.node_active, 4), np.diff(ms.row_ptr))
+    assert np.array_equal(act, masks[k])
+    assert close_mat(v, V, act, 1e-12)
     assert np.linalg.norm(r - R) <= 1e-12 * np.linalg.norm(R)
     for c in ctxs:
         vms.vms_destroy(c)

@@ -64,8 +64,10 @@ def test_deep_levels_all_forms_against_reference(env, oracle):
     for prec, tol in ((vms.VMS_FP64, 1e-12), (vms.VMS_MIXED_BF16, 1e-5), (vms.VMS_MIXED_FP16, 1e-5)):
         asm = vms.Assembler(tree, surf, vms.make_params(quad_depth=3, precision=prec))
         if f is None:
-            f = I.make_fields(node_xyz(vms, asm, tree), 1001)
+            xyz = msa.node_xyz_int.astype(np.float64) / float(1 << tree.max_level) * tree.root_len
+            f = I.make_fields(xyz + np.asarray(tree.origin), 1001)
             V, R = O.assemble(tree, msa, f, mk=mk, sub=sub, depth=3)
+            assert np.array_equal(asm.export(vms.VMS_EXPORT_NODE_XYZ).T, msa.node_xyz_int)
             assert np.array_equal(asm.export(vms.VMS_EXPORT_MARKERS), mk)
             assert np.array_equal(asm.export(vms.VMS_EXPORT_ROW_PTR), msa.row_ptr)
             assert np.array_equal(asm.export(vms.VMS_EXPORT_COL_IDX), msa.col_idx)

@@ -25,9 +25,8 @@ def vms():
     return V
 
 
-def node_xyz(asm, tree):
-    return asm.export(1).T.astype(np.float64) / float(1 << tree.max_level) * tree.root_len + \
-        np.asarray(tree.origin)
+def phys(tree, ijk):
+    return ijk.astype(np.float64) / float(1 << tree.max_level) * tree.root_len + np.asarray(tree.origin)
 
 
 def test_body_containing_the_domain(vms, oracle):
@@ -39,7 +38,8 @@ def test_body_containing_the_domain(vms, oracle):
     ms = oracle.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level, active=np.zeros(t.n, bool))
     assert asm.sizes["nnz"] == ms.nnz == 16 * ms.n_nodes
     assert np.array_equal(asm.export(vms.VMS_EXPORT_COL_IDX), ms.col_idx)
-    asm.set_fields(I.make_fields(node_xyz(asm, t), 3))
+    assert np.array_equal(asm.export(vms.VMS_EXPORT_NODE_XYZ).T, ms.node_xyz_int)
+    asm.set_fields(I.make_fields(phys(t, ms.node_xyz_int), 3))
     asm.assemble()
     torch.cuda.synchronize()
     rp = ms.row_ptr
@@ -65,7 +65,8 @@ def test_body_inside_one_element_weak_terms(vms, oracle):
     ms = O.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level, active=mk != O.IN)
     asm = vms.Assembler(t, s, vms.make_params(quad_depth=3))
     assert np.array_equal(asm.export(vms.VMS_EXPORT_MARKERS), mk)
-    f = I.make_fields(node_xyz(asm, t), 3)
+    assert np.array_equal(asm.export(vms.VMS_EXPORT_NODE_XYZ).T, ms.node_xyz_int)
+    f = I.make_fields(phys(t, ms.node_xyz_int), 3)
     asm.set_fields(f)
     asm.set_weak_bc(True, 4.0, (0.2, 0.0, 0.0))
     g = asm.export(vms.VMS_EXPORT_SURFGP)

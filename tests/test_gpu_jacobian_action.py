@@ -49,6 +49,13 @@ def reference_mesh(O, tree, surf, depth):
     return ms, mk, sub
 
 
+def ref_fields(vms, asm, tree, ms, seed):
+    """Fields at the reference's node positions (the library's must be the same)."""
+    assert np.array_equal(asm.export(vms.VMS_EXPORT_NODE_XYZ).T, ms.node_xyz_int)
+    xyz = ms.node_xyz_int.astype(np.float64) / float(1 << tree.max_level) * tree.root_len
+    return I.make_fields(xyz + np.asarray(tree.origin), seed)
+
+
 def close(y, y_ref, tol, act):
     """act: rows of active nodes (compared to tol); the others must match exactly."""
     assert np.array_equal(y[~act], y_ref[~act])
@@ -83,12 +90,12 @@ def test_jacobian_action_fp64_against_reference(vms, oracle, case):
     tree, surf = mk_tree()
     torch = pytest.importorskip("torch")
     asm = vms.Assembler(tree, surf, vms.make_params(quad_depth=depth))
-    f = I.make_fields(node_xyz(asm, tree), 1001)
+    ms, mk, sub = reference_mesh(oracle, tree, surf, depth)
+    f = ref_fields(vms, asm, tree, ms, 1001)
     asm.set_fields(f)
     n = asm.sizes["n_rows"]
     x = np.random.default_rng(3).normal(size=n)
     y = asm.jacobian_action(torch.as_tensor(x, device="cuda")).cpu().numpy()
-    ms, mk, sub = reference_mesh(oracle, tree, surf, depth)
     y_ref = oracle.jacobian_apply(tree, ms, f, x, mk=mk, sub=sub, depth=depth)
     act = np.repeat(ms.node_active, 4)
     assert np.array_equal(act, active_rows(vms, asm))
@@ -110,11 +117,11 @@ def test_jacobian_action_mixed_contexts(vms, oracle, prec):
     torch = pytest.importorskip("torch")
     p = vms.VMS_MIXED_BF16 if prec == "bf16" else vms.VMS_MIXED_FP16
     asm = vms.Assembler(tree, surf, vms.make_params(quad_depth=3, precision=p))
-    f = I.make_fields(node_xyz(asm, tree), 1001)
+    ms, mk, sub = reference_mesh(oracle, tree, surf, 3)
+    f = ref_fields(vms, asm, tree, ms, 1001)
     asm.set_fields(f)
     x = np.random.default_rng(4).normal(size=asm.sizes["n_rows"])
     y = asm.jacobian_action(torch.as_tensor(x, device="cuda")).cpu().numpy()
-    ms, mk, sub = reference_mesh(oracle, tree, surf, 3)
     y_ref = oracle.jacobian_apply(tree, ms, f, x, mk=mk, sub=sub, depth=3)
     act = np.repeat(ms.node_active, 4)
     err = np.linalg.norm((y - y_ref)[act]) / np.linalg.norm(y_ref[act])
@@ -130,13 +137,13 @@ def test_spmv_against_reference_jacobian(vms, oracle):
     tree, surf = CASES["cut"][0]()
     torch = pytest.importorskip("torch")
     asm = vms.Assembler(tree, surf, vms.make_params(quad_depth=3))
-    f = I.make_fields(node_xyz(asm, tree), 1001)
+    ms, mk, sub = reference_mesh(oracle, tree, surf, 3)
+    f = ref_fields(vms, asm, tree, ms, 1001)
     asm.set_fields(f)
     asm.assemble()
     x = np.random.default_rng(6).normal(size=asm.sizes["n_rows"])
     xt = torch.as_tensor(x, device="cuda")
     y = asm.spmv(xt).cpu().numpy()
-    ms, mk, sub = reference_mesh(oracle, tree, surf, 3)
     V, _ = oracle.assemble(tree, ms, f, mk=mk, sub=sub, depth=3, resid=False)
     rid = np.repeat(np.arange(ms.row_ptr.size - 1), np.diff(ms.row_ptr))
     y_ref = np.zeros(ms.row_ptr.size - 1)
