@@ -189,7 +189,10 @@ def run_single(torch, vms, tree, surf, f, prec, steps, warmup, flags):
     steady = n_active * steps / (time.perf_counter() - t1)
     asm.assemble(flags=flags)
     torch.cuda.synchronize()
+    dev = stage.sum(1)  # device time of each timed step (sum of its stages)
     out = {"elapsed": elapsed, "value": n_active * steps / elapsed, "ms_step": 1e3 * elapsed / steps,
+           "step_device_ms": {"p10": float(np.percentile(dev, 10)), "p50": float(np.median(dev)),
+                              "p90": float(np.percentile(dev, 90))},
            "stage": stage.mean(0), "steady": steady, "setup_s": setup_s, "stats": st,
            "sizes": asm.sizes, "n_active": n_active,
            "vals": asm.vals, "resid": asm.resid, "inactive": inactive_entries(torch, vms, asm)}
@@ -431,6 +434,7 @@ def main_single(args):
                        n_subgp=st["n_subgp"], precision=pname),
         "inout_tests_per_s": (st["n_labelled"] / (avg[0] * 1e-3)) if avg[0] > 0 else None,
         "steady_state_elements_per_s": r["steady"],
+        "step_device_ms": r["step_device_ms"],
         "stage_ms": {"relabel": avg[0], "zero": avg[1], "out_elements": avg[2],
                      "intercepted_elements": avg[3], "csr_gather": avg[4]},
         "setup_s": r["setup_s"],

@@ -190,6 +190,60 @@ int vms_apply_jacobian(vms_ctx *ctx, const vms_fields *f, const double *x, doubl
  * Alg. 2. Errors: VMS_EINVAL (null argument), VMS_EHIP. */
 int vms_spmv(vms_ctx *ctx, const void *csr_vals, const double *x, double *y);
 
+/* Dirichlet conditions of the solution procedure: the CG nodes of IN elements
+ * (Section "Algorithms", where elements are labelled: no integration on IN
+ * elements and Dirichlet conditions on their nodes) are the element corners
+ * that are independent vertices (a hanging corner constrains nothing).
+ * vms_dirichlet_nodes: count into *n (HOST) and, if nodes is not NULL, the
+ * sorted node ids (HOST, *n int32). vms_dirichlet_in_nodes: every row of those
+ * nodes in csr_vals (DEVICE, the context's precision) becomes an identity row
+ * (all other entries of the row zero) and, if resid is not NULL (DEVICE),
+ * their residual entries become zero (the iterate holds the prescribed
+ * values, so Newton's update vanishes there). Without it an INTERCEPTED
+ * element whose sub-cell points are all IN leaves its IN nodes with empty
+ * rows. Errors: VMS_EINVAL (null argument), VMS_ENOMEM, VMS_EHIP. */
+int vms_dirichlet_nodes(vms_ctx *ctx, int64_t *n, int32_t *nodes);
+int vms_dirichlet_in_nodes(vms_ctx *ctx, void *csr_vals, double *resid);
+
+/* Krylov method of vms_solve */
+enum {
+    VMS_KSP_BCGS = 0, /* BiCGStab, the paper's Krylov method (appendix "Details of solver selection") */
+    VMS_KSP_GMRES = 1 /* restarted GMRES(restart) */
+};
+/* vms_solve flags */
+enum {
+    VMS_SOLVE_DIRICHLET = 1u /* the matrix-free operator takes identity rows at the Dirichlet
+                                nodes too (use with values that had vms_dirichlet_in_nodes) */
+};
+
+/* Newton's linear step A dx = b, the solve the paper hands to its Krylov
+ * solver between Jacobian and residual assemblies (Alg. 2 feeds it; the
+ * paper's runs use BiCGStab with an additive Schwarz preconditioner, here
+ * block Jacobi on the 4x4 node blocks, its one-block-per-node form without
+ * overlap). Right preconditioning by the inverses of the diagonal node blocks
+ * of csr_vals, so the monitored residual is the true one; FP64 vectors and
+ * deterministic inner products. method: VMS_KSP_BCGS or VMS_KSP_GMRES (Arnoldi
+ * by classical Gram-Schmidt with one reorthogonalisation, restart in
+ * [1, 200]; ignored for BiCGStab). A is the assembled matrix (fields = NULL)
+ * or the matrix-free Jacobian action at the given fields (vms_apply_jacobian);
+ * the preconditioner always comes from csr_vals (DEVICE, nnz values of the
+ * context's precision, e.g. from vms_assemble). b, x: DEVICE, n_rows doubles;
+ * x holds the initial guess on entry and the iterate on return. Stops when
+ * ||b - A x|| <= rtol ||b|| (true residual, recomputed at every restart of
+ * the recurrence), after max_iter steps (a BiCGStab step has two products
+ * with A), or at a breakdown that a restart cannot cure. flags: 0 or
+ * VMS_SOLVE_DIRICHLET. iters, rel_res: HOST
+ * outputs (nullable): steps taken and the final true relative residual (the
+ * caller compares it with rtol). Device workspace (max(restart + 1, 8) + 3
+ * vectors of n_rows doubles and 16 doubles per node) is allocated by the first
+ * call and kept by the context; synchronises the context stream. Errors:
+ * VMS_EINVAL (null argument, unknown method or flag, restart outside [1, 200],
+ * negative max_iter, non-positive rtol, singular diagonal block), VMS_ENOMEM,
+ * VMS_EHIP. */
+int vms_solve(vms_ctx *ctx, const void *csr_vals, const vms_fields *fields, const double *b, double *x,
+              int method, int restart, int max_iter, double rtol, uint32_t flags, int *iters,
+              double *rel_res);
+
 /* Weak (Nitsche) enforcement of u = g on the immersed surface, eq. (weakbc)
  * with the remark after it (§"Weak Enforcement of Boundary Conditions"): once
  * enabled, vms_assemble, vms_apply and vms_apply_jacobian add the surface

@@ -440,6 +440,57 @@ def jacobian_apply(tree, ms, fields, x, prm=None, mk=None, sub=None, depth=3):
     return y
 
 
+def dirichlet_nodes(ms, mk):
+    """CG nodes of IN elements (their own corners that are independent
+    vertices; hanging corners impose nothing on their masters): the nodes on
+    which the solution procedure sets Dirichlet conditions (Section
+    "Algorithms", the step that labels elements). Sorted node ids."""
+    ev = ms.elem_vertex[np.asarray(mk) == IN].ravel()
+    ev = ev[~ms.vertex_is_hanging[ev]]
+    keys = np.unique(ms.vertex_keys[ev])
+    pos = np.searchsorted(ms.node_keys, keys)
+    assert np.array_equal(ms.node_keys[pos], keys)
+    return pos.astype(np.int64)
+
+
+def apply_dirichlet(ms, V, R, nodes):
+    """Rows of the given nodes become identity rows (every other entry of the
+    row zero) with zero residual (the iterate already holds the prescribed
+    values, so Newton's update vanishes there). Returns new arrays."""
+    V = np.array(V, np.float64)
+    R = None if R is None else np.array(R, np.float64)
+    for nd in np.asarray(nodes, np.int64):
+        for c in range(4):
+            r = 4 * nd + c
+            lo, hi = ms.row_ptr[r], ms.row_ptr[r + 1]
+            V[lo:hi] = 0.0
+            V[lo + np.nonzero(ms.col_idx[lo:hi] == r)[0]] = 1.0
+            if R is not None:
+                R[r] = 0.0
+    return V, R
+
+
+def csr_matvec(ms, V, x):
+    """y = A x for the assembled CSR (ms.row_ptr, ms.col_idx, values V), written
+    out entry by entry."""
+    V = np.asarray(V, np.float64)
+    rid = np.repeat(np.arange(ms.row_ptr.size - 1), np.diff(ms.row_ptr))
+    y = np.zeros(ms.row_ptr.size - 1)
+    np.add.at(y, rid, V * np.asarray(x, np.float64)[ms.col_idx])
+    return y
+
+
+def linear_solve(ms, V, b):
+    """Newton's linear step A x = b solved exactly (sparse LU): the definition
+    that the Krylov methods of the solution procedure approximate (the paper
+    uses BiCGStab, appendix on solver selection)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as sla
+    n = ms.row_ptr.size - 1
+    A = sp.csr_matrix((np.asarray(V, np.float64), ms.col_idx, ms.row_ptr), shape=(n, n))
+    return sla.spsolve(A.tocsc(), np.asarray(b, np.float64))
+
+
 def element(prm, h, xi, w, Cmat, Um, U0m):
     """Residual (nm*4) and Jacobian ((nm*4)^2) of one element in master space."""
     xi = _c(xi, np.float64).reshape(-1, 3)

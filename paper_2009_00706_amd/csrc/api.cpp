@@ -252,6 +252,18 @@ struct vms_ctx {
     // node-level CSR (block rows, block columns) for the product with the matrix
     int64_t *d_nrow_ptr = nullptr;
     int32_t *d_ncol = nullptr;
+    // GMRES workspace, allocated by the first solve and grown with the restart
+    // length: Krylov basis V ((m + 1) vectors), work vectors, block-Jacobi
+    // inverses, multi-dot partial sums and coefficients
+    // Dirichlet nodes: CG nodes that are corners of IN elements (host list;
+    // device copy made by the first vms_dirichlet_in_nodes)
+    std::vector<int32_t> dir_nodes;
+    int32_t *d_dir_nodes = nullptr;
+    int gm_m = 0;
+    double *d_gm_V = nullptr, *d_gm_w = nullptr, *d_gm_z = nullptr, *d_gm_r = nullptr;
+    double *d_gm_part = nullptr, *d_gm_h = nullptr, *d_gm_dinv = nullptr;
+    int32_t *d_diag_pos = nullptr;
+    int *d_gm_bad = nullptr;
     // element-matrix records (one per work item: OUT elements first, then the
     // sub-cell items) and, per CSR block, the list of record blocks summed into it
     int64_t n_slots = 0, n_blocks = 0;
@@ -861,6 +873,18 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
         }
     }
 
+    // Dirichlet nodes: independent vertices among the corners of IN elements
+    for (int64_t e = 0; e < E; ++e) {
+        if (c->markers[e] != 1) continue;
+        for (int a = 0; a < 8; ++a) {
+            const int32_t v = m.elem_vert[8 * e + a];
+            if (m.vert_type[v] != 1) continue;
+            const auto it = std::lower_bound(m.node_key.begin(), m.node_key.end(), m.vert_key[v]);
+            c->dir_nodes.push_back((int32_t)(it - m.node_key.begin()));
+        }
+    }
+    std::sort(c->dir_nodes.begin(), c->dir_nodes.end());
+    c->dir_nodes.erase(std::unique(c->dir_nodes.begin(), c->dir_nodes.end()), c->dir_nodes.end());
     stage("corner labels and markers");
     // ---- intercepted elements: background triangles, sub-cell quadrature
     for (int64_t e = 0; e < E; ++e)
@@ -1137,12 +1161,10 @@ int vms_apply(vms_ctx *c, const vms_fields *f, double *resid, double *norm2) {
     return VMS_OK;
 }
 
-int vms_apply_jacobian(vms_ctx *c, const vms_fields *f, const double *x, double *y) {
-    if (!c || !f || !x || !y) return fail(c, VMS_EINVAL, "null argument");
-    const double *fp[7] = {f->ux, f->uy, f->uz, f->p, f->ux0, f->uy0, f->uz0};
-    for (const double *p : fp)
-        if (!p) return fail(c, VMS_EINVAL, "null field pointer");
-    if (c->timing) {
+// y = J x without the matrix; stage events when timed and timing is on
+static int jv_impl(vms_ctx *c, const double *const fp[7], const double *x, double *y, bool timed) {
+    const bool tm = timed && c->timing;
+    if (tm) {
         HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
         HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
     }
@@ -1151,12 +1173,12 @@ int vms_apply_jacobian(vms_ctx *c, const vms_fields *f, const double *x, double 
     vmsk::AsmArgs a = base_args(c);
     for (int k = 0; k < 7; ++k) a.f[k] = fp[k];
     a.resid = y;
-    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
+    if (tm) HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
     a.n_items = c->n_std;
     a.items = c->d_std;
     vmsk::launch_jacobian_action(c->stream, a, false, fp64, x);
     HIPCHK(c, hipGetLastError());
-    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
+    if (tm) HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
     if (c->n_sub_items) {
         a.n_items = c->n_sub_items;
         a.items = c->d_sub_el;
@@ -1170,11 +1192,19 @@ int vms_apply_jacobian(vms_ctx *c, const vms_fields *f, const double *x, double 
         vmsk::launch_surface(c->stream, surf_args(c, fp, y), 2, true, x);
         HIPCHK(c, hipGetLastError());
     }
-    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[4], c->stream));
+    if (tm) HIPCHK(c, hipEventRecord(c->ev[4], c->stream));
     vmsk::launch_copy_rows(c->stream, x, y, c->d_inact, c->n_inact);
     HIPCHK(c, hipGetLastError());
-    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[5], c->stream));
+    if (tm) HIPCHK(c, hipEventRecord(c->ev[5], c->stream));
     return VMS_OK;
+}
+
+int vms_apply_jacobian(vms_ctx *c, const vms_fields *f, const double *x, double *y) {
+    if (!c || !f || !x || !y) return fail(c, VMS_EINVAL, "null argument");
+    const double *fp[7] = {f->ux, f->uy, f->uz, f->p, f->ux0, f->uy0, f->uz0};
+    for (const double *p : fp)
+        if (!p) return fail(c, VMS_EINVAL, "null field pointer");
+    return jv_impl(c, fp, x, y, true);
 }
 
 int vms_spmv(vms_ctx *c, const void *csr_vals, const double *x, double *y) {
@@ -1186,6 +1216,254 @@ int vms_spmv(vms_ctx *c, const void *csr_vals, const double *x, double *y) {
         vmsk::launch_bspmv_f32(c->stream, c->d_nrow_ptr, c->d_ncol, (const float *)csr_vals, x, y,
                                c->mesh.n_nodes);
     HIPCHK(c, hipGetLastError());
+    return VMS_OK;
+}
+
+// device copy of each node's diagonal block position (first use)
+static int ensure_diag_pos(vms_ctx *c) {
+    if (c->d_diag_pos) return VMS_OK;
+    std::vector<int32_t> dp(c->mesh.diag_pos.begin(), c->mesh.diag_pos.end());
+    if (upload(c, &c->d_diag_pos, dp)) return fail(c, VMS_ENOMEM, "device allocation failed (diagonal map)");
+    return VMS_OK;
+}
+
+int vms_dirichlet_nodes(vms_ctx *c, int64_t *n, int32_t *nodes) {
+    if (!c || !n) return fail(c, VMS_EINVAL, "null argument");
+    *n = (int64_t)c->dir_nodes.size();
+    if (nodes) std::memcpy(nodes, c->dir_nodes.data(), c->dir_nodes.size() * sizeof(int32_t));
+    return VMS_OK;
+}
+
+int vms_dirichlet_in_nodes(vms_ctx *c, void *csr_vals, double *resid) {
+    if (!c || !csr_vals) return fail(c, VMS_EINVAL, "null argument");
+    int rc = ensure_diag_pos(c);
+    if (rc) return rc;
+    const int64_t nd = (int64_t)c->dir_nodes.size();
+    if (nd == 0) return VMS_OK;
+    if (!c->d_dir_nodes && upload(c, &c->d_dir_nodes, c->dir_nodes))
+        return fail(c, VMS_ENOMEM, "device allocation failed (Dirichlet nodes)");
+    if (c->prm.precision == VMS_FP64)
+        vmsk::launch_dirichlet_rows_f64(c->stream, (double *)csr_vals, c->d_nrow_ptr, c->d_diag_pos,
+                                        c->d_dir_nodes, nd, resid);
+    else
+        vmsk::launch_dirichlet_rows_f32(c->stream, (float *)csr_vals, c->d_nrow_ptr, c->d_diag_pos,
+                                        c->d_dir_nodes, nd, resid);
+    HIPCHK(c, hipGetLastError());
+    return VMS_OK;
+}
+
+// Krylov solve of A dx = b (Newton's linear step), right-preconditioned by
+// the inverses of the 4x4 diagonal blocks of the assembled values, so the
+// residual monitored is the true one of the unpreconditioned system. BiCGStab
+// (the paper's Krylov method) or restarted GMRES(m) (Arnoldi with classical
+// Gram-Schmidt and one reorthogonalisation pass; Givens rotations and the small
+// triangular solve on the host). A = the assembled matrix, or the matrix-free
+// Jacobian action at the given fields. Inner products are deterministic
+// two-stage sums; every scalar decision is taken on the host in FP64.
+int vms_solve(vms_ctx *c, const void *csr_vals, const vms_fields *f, const double *b, double *x,
+              int method, int restart, int max_iter, double rtol, uint32_t flags, int *iters,
+              double *rel_res) {
+    if (!c || !csr_vals || !b || !x) return fail(c, VMS_EINVAL, "null argument");
+    if (flags & ~(uint32_t)VMS_SOLVE_DIRICHLET) return fail(c, VMS_EINVAL, "unknown flags");
+    if (method != VMS_KSP_BCGS && method != VMS_KSP_GMRES) return fail(c, VMS_EINVAL, "unknown method");
+    if (method == VMS_KSP_GMRES && (restart < 1 || restart > 200))
+        return fail(c, VMS_EINVAL, "restart must be in [1, 200]");
+    if (max_iter < 0) return fail(c, VMS_EINVAL, "negative iteration limit");
+    if (!(rtol > 0.0) || !std::isfinite(rtol)) return fail(c, VMS_EINVAL, "rtol must be positive");
+    const double *fp[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    if (f) {
+        const double *q[7] = {f->ux, f->uy, f->uz, f->p, f->ux0, f->uy0, f->uz0};
+        for (int k = 0; k < 7; ++k) {
+            if (!q[k]) return fail(c, VMS_EINVAL, "null field pointer");
+            fp[k] = q[k];
+        }
+    }
+    const hipStream_t st = c->stream;
+    const int64_t N = c->mesh.n_nodes, n = 4 * N;
+    // Krylov vectors: m + 1 for GMRES, 8 for BiCGStab
+    const int m = method == VMS_KSP_GMRES ? restart : 7;
+    // ---- workspace (kept by the context)
+    if (c->gm_m < m) {
+        for (double *p : {c->d_gm_V, c->d_gm_part, c->d_gm_h}) c->buf.free(p);
+        c->d_gm_V = c->d_gm_part = c->d_gm_h = nullptr;
+        c->gm_m = 0;
+        if (c->buf.alloc(&c->d_gm_V, (size_t)(m + 1) * n) ||
+            c->buf.alloc(&c->d_gm_part, (size_t)(m + 1) * vmsk::multidot_blocks(n)) ||
+            c->buf.alloc(&c->d_gm_h, (size_t)m + 2))
+            return fail(c, VMS_ENOMEM, "device allocation failed (Krylov vectors)");
+        c->gm_m = m;
+    }
+    if (!c->d_gm_dinv) {
+        int rc0 = ensure_diag_pos(c);
+        if (rc0) return rc0;
+        if (c->buf.alloc(&c->d_gm_w, n) || c->buf.alloc(&c->d_gm_z, n) || c->buf.alloc(&c->d_gm_r, n) ||
+            c->buf.alloc(&c->d_gm_bad, 1) || c->buf.alloc(&c->d_gm_dinv, (size_t)16 * N))
+            return fail(c, VMS_ENOMEM, "device allocation failed (preconditioner)");
+    }
+    double *V = c->d_gm_V, *w = c->d_gm_w, *z = c->d_gm_z, *r = c->d_gm_r, *dh = c->d_gm_h;
+    // ---- block-Jacobi preconditioner from the current values
+    HIPCHK(c, hipMemsetAsync(c->d_gm_bad, 0, sizeof(int), st));
+    if (c->prm.precision == VMS_FP64)
+        vmsk::launch_bjac_invert_f64(st, (const double *)csr_vals, c->d_nrow_ptr, c->d_diag_pos, N,
+                                     c->d_gm_dinv, c->d_gm_bad);
+    else
+        vmsk::launch_bjac_invert_f32(st, (const float *)csr_vals, c->d_nrow_ptr, c->d_diag_pos, N,
+                                     c->d_gm_dinv, c->d_gm_bad);
+    HIPCHK(c, hipGetLastError());
+    int bad = 0;
+    HIPCHK(c, hipMemcpyAsync(&bad, c->d_gm_bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (bad) return fail(c, VMS_EINVAL, "singular diagonal block (assemble before solving)");
+    const bool mf_dir = f && (flags & VMS_SOLVE_DIRICHLET) && !c->dir_nodes.empty();
+    if (mf_dir && !c->d_dir_nodes && upload(c, &c->d_dir_nodes, c->dir_nodes))
+        return fail(c, VMS_ENOMEM, "device allocation failed (Dirichlet nodes)");
+    auto op = [&](const double *in, double *out) -> int {
+        if (!f) return vms_spmv(c, csr_vals, in, out);
+        int e = jv_impl(c, fp, in, out, false);
+        if (e) return e;
+        if (mf_dir) {  // identity rows at the Dirichlet nodes, as in the CSR values
+            vmsk::launch_copy_rows(st, in, out, c->d_dir_nodes, (int64_t)c->dir_nodes.size());
+            HIPCHK(c, hipGetLastError());
+        }
+        return VMS_OK;
+    };
+    auto prec = [&](const double *in, double *out) { vmsk::launch_bjac_apply(st, c->d_gm_dinv, in, out, N); };
+    // host copies of nk inner products Vb_k . v (the coefficients stay in dh)
+    std::vector<double> hv(m + 2);
+    auto dots = [&](const double *Vb, int nk, const double *v) -> int {
+        vmsk::launch_multidot(st, Vb, n, nk, v, n, c->d_gm_part, dh);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(hv.data(), dh, sizeof(double) * nk, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
+        return VMS_OK;
+    };
+    int rc;
+    if ((rc = dots(b, 1, b))) return rc;
+    const double bnorm = std::sqrt(hv[0]);
+    if (bnorm == 0.0) {
+        vmsk::launch_fill_f64(st, x, n, 0.0);
+        HIPCHK(c, hipStreamSynchronize(st));
+        if (iters) *iters = 0;
+        if (rel_res) *rel_res = 0.0;
+        return VMS_OK;
+    }
+    int it = 0;
+    double res = 0.0;
+    if (method == VMS_KSP_BCGS) {
+        // vectors: r (residual), rh (shadow), p, v, ph = M^-1 p, s and t adjacent
+        // (one multi-dot gives t.s and t.t), sh = M^-1 s
+        double *rr = V, *rh = V + n, *pp = V + 2 * n, *vv = V + 3 * n, *ph = V + 4 * n, *ss = V + 5 * n,
+               *tt = V + 6 * n, *sh = V + 7 * n;
+        while (true) {
+            // true residual; the recurrence restarts from it
+            if ((rc = op(x, w))) return rc;
+            vmsk::launch_axpby(st, 1.0, b, -1.0, w, rr, n);
+            if ((rc = dots(rr, 1, rr))) return rc;
+            res = std::sqrt(hv[0]) / bnorm;
+            if (res <= rtol || it >= max_iter) break;
+            vmsk::launch_axpby(st, 1.0, rr, 0.0, rr, rh, n);
+            double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+            const int it0 = it;
+            for (int k = 0; it < max_iter; ++k) {
+                if ((rc = dots(rh, 1, rr))) return rc;
+                const double rho = hv[0];
+                if (rho == 0.0) break;
+                if (k == 0) {
+                    vmsk::launch_axpby(st, 1.0, rr, 0.0, rr, pp, n);
+                } else {
+                    const double beta = (rho / rho_old) * (alpha / omega);
+                    vmsk::launch_axpbypcz(st, 1.0, rr, beta, pp, -beta * omega, vv, pp, n);
+                }
+                prec(pp, ph);
+                if ((rc = op(ph, vv))) return rc;
+                if ((rc = dots(rh, 1, vv))) return rc;
+                if (hv[0] == 0.0) break;
+                alpha = rho / hv[0];
+                vmsk::launch_axpby(st, 1.0, rr, -alpha, vv, ss, n);
+                ++it;
+                if ((rc = dots(ss, 1, ss))) return rc;
+                if (std::sqrt(hv[0]) <= rtol * bnorm) {  // confirmed by the true residual
+                    vmsk::launch_axpby(st, 1.0, x, alpha, ph, x, n);
+                    break;
+                }
+                prec(ss, sh);
+                if ((rc = op(sh, tt))) return rc;
+                if ((rc = dots(ss, 2, tt))) return rc;  // s.t, t.t
+                if (hv[1] == 0.0) {
+                    vmsk::launch_axpby(st, 1.0, x, alpha, ph, x, n);
+                    break;
+                }
+                omega = hv[0] / hv[1];
+                vmsk::launch_axpbypcz(st, 1.0, x, alpha, ph, omega, sh, x, n);
+                vmsk::launch_axpby(st, 1.0, ss, -omega, tt, rr, n);
+                if ((rc = dots(rr, 1, rr))) return rc;
+                if (std::sqrt(hv[0]) <= rtol * bnorm || omega == 0.0) break;
+                rho_old = rho;
+            }
+            if (it == it0) break;  // breakdown before any step: no progress from a restart
+        }
+    } else {
+        std::vector<std::vector<double>> H(m + 1, std::vector<double>(m, 0.0));
+        std::vector<double> cs(m), sn(m), g(m + 1), y(m), h(m + 1);
+        while (true) {
+            // true residual r = b - A x
+            if ((rc = op(x, w))) return rc;
+            vmsk::launch_axpby(st, 1.0, b, -1.0, w, r, n);
+            if ((rc = dots(r, 1, r))) return rc;
+            const double beta = std::sqrt(hv[0]);
+            res = beta / bnorm;
+            if (res <= rtol || it >= max_iter) break;
+            vmsk::launch_axpby(st, 1.0 / beta, r, 0.0, r, V, n);
+            std::fill(g.begin(), g.end(), 0.0);
+            g[0] = beta;
+            int j = 0;
+            while (j < m && it < max_iter) {
+                double *vj1 = V + (int64_t)(j + 1) * n;
+                prec(V + (int64_t)j * n, z);
+                if ((rc = op(z, w))) return rc;
+                // two Gram-Schmidt passes against V_0 .. V_j
+                if ((rc = dots(V, j + 1, w))) return rc;
+                for (int i = 0; i <= j; ++i) h[i] = hv[i];
+                vmsk::launch_combine(st, V, n, j + 1, dh, w, n, 0);
+                if ((rc = dots(V, j + 1, w))) return rc;
+                for (int i = 0; i <= j; ++i) h[i] += hv[i];
+                vmsk::launch_combine(st, V, n, j + 1, dh, w, n, 0);
+                if ((rc = dots(w, 1, w))) return rc;
+                const double hn = std::sqrt(hv[0]);
+                if (hn > 0.0) vmsk::launch_axpby(st, 1.0 / hn, w, 0.0, w, vj1, n);
+                // Givens rotations
+                for (int i = 0; i < j; ++i) {
+                    const double t = cs[i] * h[i] + sn[i] * h[i + 1];
+                    h[i + 1] = -sn[i] * h[i] + cs[i] * h[i + 1];
+                    h[i] = t;
+                }
+                const double den = std::hypot(h[j], hn);
+                cs[j] = den > 0.0 ? h[j] / den : 1.0;
+                sn[j] = den > 0.0 ? hn / den : 0.0;
+                h[j] = den;
+                for (int i = 0; i <= j; ++i) H[i][j] = h[i];
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+                ++j;
+                ++it;
+                if (std::fabs(g[j]) <= rtol * bnorm || hn == 0.0) break;
+            }
+            // y = H^-1 g (upper triangular j x j), x += M^-1 (V y)
+            for (int i = j - 1; i >= 0; --i) {
+                double sum = g[i];
+                for (int k = i + 1; k < j; ++k) sum -= H[i][k] * y[k];
+                y[i] = H[i][i] != 0.0 ? sum / H[i][i] : 0.0;
+            }
+            HIPCHK(c, hipMemcpyAsync(dh, y.data(), sizeof(double) * j, hipMemcpyHostToDevice, st));
+            vmsk::launch_combine(st, V, n, j, dh, w, n, 1);
+            prec(w, z);
+            vmsk::launch_axpby(st, 1.0, x, 1.0, z, x, n);
+            HIPCHK(c, hipGetLastError());
+        }
+    }
+    HIPCHK(c, hipStreamSynchronize(st));
+    if (iters) *iters = it;
+    if (rel_res) *rel_res = res;
     return VMS_OK;
 }
 

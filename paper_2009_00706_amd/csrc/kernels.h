@@ -130,6 +130,12 @@ void launch_fill_f64(hipStream_t s, double *p, int64_t n, double v);
 void launch_fill_f32(hipStream_t s, float *p, int64_t n, float v);
 void launch_set_ones_f64(hipStream_t s, double *vals, const int64_t *idx, int64_t n);
 void launch_set_ones_f32(hipStream_t s, float *vals, const int64_t *idx, int64_t n);
+// rows of the listed nodes -> identity rows (diag_pos: block index of the
+// diagonal in each node row), their residual entries (if resid) -> 0
+void launch_dirichlet_rows_f64(hipStream_t s, double *vals, const int64_t *nrow_ptr, const int32_t *diag_pos,
+                               const int32_t *nodes, int64_t n, double *resid);
+void launch_dirichlet_rows_f32(hipStream_t s, float *vals, const int64_t *nrow_ptr, const int32_t *diag_pos,
+                               const int32_t *nodes, int64_t n, double *resid);
 // sum of squares, FP64, into out[0] (zeroed by the caller)
 void launch_norm2(hipStream_t s, const double *v, int64_t n, double *out);
 // Weak (Nitsche) boundary terms at surface points: items [0, n_items), item
@@ -166,5 +172,28 @@ void launch_bspmv_f64(hipStream_t s, const int64_t *nrow_ptr, const int32_t *nco
                       const double *x, double *y, int64_t n_nodes);
 void launch_bspmv_f32(hipStream_t s, const int64_t *nrow_ptr, const int32_t *ncol, const float *vals,
                       const double *x, double *y, int64_t n_nodes);
+
+// Krylov vector kernels (krylov.hip). dinv: 16 doubles per node, the inverse
+// of the node's diagonal 4x4 block (diag_pos[n] = its block index in the node
+// row); *bad is or-ed with 1 where a block is singular.
+void launch_bjac_invert_f64(hipStream_t s, const double *vals, const int64_t *nrow_ptr,
+                            const int32_t *diag_pos, int64_t n_nodes, double *dinv, int *bad);
+void launch_bjac_invert_f32(hipStream_t s, const float *vals, const int64_t *nrow_ptr,
+                            const int32_t *diag_pos, int64_t n_nodes, double *dinv, int *bad);
+void launch_bjac_apply(hipStream_t s, const double *dinv, const double *x, double *y, int64_t n_nodes);
+// out[k] = V_k . w for k < nk (V_k = V + k ldv), deterministic; partial holds
+// nk * multidot_blocks(n) doubles
+int multidot_blocks(int64_t n);
+void launch_multidot(hipStream_t s, const double *V, int64_t ldv, int nk, const double *w, int64_t n,
+                     double *partial, double *out);
+// mode 0: w -= sum_k c[k] V_k; mode 1: w = sum_k c[k] V_k (c: device, nk entries)
+void launch_combine(hipStream_t s, const double *V, int64_t ldv, int nk, const double *c, double *w,
+                    int64_t n, int mode);
+// out = a x + b y
+void launch_axpby(hipStream_t s, double a, const double *x, double b, const double *y, double *out,
+                  int64_t n);
+// out = a x + b y + c z
+void launch_axpbypcz(hipStream_t s, double a, const double *x, double b, const double *y, double c,
+                     const double *z, double *out, int64_t n);
 
 }  // namespace vmsk

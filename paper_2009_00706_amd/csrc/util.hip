@@ -44,6 +44,35 @@ void launch_set_ones_f32(hipStream_t s, float *vals, const int64_t *idx, int64_t
                            vals, idx, n);
 }
 
+// Dirichlet rows: node nodes[blockIdx.x]'s four rows (entries 16 nrow_ptr[n]
+// .. 16 nrow_ptr[n + 1]) become identity rows; its residual entries zero
+template <typename T>
+__global__ void k_dirichlet_rows(T *vals, const int64_t *nrow_ptr, const int32_t *diag_pos,
+                                 const int32_t *nodes, double *resid) {
+    const int64_t n = nodes[blockIdx.x];
+    const int64_t b0 = nrow_ptr[n], deg = nrow_ptr[n + 1] - b0;
+    for (int64_t e = 16 * b0 + threadIdx.x; e < 16 * (b0 + deg); e += blockDim.x) vals[e] = (T)0;
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int c = threadIdx.x;
+        vals[16 * b0 + 4 * c * deg + 4 * (int64_t)diag_pos[n] + c] = (T)1;
+        if (resid) resid[4 * n + c] = 0.0;
+    }
+}
+
+void launch_dirichlet_rows_f64(hipStream_t s, double *vals, const int64_t *nrow_ptr, const int32_t *diag_pos,
+                               const int32_t *nodes, int64_t n, double *resid) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_dirichlet_rows<double>, dim3((unsigned)n), dim3(64), 0, s, vals, nrow_ptr,
+                           diag_pos, nodes, resid);
+}
+void launch_dirichlet_rows_f32(hipStream_t s, float *vals, const int64_t *nrow_ptr, const int32_t *diag_pos,
+                               const int32_t *nodes, int64_t n, double *resid) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_dirichlet_rows<float>, dim3((unsigned)n), dim3(64), 0, s, vals, nrow_ptr,
+                           diag_pos, nodes, resid);
+}
+
 __global__ void k_norm2(const double *v, int64_t n, double *out) {
     __shared__ double part[4];
     double acc = 0.0;

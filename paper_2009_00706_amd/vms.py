@@ -20,12 +20,15 @@ VMS_OK, VMS_EINVAL, VMS_EMESH, VMS_EHIP, VMS_ENOMEM, VMS_EOVERFLOW, VMS_EUNSUPPO
 VMS_FP64, VMS_MIXED_BF16, VMS_MIXED_FP16 = 0, 1, 2
 VMS_INOUT_EXACT, VMS_INOUT_LEARNED = 0, 1
 VMS_RELABEL = 1
+VMS_KSP_BCGS, VMS_KSP_GMRES = 0, 1
+VMS_SOLVE_DIRICHLET = 1
 VMS_EXPORT_SURFGP = 8
 (VMS_EXPORT_NODE_XYZ, VMS_EXPORT_ROW_PTR, VMS_EXPORT_COL_IDX, VMS_EXPORT_MARKERS,
  VMS_EXPORT_VERTEX_LAB, VMS_EXPORT_SUBGP, VMS_EXPORT_MASTERS) = range(1, 8)
 
 EXPORTED = ["vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply",
-            "vms_apply_jacobian", "vms_spmv", "vms_set_weak_bc", "vms_element_weights",
+            "vms_apply_jacobian", "vms_spmv", "vms_solve", "vms_dirichlet_nodes", "vms_dirichlet_in_nodes",
+            "vms_set_weak_bc", "vms_element_weights",
             "inout_classify",
             "inout_prepare", "inout_classify_prepared", "inout_release", "vms_stats",
             "vms_mesh_create", "vms_mesh_sizes", "vms_mesh_export", "vms_mesh_destroy",
@@ -83,6 +86,10 @@ def lib():
         L.vms_apply.argtypes = [p, C.POINTER(Fields), p, p]
         L.vms_apply_jacobian.argtypes = [p, C.POINTER(Fields), p, p]
         L.vms_spmv.argtypes = [p, p, p, p]
+        L.vms_dirichlet_nodes.argtypes = [p, C.POINTER(C.c_int64), p]
+        L.vms_dirichlet_in_nodes.argtypes = [p, p, p]
+        L.vms_solve.argtypes = [p, p, C.POINTER(Fields), p, p, C.c_int, C.c_int, C.c_int, C.c_double,
+                                C.c_uint32, C.POINTER(C.c_int), C.POINTER(C.c_double)]
         L.vms_set_weak_bc.argtypes = [p, C.c_int, C.c_double, p]
         L.vms_element_weights.argtypes = [p, C.c_double, p]
         L.inout_classify.argtypes = [C.POINTER(Surface), p, p, p, i64, p, u32, p, p]
@@ -319,6 +326,32 @@ def vms_spmv(ctx, vals, x, y):
     _check(lib().vms_spmv(ctx, _ptr(vals), _ptr(x), _ptr(y)), ctx)
 
 
+def vms_dirichlet_nodes(ctx):
+    """Sorted ids of the CG nodes of IN elements (int32 numpy array)."""
+    n = C.c_int64(0)
+    _check(lib().vms_dirichlet_nodes(ctx, C.byref(n), None), ctx)
+    out = np.zeros(n.value, np.int32)
+    _check(lib().vms_dirichlet_nodes(ctx, C.byref(n), out.ctypes.data_as(C.c_void_p)), ctx)
+    return out
+
+
+def vms_dirichlet_in_nodes(ctx, vals, resid=None):
+    """Identity rows (and zero residual entries) at the CG nodes of IN elements."""
+    _check(lib().vms_dirichlet_in_nodes(ctx, _ptr(vals), _ptr(resid)), ctx)
+
+
+def vms_solve(ctx, vals, b, x, fields=None, method=VMS_KSP_BCGS, restart=30, max_iter=1000, rtol=1e-6,
+              flags=0):
+    """Krylov solve of A x = b (device tensors of n_rows doubles; x: initial
+    guess in, iterate out); A is the assembled matrix with values vals, or the
+    matrix-free Jacobian action at fields. Returns (steps, true relative residual)."""
+    it, rr = C.c_int(0), C.c_double(0.0)
+    fs = C.byref(_fields(fields)) if fields is not None else None
+    _check(lib().vms_solve(ctx, _ptr(vals), fs, _ptr(b), _ptr(x), int(method), int(restart), int(max_iter),
+                           float(rtol), int(flags), C.byref(it), C.byref(rr)), ctx)
+    return it.value, rr.value
+
+
 def inout_classify(surf, px, py, pz, labels, mode=VMS_INOUT_EXACT, mlp=None, stream=None):
     s = make_surface(surf.verts, surf.tris)
     rc = lib().inout_classify(C.byref(s), _ptr(px), _ptr(py), _ptr(pz), px.numel(), _ptr(labels),
@@ -532,6 +565,23 @@ class Assembler:
             y = self.torch.empty_like(x)
         vms_spmv(self.ctx, self.vals, x, y)
         return y
+
+    def apply_dirichlet(self, resid=True):
+        """Dirichlet rows at the CG nodes of IN elements in the current values
+        (and residual)."""
+        vms_dirichlet_in_nodes(self.ctx, self.vals, self.resid if resid else None)
+
+    def solve(self, b, x=None, matrix_free=False, method=VMS_KSP_BCGS, restart=30, max_iter=1000,
+              rtol=1e-6, dirichlet=True):
+        """Solve J x = b with the last assembled values (preconditioner, and the
+        operator unless matrix_free; dirichlet: the values carry the Dirichlet
+        rows of apply_dirichlet, which the matrix-free operator then copies);
+        returns (x, steps, true relative residual)."""
+        if x is None:
+            x = self.torch.zeros_like(b)
+        it, rr = vms_solve(self.ctx, self.vals, b, x, self.fields if matrix_free else None, method,
+                           restart, max_iter, rtol, VMS_SOLVE_DIRICHLET if dirichlet else 0)
+        return x, it, rr
 
     def export(self, what):
         return vms_export(self.ctx, what, self.n_oct)

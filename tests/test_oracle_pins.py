@@ -744,3 +744,77 @@ def test_element_weights_reduce_to_one_and_zero(oracle):
     assert np.all(w[mk == oracle.OUT] == 1.0) and np.all(w[mk == oracle.IN] == 0.0)
     cut = mk == oracle.INTERCEPTED
     assert abs(8.0 * w[cut].sum() - (sub["el"].size + 2.5 * sp["el"].size)) < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# Newton's linear step: the exact solve that the Krylov methods approximate
+# ---------------------------------------------------------------------------
+
+
+def test_linear_solve_recovers_a_known_solution(oracle):
+    """On a cut, hanging mesh: the CSR product equals the matrix-free Jacobian
+    action (independent complex-step formulation), and solving A x = A x*
+    returns x* to within the conditioning of A (dense 2-norm condition number)."""
+    c = tuple(0.5 + o for o in I.BODY_OFFSET)
+    t = I.sphere_refined_octree(c, 0.25, 2, 4, 1.0)
+    s = I.icosphere(2, 0.25, c)
+    ms0 = oracle.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level)
+    mk, _, _ = oracle.markers(t, ms0, s)
+    ms = oracle.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level, active=mk != oracle.IN)
+    sub = oracle.subquad(t, s, np.nonzero(mk == oracle.INTERCEPTED)[0], 2)
+    f = I.make_fields(ms.node_xyz_int.astype(np.float64) / float(1 << t.max_level), 12)
+    V, _ = oracle.assemble(t, ms, f, mk=mk, sub=sub, depth=2, resid=False)
+    xs = np.random.default_rng(8).normal(size=4 * ms.n_nodes)
+    b = oracle.csr_matvec(ms, V, xs)
+    y = oracle.jacobian_apply(t, ms, f, xs, mk=mk, sub=sub, depth=2)
+    assert np.linalg.norm(b - y) <= 1e-13 * np.linalg.norm(b)
+    # INTERCEPTED elements whose sub-cell points are all IN leave rows of IN
+    # nodes empty: only the Dirichlet rows of IN nodes make the system regular
+    nodes = oracle.dirichlet_nodes(ms, mk)
+    V, _ = oracle.apply_dirichlet(ms, V, None, nodes)
+    b = oracle.csr_matvec(ms, V, xs)
+    x = oracle.linear_solve(ms, V, b)
+    A = np.zeros((b.size, b.size))
+    A[np.repeat(np.arange(b.size), np.diff(ms.row_ptr)), ms.col_idx] = V
+    kappa = np.linalg.cond(A)
+    err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
+    print(f"{b.size} unknowns, condition number {kappa:.2e}, error {err:.2e}")
+    assert err <= 100 * kappa * np.finfo(float).eps
+    assert np.linalg.norm(A @ x - b) <= 1e-12 * np.linalg.norm(b)
+
+
+def test_dirichlet_nodes_are_the_in_corners(oracle):
+    """The Dirichlet nodes are exactly the independent vertices labelled IN that
+    are corners of IN elements (the exact labels decide, no hanging vertex), and
+    the rows they replace become identity rows while the others keep their
+    values."""
+    c = tuple(0.5 + o for o in I.BODY_OFFSET)
+    t = I.sphere_refined_octree(c, 0.25, 2, 4, 1.0)
+    s = I.icosphere(2, 0.25, c)
+    ms = oracle.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level)
+    mk, vlab, _ = oracle.markers(t, ms, s)
+    nodes = oracle.dirichlet_nodes(ms, mk)
+    xyz = ms.node_xyz_int[nodes].astype(np.float64) / float(1 << t.max_level)
+    lab, _ = oracle.label_points(s, xyz)
+    assert nodes.size > 0 and lab.all()             # every Dirichlet node is IN
+    # brute force: an independent vertex is a Dirichlet node iff some IN element has it as a corner
+    side = (1 << (t.max_level - t.level.astype(np.int64)))
+    want = set()
+    for e in np.nonzero(mk == oracle.IN)[0]:
+        for a in range(8):
+            p = (int(t.ax[e]) + (a & 1) * side[e], int(t.ay[e]) + ((a >> 1) & 1) * side[e],
+                 int(t.az[e]) + ((a >> 2) & 1) * side[e])
+            want.add(p)
+    got = {tuple(map(int, q)) for q in ms.node_xyz_int[nodes]}
+    indep = {tuple(map(int, q)) for q in ms.node_xyz_int}
+    assert got == want & indep
+    V = np.random.default_rng(2).normal(size=ms.nnz)
+    R = np.random.default_rng(3).normal(size=4 * ms.n_nodes)
+    V2, R2 = oracle.apply_dirichlet(ms, V, R, nodes)
+    rows = np.zeros(4 * ms.n_nodes, bool)
+    rows[(4 * nodes[:, None] + np.arange(4)).ravel()] = True
+    rid = np.repeat(np.arange(4 * ms.n_nodes), np.diff(ms.row_ptr))
+    sel = rows[rid]
+    assert np.array_equal(V2[~sel], V[~sel]) and np.array_equal(R2[~rows], R[~rows])
+    assert np.array_equal(V2[sel], (ms.col_idx[sel] == rid[sel]).astype(float))
+    assert not R2[rows].any()
