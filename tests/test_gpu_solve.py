@@ -121,6 +121,15 @@ def test_solve_arguments(vms, case):
         vms.vms_solve(asm.ctx, asm.vals, b, x, method=1, restart=0)
     with pytest.raises(vms.VmsError):
         vms.vms_solve(asm.ctx, asm.vals, b, x, rtol=0.0)
+    with pytest.raises(vms.VmsError):
+        vms.vms_solve(asm.ctx, asm.vals, b, x, flags=4)
+    # values without their diagonal blocks: the preconditioner reports it
+    with pytest.raises(vms.VmsError, match="singular diagonal block"):
+        vms.vms_solve(asm.ctx, torch.zeros_like(asm.vals), asm.resid, x)
+    # an iteration limit of zero returns the initial guess and its residual
+    x0 = torch.zeros_like(asm.resid)
+    it, rr = vms.vms_solve(asm.ctx, asm.vals, asm.resid, x0, max_iter=0)
+    assert it == 0 and rr == 1.0 and not x0.any().item()
     asm.close()
 
 
