@@ -34,25 +34,33 @@ __global__ void k_bjac_invert(const T *vals, const int64_t *nrow_ptr, const int3
             a[i][j] = (double)v[4 * i * deg + j];
             a[i][4 + j] = i == j ? 1.0 : 0.0;
         }
+    // partial pivoting by compare-and-swap against each lower row in turn (the
+    // largest entry ends in the pivot row); fully unrolled so that every index
+    // is static and the matrix stays in registers
+#pragma unroll
     for (int c = 0; c < 4; ++c) {
-        int piv = c;
-        for (int r = c + 1; r < 4; ++r)
-            if (fabs(a[r][c]) > fabs(a[piv][c])) piv = r;
-        if (a[piv][c] == 0.0) {
+#pragma unroll
+        for (int r = c + 1; r < 4; ++r) {
+            const bool sw = fabs(a[r][c]) > fabs(a[c][c]);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const double t = a[c][j];
+                a[c][j] = sw ? a[r][j] : t;
+                a[r][j] = sw ? t : a[r][j];
+            }
+        }
+        if (a[c][c] == 0.0) {
             atomicOr(bad, 1);
             return;
         }
-        if (piv != c)
-            for (int j = 0; j < 8; ++j) {
-                const double t = a[c][j];
-                a[c][j] = a[piv][j];
-                a[piv][j] = t;
-            }
         const double ip = 1.0 / a[c][c];
+#pragma unroll
         for (int j = 0; j < 8; ++j) a[c][j] *= ip;
+#pragma unroll
         for (int r = 0; r < 4; ++r) {
             if (r == c) continue;
             const double f = a[r][c];
+#pragma unroll
             for (int j = 0; j < 8; ++j) a[r][j] -= f * a[c][j];
         }
     }
