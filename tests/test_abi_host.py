@@ -121,3 +121,38 @@ def test_misaligned_leaf_rejected():
     with pytest.raises(vms.VmsError) as ei:
         vms.vms_mesh_create(I.Octree(ax, t.ay, t.az, t.level, 3))
     assert ei.value.code == vms.VMS_EINVAL
+
+
+_THREADS_PROBE = r"""
+import hashlib, sys
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from paper_2009_00706_amd import inputs as I
+from paper_2009_00706_amd import vms
+c = (0.5 + I.BODY_OFFSET[0], 0.5, 0.5)
+t = I.sphere_refined_octree(c, 0.3, 3, 7, 1.5)
+mk = (np.arange(t.n) % 7 == 3).astype(np.uint8)  # some IN elements: a partial pattern
+h = vms.vms_mesh_create(t, mk)
+d = hashlib.sha256()
+for w in (vms.VMS_EXPORT_NODE_XYZ, vms.VMS_EXPORT_ROW_PTR, vms.VMS_EXPORT_COL_IDX):
+    d.update(vms.vms_mesh_export(h, w).tobytes())
+d.update(vms.vms_mesh_export(h, vms.VMS_EXPORT_MASTERS, t.n).tobytes())
+print(t.n, d.hexdigest())
+vms.vms_mesh_destroy(h)
+"""
+
+
+def test_host_setup_independent_of_thread_count():
+    """The host mesh derivation and CSR pattern run on worker threads; their
+    exports are identical for 1, 3 and 8 threads (a tree large enough to split)."""
+    import subprocess
+    import sys
+    out = {}
+    for n in (1, 3, 8):
+        env = dict(os.environ, VMS_HOST_THREADS=str(n))
+        r = subprocess.run([sys.executable, "-c", _THREADS_PROBE, ROOT], env=env, capture_output=True,
+                           text=True, timeout=600)
+        assert r.returncode == 0, r.stderr[-2000:]
+        out[n] = r.stdout.split()
+    assert int(out[1][0]) > 3 * 32768  # at least three ranges of the parallel loops
+    assert out[1][1] == out[3][1] == out[8][1]
