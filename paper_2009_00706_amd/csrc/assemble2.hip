@@ -22,7 +22,10 @@
 // contraction over (point, derivative) and the 128 columns (b, j, i) as N in
 // eight 16-column tiles t = (i, b-half) with columns (b mod 4, j), j fastest.
 //
-// Precision forms: FP64 uses v_mfma_f64_16x16x4 (one point per k-step).
+// Precision forms: FP64 uses v_mfma_f64_4x4x4 (four 4x4 blocks per
+// instruction, one point per k-step): the 8 x 8 block of a component pair
+// (i, j) is four 4 x 4 blocks, so no row is idle (a 16-row tile would leave 8
+// of its 16 rows empty), and each F value feeds both row halves.
 // MIXED_BF16 splits both operands into three bf16 terms and MIXED_FP16 into
 // two fp16 terms (with power-of-two scaling), accumulating in FP32 with
 // v_mfma_f32_16x16x32 (eight points per k-step); everything before the
@@ -300,18 +303,21 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
     const float hhalf = (float)(0.5 * hd), gh = (float)two_over_h;
     int s16 = INT_MAX;
 
-    // stage-2 accumulators and residual
-    v4d accd[8];
+    // stage-2 accumulators and residual. FP64: 4x4x4 MFMA blocks (four per
+    // instruction, block = trial component j); lane l holds, for every (i, a
+    // half ah, b half bh), K^{ij}[4 ah + m][4 bh + n] with m = l / 16,
+    // j = (l / 4) % 4, n = l % 4. Mixed: 16x16 blocks (see phase 5).
+    double acc4[4][2][2];
     v4f accf[8];
-    for (int t = 0; t < 8; ++t) {
-        accd[t] = v4d{0, 0, 0, 0};
-        accf[t] = v4f{0, 0, 0, 0};
-    }
+    for (int i = 0; i < 4; ++i)
+        for (int h = 0; h < 4; ++h) acc4[i][h >> 1][h & 1] = 0.0;
+    for (int t = 0; t < 8; ++t) accf[t] = v4f{0, 0, 0, 0};
     T R = T(0);  // lanes < 32: residual of (a = lane & 7, i = lane >> 3)
-    // FP64 with the matrix: the residual is a ninth MFMA column block (columns
-    // i < 4 carry r^i[k]); rows a = 4 r + lane / 16, column i = lane % 16
+    // FP64 with the matrix: the residual is one more 4x4x4 MFMA whose blocks
+    // 0 and 1 are the two halves of the rows a (columns i carry r^i[k]): lane
+    // l holds R[4 ((l / 4) % 4) + l / 16][l % 4] for (l / 4) % 4 < 2
     constexpr bool RES_MFMA = MODE == 0 && MAT;
-    v4d accr = v4d{0, 0, 0, 0};
+    double accr = 0.0;
     // sub-cell entry of the lane's point (lane = (p, s)), loaded one chunk ahead
     const int64_t eoff = SUB ? a.pt_off[item] : 0;
     uint32_t en_cur = (SUB && (lane >> 3) < npts) ? a.entries[eoff + (lane >> 3)] : 0u;
@@ -588,23 +594,29 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
             // ---- phase 5: stage 1 (VALU) and stage 2 (MFMA)
             const int col = lane & 15, bb = col >> 2, jc = col & 3;
             if (MODE == 0) {
-                const int k = lane >> 4, arow = lane & 15;
+                // 4x4x4 MFMA operands: lane l carries k = l / 16 of block (l / 4) % 4
+                // at row / column l % 4. A = basis rows a = 4 ah + l % 4 (both
+                // halves, the same for the four blocks); B = E^{ij}[k][4 bh + l % 4]
+                // with j = the block; each E serves both halves of a.
+                const int k = lane >> 4, j4 = (lane >> 2) & 3, n4 = lane & 3;
 #pragma unroll
                 for (int p = 0; p < 4; ++p) {
                     if (p >= nd) break;
-                    const double A = arow < 8 ? (double)SB(pb + p, k, arow) : 0.0;
-                    const double rc = arow < 4 ? (double)sQ[pb + p][QRC + 4 * (arow & 3) + k] : 0.0;
-                    accr = __builtin_amdgcn_mfma_f64_16x16x4f64(A, rc, accr, 0, 0, 0);
+                    const double A0 = (double)SB(pb + p, k, n4), A1 = (double)SB(pb + p, k, 4 + n4);
+                    const double Ar = j4 == 0 ? A0 : (j4 == 1 ? A1 : 0.0);
+                    const double rc = (double)sQ[pb + p][QRC + 4 * n4 + k];
+                    accr = __builtin_amdgcn_mfma_f64_4x4x4f64(Ar, rc, accr, 0, 0, 0);
                     double Bv[2][4];
                     for (int bh = 0; bh < 2; ++bh)
-                        for (int m = 0; m < 4; ++m) Bv[bh][m] = (double)SB(pb + p, m, 4 * bh + bb);
+                        for (int m = 0; m < 4; ++m) Bv[bh][m] = (double)SB(pb + p, m, 4 * bh + n4);
                     for (int i = 0; i < 4; ++i) {
                         double Dv[4];
-                        for (int m = 0; m < 4; ++m) Dv[m] = (double)SD(p, i, jc, k, m);
+                        for (int m = 0; m < 4; ++m) Dv[m] = (double)SD(p, i, j4, k, m);
                         for (int bh = 0; bh < 2; ++bh) {
                             const double F = Dv[0] * Bv[bh][0] + Dv[1] * Bv[bh][1] + Dv[2] * Bv[bh][2] +
                                              Dv[3] * Bv[bh][3];
-                            accd[2 * i + bh] = __builtin_amdgcn_mfma_f64_16x16x4f64(A, F, accd[2 * i + bh], 0, 0, 0);
+                            acc4[i][0][bh] = __builtin_amdgcn_mfma_f64_4x4x4f64(A0, F, acc4[i][0][bh], 0, 0, 0);
+                            acc4[i][1][bh] = __builtin_amdgcn_mfma_f64_4x4x4f64(A1, F, acc4[i][1][bh], 0, 0, 0);
                         }
                     }
                 }
@@ -752,13 +764,11 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
         const int col = lane & 15, bb = col >> 2, jc = col & 3;
         T *dst = (T *)a.em + (a.slot0 + item) * 1024;
         if (MODE == 0) {
-            for (int t = 0; t < 8; ++t) {
-                const int i = t >> 1, b = 4 * (t & 1) + bb;
-                for (int r = 0; r < 2; ++r) {
-                    const int av = 4 * r + (lane >> 4);
-                    dst[(av * 8 + b) * 16 + 4 * i + jc] = (T)accd[t][r];
-                }
-            }
+            const int m4 = lane >> 4, j4 = (lane >> 2) & 3, n4 = lane & 3;
+            for (int i = 0; i < 4; ++i)
+                for (int ah = 0; ah < 2; ++ah)
+                    for (int bh = 0; bh < 2; ++bh)
+                        dst[((4 * ah + m4) * 8 + 4 * bh + n4) * 16 + 4 * i + j4] = (T)acc4[i][ah][bh];
         } else {
             // rows 8..15 carry the second split term: fold them onto rows 0..7
             const float unscale = (MODE == 2 && s16 != INT_MAX) ? ldexpf(1.0f, -s16) : 1.0f;
@@ -776,12 +786,10 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
         }
     }
     if (RES_MFMA) {
-        if ((lane & 15) < 4 && a.resid) {
-            const int i = lane & 15;
-            for (int r = 0; r < 2; ++r) {
-                const int av = 4 * r + (lane >> 4);
-                if (sM[av] >= 0) atomicAdd(a.resid + 4 * (int64_t)sM[av] + i, (double)accr[r]);
-            }
+        const int blk = (lane >> 2) & 3;
+        if (blk < 2 && a.resid) {
+            const int av = 4 * blk + (lane >> 4), i = lane & 3;
+            if (sM[av] >= 0) atomicAdd(a.resid + 4 * (int64_t)sM[av] + i, accr);
         }
     } else if (lane < 32 && a.resid) {
         const int av = lane & 7, i = lane >> 3;
