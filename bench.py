@@ -230,10 +230,28 @@ def learned_inout(torch, vms, tree, surf, n_train=1_000_000):
             lf.classify(pts, learned=mode)
         torch.cuda.synchronize()
         tt[mode] = (time.perf_counter() - t1) / 5
+    # general queries drawn like the training set (90% within 0.02 of the surface)
+    q = I.sdf_sample_points(surf, lo, hi, 2_000_000, 12, near_frac=0.9, near_dist=0.02)
+    qe, ql = lf.classify(q, learned=False), lf.classify(q, learned=True)
+    torch.cuda.synchronize()
+    q_same = bool(torch.equal(qe, ql))
+    tq = {}
+    for mode in (False, True):
+        lf.classify(q, learned=mode)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(5):
+            lf.classify(q, learned=mode)
+        torch.cuda.synchronize()
+        tq[mode] = (time.perf_counter() - t1) / 5
     lf.close()
     return {"points": int(pts.shape[0]), "labels_equal": same,
             "exact_tests_per_s": pts.shape[0] / tt[False], "learned_tests_per_s": pts.shape[0] / tt[True],
             "gain": tt[False] / tt[True], "train_and_calibrate_s": train_s,
+            "queries": {"points": int(q.shape[0]), "labels_equal": q_same,
+                        "exact_tests_per_s": q.shape[0] / tq[False],
+                        "learned_tests_per_s": q.shape[0] / tq[True], "gain": tq[False] / tq[True],
+                        "sample": "90% within 0.02 of the surface, the rest uniform in its box grown by 0.1"},
             "note": "kept sub-cell points of the workload; exact: +x ray parity with exact predicates; "
                     "learned: FP16-MFMA network, exact test inside the per-cell margin"}
 
