@@ -114,6 +114,32 @@ def test_non_watertight_surface_rejected():
     assert ei.value.code == vms.VMS_EMESH
 
 
+def test_empty_and_duplicate_leaves_rejected():
+    t = I.uniform_octree(2)
+    empty = I.Octree(t.ax[:0], t.ay[:0], t.az[:0], t.level[:0], t.max_level)
+    with pytest.raises(vms.VmsError) as ei:
+        vms.vms_mesh_create(empty)
+    assert ei.value.code == vms.VMS_EINVAL
+    with pytest.raises(vms.VmsError) as ei:
+        vms.vms_create(empty, None, vms.make_params(), stream=0)
+    assert ei.value.code == vms.VMS_EINVAL
+    dup = I.Octree(np.concatenate([t.ax, t.ax[:1]]), np.concatenate([t.ay, t.ay[:1]]),
+                   np.concatenate([t.az, t.az[:1]]), np.concatenate([t.level, t.level[:1]]), t.max_level)
+    with pytest.raises(vms.VmsError) as ei:
+        vms.vms_mesh_create(dup)
+    assert ei.value.code == vms.VMS_EMESH
+
+
+def test_index_parity_domain_within_the_root(oracle):
+    """Leaves covering only part of the root cube (the 8 x 2 x 2 domain of the
+    two-box geometry in a root of side 8): nodes on the domain's faces inside
+    the root are ordinary boundary nodes."""
+    t, _ = I.two_box_workload(lmin=3, lmax=7, beta=2.0, n_face=4)
+    assert int(t.ay.max()) < (1 << t.max_level) // 4
+    ms = _parity(oracle, t)
+    assert ms.n_hanging > 0
+
+
 def test_misaligned_leaf_rejected():
     t = I.uniform_octree(2, max_level=3)
     ax = t.ax.copy()
