@@ -1363,10 +1363,12 @@ int vms_solve(vms_ctx *c, const void *csr_vals, const vms_fields *f, const doubl
             if (res <= rtol || it >= max_iter) break;
             vmsk::launch_axpby(st, 1.0, rr, 0.0, rr, rh, n);
             double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+            // rh . r of the next step: r . r at a restart (rh = r), else from the
+            // same multi-dot as the end-of-step residual norm (r and rh adjacent)
+            double rho_next = hv[0];
             const int it0 = it;
             for (int k = 0; it < max_iter; ++k) {
-                if ((rc = dots(rh, 1, rr))) return rc;
-                const double rho = hv[0];
+                const double rho = rho_next;
                 if (rho == 0.0) break;
                 if (k == 0) {
                     vmsk::launch_axpby(st, 1.0, rr, 0.0, rr, pp, n);
@@ -1396,8 +1398,9 @@ int vms_solve(vms_ctx *c, const void *csr_vals, const vms_fields *f, const doubl
                 omega = hv[0] / hv[1];
                 vmsk::launch_axpbypcz(st, 1.0, x, alpha, ph, omega, sh, x, n);
                 vmsk::launch_axpby(st, 1.0, ss, -omega, tt, rr, n);
-                if ((rc = dots(rr, 1, rr))) return rc;
+                if ((rc = dots(rr, 2, rr))) return rc;  // r . r, rh . r
                 if (std::sqrt(hv[0]) <= rtol * bnorm || omega == 0.0) break;
+                rho_next = hv[1];
                 rho_old = rho;
             }
             if (it == it0) break;  // breakdown before any step: no progress from a restart
