@@ -147,3 +147,73 @@ def test_batch_tree_against_reference(env, oracle):
     assert np.linalg.norm(r - R) <= 1e-12 * np.linalg.norm(R)
     for c in ctxs:
         vms.vms_destroy(c)
+
+
+@pytest.mark.timeout(900)
+def test_batch_full_size(env):
+    """The 64-tree workload at full size (log-uniform 1e4..5e5 octants, seed 3),
+    BF16x3, autotuned and replayed as a graph (the benchmark's launch): every
+    tree's values and residual equal its single-context assembly (values over
+    the rows of active nodes, identity rows exactly; norms on the device), and
+    a constant state gives a zero residual in every tree."""
+    import os
+    import time
+    torch, vms = env
+    t0 = time.perf_counter()
+    work = I.batch_workload(64, 3, workers=min(16, os.cpu_count() or 1))
+    print(f"64 trees, {sum(t.n for t, _ in work)} octants ({time.perf_counter() - t0:.1f} s)", flush=True)
+    stream = torch.cuda.Stream()
+    ctxs, fields, vals, resid, ident = [], [], [], [], []
+    with torch.cuda.stream(stream):
+        for k, (tree, surf) in enumerate(work):
+            ctx = vms.vms_create(tree, surf, vms.make_params(quad_depth=3, precision=vms.VMS_MIXED_BF16),
+                                 stream.cuda_stream)
+            sz = vms.vms_sizes(ctx)
+            xyz = vms.vms_export(ctx, vms.VMS_EXPORT_NODE_XYZ).T.astype(np.float64) / \
+                float(1 << tree.max_level) * tree.root_len + np.asarray(tree.origin)
+            f = I.make_fields(xyz, 3000 + k)
+            fields.append({n: torch.as_tensor(f[n], device="cuda") for n in f})
+            vals.append(torch.zeros(sz["nnz"], dtype=torch.float32, device="cuda"))
+            resid.append(torch.zeros(sz["n_rows"], dtype=torch.float64, device="cuda"))
+            # CSR places of the rows of inactive nodes (one diagonal block each)
+            mk = vms.vms_export(ctx, vms.VMS_EXPORT_MARKERS, tree.n)
+            ma = vms.vms_export(ctx, vms.VMS_EXPORT_MASTERS, tree.n)[mk != 1]
+            act = np.zeros(sz["n_nodes"], bool)
+            act[ma[ma >= 0]] = True
+            rp = vms.vms_export(ctx, vms.VMS_EXPORT_ROW_PTR)
+            first = rp[4 * np.nonzero(~act)[0]]
+            ident.append(torch.as_tensor((first[:, None] + np.arange(16)).ravel(), device="cuda"))
+            ctxs.append(ctx)
+        print(f"contexts ({time.perf_counter() - t0:.1f} s)", flush=True)
+        b = vms.vms_batch_create(ctxs, stream.cuda_stream)
+        vms.vms_batch_autotune(b, fields, vals, resid)
+        vms.vms_batch_use_graph(b, True)
+        for _ in range(2):
+            vms.vms_batch_assemble(b, fields, vals, resid)
+        stream.synchronize()
+        got = [(v.clone(), r.clone()) for v, r in zip(vals, resid)]
+        for c, f, v, r in zip(ctxs, fields, vals, resid):
+            vms.vms_assemble(c, f, v, r)
+        stream.synchronize()
+        worst_j = worst_r = 0.0
+        for (gv, gr), v, r, idx in zip(got, vals, resid, ident):
+            assert torch.equal(gv[idx], v[idx])
+            ej = (torch.linalg.vector_norm((gv - v).double()) /
+                  (torch.linalg.vector_norm(v.double()) ** 2 - float((v[idx].double() ** 2).sum())) ** 0.5).item()
+            er = (torch.linalg.vector_norm(gr - r) / torch.linalg.vector_norm(r)).item()
+            worst_j, worst_r = max(worst_j, ej), max(worst_r, er)
+        print(f"batch vs single contexts: worst J {worst_j:.2e}, worst R {worst_r:.2e}", flush=True)
+        assert worst_j <= 1e-6 and worst_r <= 1e-6
+        # constant state: zero residual in every tree (graph replay)
+        for f in fields:
+            for n, v in (("ux", 0.7), ("uy", -0.3), ("uz", 0.2), ("p", 0.0), ("ux0", 0.7), ("uy0", -0.3),
+                         ("uz0", 0.2)):
+                f[n].fill_(v)
+        vms.vms_batch_assemble(b, fields, vals, resid)
+        stream.synchronize()
+        rmax = max(r.abs().max().item() for r in resid)
+        print(f"constant state: max |R| {rmax:.2e}")
+        assert rmax < 1e-6
+        vms.vms_batch_destroy(b)
+    for c in ctxs:
+        vms.vms_destroy(c)
