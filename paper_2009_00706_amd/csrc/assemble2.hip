@@ -16,20 +16,22 @@
 // This is the precomputed-operator form of Alg. 6 / App. A (basis values and
 // gradients tabulated at Gauss points; the element matrix is a contraction
 // over points), split in two stages:
-//   stage 1 (VALU):  F_q[(i,k)][(b,j)] = sum_l W D^{ij}[k][l] B[l][b]
-//   stage 2 (MFMA):  K[a][(b,j,i)]     = sum_{q,k} B_q[k][a] F_q[(i,k)][(b,j)]
-// Stage 2 is a GEMM with the 8 basis rows a as M (padded to 16), the
-// contraction over (point, derivative) and the 128 columns (b, j, i) as N in
-// eight 16-column tiles t = (i, b-half) with columns (b mod 4, j), j fastest.
+//   stage 1:  F_q[(i,k)][(b,j)] = sum_l W D^{ij}[k][l] B[l][b]
+//   stage 2:  K[a][(b,j,i)]     = sum_{q,k} B_q[k][a] F_q[(i,k)][(b,j)]
+// Stage 2 is a GEMM over the 8 basis rows a, the contraction over (point,
+// derivative) and the 128 columns (b, j, i).
 //
-// Precision forms: FP64 uses v_mfma_f64_4x4x4 (four 4x4 blocks per
-// instruction, one point per k-step): the 8 x 8 block of a component pair
-// (i, j) is four 4 x 4 blocks, so no row is idle (a 16-row tile would leave 8
-// of its 16 rows empty), and each F value feeds both row halves.
-// MIXED_BF16 splits both operands into three bf16 terms and MIXED_FP16 into
-// two fp16 terms (with power-of-two scaling), accumulating in FP32 with
-// v_mfma_f32_16x16x32 (eight points per k-step); everything before the
-// contraction runs in FP32 and the result is written as FP32.
+// Precision forms. FP64 runs both stages on v_mfma_f64_4x4x4 (four 4x4
+// blocks per instruction, block = trial component j): stage 1 produces, per
+// (i, b half), the 4x4 blocks F^{ij}[k][b] directly in the register layout of
+// stage 2's second operand, and stage 2 adds them into the four 4x4 blocks of
+// each 8x8 component-pair block (no idle rows, one point per k-step).
+// MIXED_BF16 splits both stage-2 operands into three bf16 terms and
+// MIXED_FP16 into two fp16 terms (with power-of-two scaling), accumulating in
+// FP32 with v_mfma_f32_16x16x32 (eight points per k-step; rows a in 16-row
+// tiles with the second split term in rows 8-15); stage 1 and everything
+// before the contraction run in FP32 on the VALU and the result is written
+// as FP32.
 //
 // One 64-lane workgroup per element, points in chunks of 8.
 #include "geom.h"
@@ -594,10 +596,15 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
             // ---- phase 5: stage 1 (VALU) and stage 2 (MFMA)
             const int col = lane & 15, bb = col >> 2, jc = col & 3;
             if (MODE == 0) {
-                // 4x4x4 MFMA operands: lane l carries k = l / 16 of block (l / 4) % 4
-                // at row / column l % 4. A = basis rows a = 4 ah + l % 4 (both
-                // halves, the same for the four blocks); B = E^{ij}[k][4 bh + l % 4]
-                // with j = the block; each E serves both halves of a.
+                // Both stages on 4x4x4 MFMA. Lane l carries, in every operand,
+                // index l / 16 of the contraction, block (l / 4) % 4 = trial
+                // component j and row / column l % 4. Stage 1, per (i, b half bh):
+                // E^{ij}[k][4 bh + n] = sum_l D^{ij}[k][l] B[l][4 bh + n], with A =
+                // D^{ij} read transposed from LDS and B = basis columns 4 bh + n;
+                // its output lands in exactly the layout of stage 2's B operand
+                // (k = l / 16, j, n = l % 4). Stage 2: K^{ij}[4 ah + m][4 bh + n] +=
+                // sum_k B[k][4 ah + m] E^{ij}[k][4 bh + n]. The basis values A0 / A1
+                // (rows 0-3 / 4-7) serve as stage 1's B and stage 2's A alike.
                 const int k = lane >> 4, j4 = (lane >> 2) & 3, n4 = lane & 3;
 #pragma unroll
                 for (int p = 0; p < 4; ++p) {
@@ -606,17 +613,12 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
                     const double Ar = j4 == 0 ? A0 : (j4 == 1 ? A1 : 0.0);
                     const double rc = (double)sQ[pb + p][QRC + 4 * n4 + k];
                     accr = __builtin_amdgcn_mfma_f64_4x4x4f64(Ar, rc, accr, 0, 0, 0);
-                    double Bv[2][4];
-                    for (int bh = 0; bh < 2; ++bh)
-                        for (int m = 0; m < 4; ++m) Bv[bh][m] = (double)SB(pb + p, m, 4 * bh + n4);
                     for (int i = 0; i < 4; ++i) {
-                        double Dv[4];
-                        for (int m = 0; m < 4; ++m) Dv[m] = (double)SD(p, i, j4, k, m);
+                        const double Dt = (double)SD(p, i, j4, n4, k);  // D^{ij}[n4][k]
                         for (int bh = 0; bh < 2; ++bh) {
-                            const double F = Dv[0] * Bv[bh][0] + Dv[1] * Bv[bh][1] + Dv[2] * Bv[bh][2] +
-                                             Dv[3] * Bv[bh][3];
-                            acc4[i][0][bh] = __builtin_amdgcn_mfma_f64_4x4x4f64(A0, F, acc4[i][0][bh], 0, 0, 0);
-                            acc4[i][1][bh] = __builtin_amdgcn_mfma_f64_4x4x4f64(A1, F, acc4[i][1][bh], 0, 0, 0);
+                            const double E = __builtin_amdgcn_mfma_f64_4x4x4f64(Dt, bh ? A1 : A0, 0.0, 0, 0, 0);
+                            acc4[i][0][bh] = __builtin_amdgcn_mfma_f64_4x4x4f64(A0, E, acc4[i][0][bh], 0, 0, 0);
+                            acc4[i][1][bh] = __builtin_amdgcn_mfma_f64_4x4x4f64(A1, E, acc4[i][1][bh], 0, 0, 0);
                         }
                     }
                 }
