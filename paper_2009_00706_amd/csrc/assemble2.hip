@@ -254,10 +254,40 @@ struct Smem {
 // one 64-lane workgroup. JV: the Jacobian action along the direction xd
 // (DEVICE, 4 n_nodes doubles, dof 4 node + c) instead of the residual, no
 // matrix.
+// Per-lane element data of one OUT work item, loaded ahead of its use: the
+// element, its level and hanging flag, the master of slot lane % 8, the
+// constraint weight code of (corner lane / 8, slot lane % 8) and, for lanes
+// < 56, nodal field lane / 8 at that master.
+struct ItemPre {
+    int32_t e, m, hang, level;
+    uint32_t code;
+    double fv;
+};
+
+// The loads of two OUT items interleaved, so that the second item's chain
+// (item -> element -> masters -> fields) is in flight while the first is
+// assembled.
+__device__ inline void load_pre2(const AsmArgs &a, int64_t i0, int64_t i1, bool has1, ItemPre &P0,
+                                 ItemPre &P1) {
+    const int lane = threadIdx.x, s = lane & 7, bit = 2 * ((lane >> 3) * 8 + s);
+    P0.e = a.items[i0];
+    P1.e = has1 ? a.items[i1] : P0.e;
+    P0.hang = a.has_hang[P0.e];
+    P1.hang = a.has_hang[P1.e];
+    P0.level = a.level[P0.e];
+    P1.level = a.level[P1.e];
+    P0.code = (a.ccode[4 * (int64_t)P0.e + (bit >> 5)] >> (bit & 31)) & 3u;
+    P1.code = (a.ccode[4 * (int64_t)P1.e + (bit >> 5)] >> (bit & 31)) & 3u;
+    P0.m = a.masters[8 * (int64_t)P0.e + s];
+    P1.m = a.masters[8 * (int64_t)P1.e + s];
+    P0.fv = (lane < 56 && P0.m >= 0) ? field_in(a, lane >> 3)[P0.m] : 0.0;
+    P1.fv = (lane < 56 && P1.m >= 0) ? field_in(a, lane >> 3)[P1.m] : 0.0;
+}
+
 template <typename T, int MODE, bool SUB, bool MAT, int PD, bool JV = false>
 __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
                                          Smem<T, PD, MAT, JV ? 11 : 7> &sm,
-                                         const double *xd = nullptr) {
+                                         const double *xd = nullptr, const ItemPre *pre = nullptr) {
     constexpr int CP = 8;  // points per chunk (one lane group of 8 per point)
     constexpr int NF = JV ? 11 : 7;
     static_assert(!(JV && MAT), "the Jacobian action has no matrix");
@@ -273,23 +303,29 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
     auto &sM = sm.sM;
     const int lane = threadIdx.x;
     __syncthreads();  // the previous item of this workgroup is done with the LDS
-    const int e = a.items[item];
-    const bool hang = a.has_hang[e] != 0;
-    const double hd = ldexp(a.root_len, -(int)a.level[e]);
-    const double two_over_h = ldexp(a.two_over_root, (int)a.level[e]);
+    const int e = pre ? pre->e : a.items[item];
+    const bool hang = (pre ? pre->hang : a.has_hang[e]) != 0;
+    const int lev = pre ? pre->level : (int)a.level[e];
+    const double hd = ldexp(a.root_len, -lev);
+    const double two_over_h = ldexp(a.two_over_root, lev);
     const T h = (T)hd;
-    if (lane < 8) sM[lane] = a.masters[8 * (int64_t)e + lane];
+    if (lane < 8) sM[lane] = pre ? pre->m : a.masters[8 * (int64_t)e + lane];
     {
         const int v = lane >> 3, s = lane & 7, bit = 2 * (v * 8 + s);
-        const uint32_t code = (a.ccode[4 * (int64_t)e + (bit >> 5)] >> (bit & 31)) & 3u;
+        const uint32_t code = pre ? pre->code : (a.ccode[4 * (int64_t)e + (bit >> 5)] >> (bit & 31)) & 3u;
         sC[v][s] = code == 3u ? T(1) : (code == 2u ? T(0.5) : (code == 1u ? T(0.25) : T(0)));
     }
-    __syncthreads();
-    for (int idx = lane; idx < NF * 8; idx += 64) {
-        const int f = idx >> 3, s = idx & 7, m = sM[s];
-        double v = 0.0;
-        if (m >= 0) v = f < 7 ? field_in(a, f)[m] : xd[4 * (int64_t)m + (f - 7)];
-        SU(f, s) = (T)v;
+    if (pre && NF == 7) {
+        if (lane < 56) SU(lane >> 3, lane & 7) = (T)pre->fv;
+        __syncthreads();
+    } else {
+        __syncthreads();
+        for (int idx = lane; idx < NF * 8; idx += 64) {
+            const int f = idx >> 3, s = idx & 7, m = sM[s];
+            double v = 0.0;
+            if (m >= 0) v = f < 7 ? field_in(a, f)[m] : xd[4 * (int64_t)m + (f - 7)];
+            SU(f, s) = (T)v;
+        }
     }
     const int npts = SUB ? a.pt_cnt[item] : 8;
     const T rho = (T)a.rho, mu = (T)a.mu, th = (T)a.theta;
@@ -810,10 +846,21 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
 #define VMS_ASM_BOUNDS(MODE) \
     __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu((MODE) == 0 ? VMS_WPE64 : VMS_WPEMX, 8)))
 
+// OUT elements (SUB = false) two per workgroup: the second element's data
+// and fields load while the first is assembled
 template <typename T, int MODE, bool SUB, bool MAT>
 __global__ VMS_ASM_BOUNDS(MODE) void k_asm2(AsmArgs a) {
     __shared__ Smem<T, MODE == 0 ? 4 : 8, MAT, 7> sm;
-    asm_item<T, MODE, SUB, MAT, MODE == 0 ? 4 : 8>(a, blockIdx.x, sm);
+    if constexpr (SUB) {
+        asm_item<T, MODE, SUB, MAT, MODE == 0 ? 4 : 8>(a, blockIdx.x, sm);
+    } else {
+        const int64_t i0 = 2 * (int64_t)blockIdx.x, i1 = i0 + 1;
+        const bool has1 = i1 < a.n_items;
+        ItemPre P0, P1;
+        load_pre2(a, i0, i1, has1, P0, P1);
+        asm_item<T, MODE, SUB, MAT, MODE == 0 ? 4 : 8>(a, i0, sm, nullptr, &P0);
+        if (has1) asm_item<T, MODE, SUB, MAT, MODE == 0 ? 4 : 8>(a, i1, sm, nullptr, &P1);
+    }
 }
 
 // Jacobian action y = J x along x (the residual output of a receives y)
@@ -922,7 +969,7 @@ void launch_gather_f32(hipStream_t s, const float *em, const int64_t *cb_off, co
 
 void launch_assemble_f64(hipStream_t s, const AsmArgs &a, bool sub, bool mat) {
     if (a.n_items <= 0) return;
-    dim3 grid((unsigned)a.n_items), block(64);
+    dim3 grid((unsigned)(sub ? a.n_items : (a.n_items + 1) / 2)), block(64);
     if (!sub) {
         if (mat) hipLaunchKernelGGL((k_asm2<double, 0, false, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((k_asm2<double, 0, false, false>), grid, block, 0, s, a);
@@ -934,7 +981,7 @@ void launch_assemble_f64(hipStream_t s, const AsmArgs &a, bool sub, bool mat) {
 
 void launch_assemble_mixed(hipStream_t s, const AsmArgs &a, bool sub, bool mat, int fp16) {
     if (a.n_items <= 0) return;
-    dim3 grid((unsigned)a.n_items), block(64);
+    dim3 grid((unsigned)(sub ? a.n_items : (a.n_items + 1) / 2)), block(64);
 #define VMS_L(MODE)                                                                              \
     do {                                                                                         \
         if (!sub) {                                                                              \
