@@ -3,7 +3,7 @@
 One step (default workload) = vms_assemble with relabelling: adaptive sub-cell
 quadrature of every INTERCEPTED element with an exact in-out test of each
 candidate point, then the residual and Jacobian of every non-IN element
-scattered into the CSR (zeroing and identity rows included). Inputs are
+summed from element records into the CSR and the residual (identity rows included). Inputs are
 resident in HBM before the timed region. Prints one JSON line.
 
 Workloads:
@@ -479,7 +479,7 @@ def main_single(args):
         "inout_tests_per_s": (st["n_labelled"] / (avg[0] * 1e-3)) if avg[0] > 0 else None,
         "steady_state_elements_per_s": r["steady"],
         "step_device_ms": r["step_device_ms"],
-        "stage_ms": {"relabel": avg[0], "zero": avg[1], "out_elements": avg[2],
+        "stage_ms": {"relabel": avg[0], "args": avg[1], "out_elements": avg[2],
                      "intercepted_elements": avg[3], "csr_gather": avg[4]},
         "setup_s": r["setup_s"],
         "roofline": roofline(k_ms, n_pts, peak, traffic_for(args.traffic, args.workload, pname),
@@ -495,7 +495,7 @@ def main_single(args):
                                 "speedup_vs_fp64": m["value"] / r["value"]},
                                **form_errors(torch, m, r))
             del m["vals"]
-            forms[name]["stage_ms"] = {"relabel": m["stage"][0], "zero": m["stage"][1],
+            forms[name]["stage_ms"] = {"relabel": m["stage"][0], "args": m["stage"][1],
                                        "out_elements": m["stage"][2],
                                        "intercepted_elements": m["stage"][3],
                                        "csr_gather": m["stage"][4]}
@@ -593,7 +593,7 @@ def main_batch(args):
                    "n_subgp": n_sub, "tree_sizes_min_median_max": [sizes[0], sizes[len(sizes) // 2],
                                                                    sizes[-1]],
                    "precision": pname, "autotuned": cfgb, "autotune_best_ms": tune_ms},
-        "stage_ms": {"zero": float(kms[0]), "persistent_assembly": float(kms[1]),
+        "stage_ms": {"args": float(kms[0]), "persistent_assembly": float(kms[1]),
                      "csr_gather": float(kms[2])},
         "setup_s": {"generate": gen_s, "contexts": setup_s},
         "roofline": roofline(float(kms[1]), n_pts,

@@ -156,7 +156,9 @@ int vms_export(vms_ctx *ctx, uint32_t what, void *dst);
 /* Matrix and vector assembly (Alg. 1 element loop, Alg. 2, Alg. 6):
  * csr_vals (DEVICE, nnz entries, double for VMS_FP64 else float) receives the
  * Jacobian, resid (DEVICE, n_rows doubles, nullable) the residual. Both are
- * overwritten (zeroed first). OUT elements use the 2x2x2 Gauss points,
+ * overwritten; every entry is the sum of its element contributions in a fixed
+ * order (element records summed by a gather, no atomics), so repeated calls on
+ * the same input give the same bits. OUT elements use the 2x2x2 Gauss points,
  * INTERCEPTED elements their kept sub-cell points, IN elements nothing. */
 int vms_assemble(vms_ctx *ctx, const vms_fields *f, void *csr_vals, double *resid,
                  uint32_t flags);
@@ -309,9 +311,10 @@ void vms_mesh_destroy(vms_mesh *h);
 /* Per-stage timing with HIP events recorded on the context stream (off by
  * default). vms_last_timing synchronises on the last recorded event and
  * writes HOST ms[5]: relabelling (sub-cell quadrature and in-out tests),
- * zeroing of the residual, OUT-element assembly kernel, INTERCEPTED-element
- * assembly kernel, CSR summation of the element matrices (with identity
- * rows), of the last vms_assemble / vms_apply. */
+ * host set-up of the kernel arguments (no kernel), OUT-element assembly
+ * kernel, INTERCEPTED-element assembly kernel, summation of the element
+ * records into the CSR values (with identity rows) and the residual, of the
+ * last vms_assemble / vms_apply. */
 int vms_set_timing(vms_ctx *ctx, int on);
 int vms_last_timing(vms_ctx *ctx, float *ms);
 
@@ -371,8 +374,9 @@ int vms_sdf_sample(inout_handle *h, const double *px, const double *py, const do
  * work first: INTERCEPTED elements carry more quadrature points and in-out
  * work, the load imbalance that the paper's weighted partition (eq. Wpart,
  * section on dynamic load balancing) addresses across processes.
- * vms_batch_last_timing writes HOST ms[3] (zeroing kernels, persistent
- * assembly kernel, CSR summations) of the last eager (not graph-replayed)
+ * vms_batch_last_timing writes HOST ms[3] (an empty interval before the
+ * kernels, persistent assembly kernel, summations of the records into CSR
+ * values and residuals) of the last eager (not graph-replayed)
  * vms_batch_assemble, synchronising on it; VMS_EINVAL if there was none. */
 typedef struct vms_batch vms_batch;
 int vms_batch_create(vms_batch **out, vms_ctx *const *ctxs, int n, void *stream);

@@ -268,6 +268,11 @@ struct vms_ctx {
     // sub-cell items) and, per CSR block, the list of record blocks summed into it
     int64_t n_slots = 0, n_blocks = 0;
     void *d_em = nullptr;
+    // residual records (32 doubles per record) and each node's list of
+    // (record, slot) entries, 8 record + slot, ascending
+    double *d_rrec = nullptr;
+    int64_t *d_roff = nullptr;
+    int32_t *d_rlist = nullptr;
     int64_t *d_cb_off = nullptr, *d_vbase = nullptr;
     int32_t *d_contrib = nullptr, *d_vstride = nullptr;
     unsigned long long *d_counters = nullptr;  // 0: labelled points, 1: degenerate directions
@@ -525,20 +530,58 @@ static int build_gather(vms_ctx *c, const std::vector<int32_t> &stdl) {
             }
         }
     });
+    // residual lists: node n receives slot s of every record whose element has
+    // master n at slot s (counted, filled, then sorted like the block lists)
+    std::vector<int64_t> roff(m.n_nodes + 1, 0);
+    vms::parallel_for(c->n_slots, [&](int64_t b, int64_t f, int) {
+        for (int64_t sl = b; sl < f; ++sl) {
+            const int64_t e = el_of(sl);
+            for (int s = 0; s < 8; ++s) {
+                const int ms = m.masters[8 * e + s];
+                if (ms >= 0) __atomic_fetch_add(&roff[ms + 1], 1, __ATOMIC_RELAXED);
+            }
+        }
+    });
+    for (int64_t n = 0; n < m.n_nodes; ++n) roff[n + 1] += roff[n];
+    std::vector<int32_t> rlist(roff[m.n_nodes]);
+    {
+        std::vector<int64_t> pos(roff.begin(), roff.end() - 1);
+        vms::parallel_for(c->n_slots, [&](int64_t b, int64_t f, int) {
+            for (int64_t sl = b; sl < f; ++sl) {
+                const int64_t e = el_of(sl);
+                for (int s = 0; s < 8; ++s) {
+                    const int ms = m.masters[8 * e + s];
+                    if (ms >= 0) rlist[__atomic_fetch_add(&pos[ms], 1, __ATOMIC_RELAXED)] = (int32_t)(8 * sl + s);
+                }
+            }
+        });
+    }
+    vms::parallel_for(m.n_nodes, [&](int64_t b, int64_t f, int) {
+        for (int64_t n = b; n < f; ++n)
+            if (roff[n + 1] - roff[n] > 1) std::sort(rlist.begin() + roff[n], rlist.begin() + roff[n + 1]);
+    });
     const size_t esz = c->prm.precision == VMS_FP64 ? 8 : 4;
     char *em = nullptr;
+    double *rrec = nullptr;
     // a rebuild (weak boundary terms switched) replaces the previous lists
     c->buf.free(c->d_cb_off);
     c->buf.free(c->d_contrib);
     c->buf.free(c->d_vbase);
     c->buf.free(c->d_vstride);
     c->buf.free(c->d_em);
+    c->buf.free(c->d_rrec);
+    c->buf.free(c->d_roff);
+    c->buf.free(c->d_rlist);
     c->d_em = nullptr;
+    c->d_rrec = nullptr;
     if (upload(c, &c->d_cb_off, off) || upload(c, &c->d_contrib, contrib) ||
         upload(c, &c->d_vbase, vbase) || upload(c, &c->d_vstride, vstride) ||
-        c->buf.alloc(&em, (size_t)std::max<int64_t>(c->n_slots, 1) * 1024 * esz))
+        upload(c, &c->d_roff, roff) || upload(c, &c->d_rlist, rlist) ||
+        c->buf.alloc(&em, (size_t)std::max<int64_t>(c->n_slots, 1) * 1024 * esz) ||
+        c->buf.alloc(&rrec, (size_t)std::max<int64_t>(c->n_slots, 1) * 32 * sizeof(double)))
         return fail(c, VMS_ENOMEM, "device allocation failed (element-matrix records)");
     c->d_em = em;
+    c->d_rrec = rrec;
     return VMS_OK;
 }
 
@@ -715,10 +758,15 @@ static vmsk::SurfArgs surf_args(vms_ctx *c, const double *const fp[7], double *r
     s.theta = c->prm.theta;
     s.root_len = c->root_len;
     for (int k = 0; k < 3; ++k) s.g[k] = c->wbc_g[k];
-    s.resid = resid;
+    s.rrec = resid ? c->d_rrec : nullptr;
     s.em = c->d_em;
     s.slot0 = c->n_std + c->n_sub_items;
     return s;
+}
+
+// residual (or Jacobian action) = sums of the residual records by node
+static void gather_resid(vms_ctx *c, hipStream_t st, double *out) {
+    vmsk::launch_res_gather(st, c->d_rrec, c->d_roff, c->d_rlist, c->mesh.n_nodes, out);
 }
 
 // CSR values = sums of the element-matrix records, then identity blocks
@@ -1085,11 +1133,9 @@ static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *re
     }
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
     const bool fp64 = c->prm.precision == VMS_FP64;
-    const int64_t nrows = 4 * c->mesh.n_nodes;
-    if (resid) vmsk::launch_fill_f64(c->stream, resid, nrows, 0.0);
     vmsk::AsmArgs a = base_args(c);
     for (int k = 0; k < 7; ++k) a.f[k] = fp[k];
-    a.resid = resid;
+    a.rrec = resid ? c->d_rrec : nullptr;
     a.em = c->d_em;
     a.slot0 = 0;
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
@@ -1118,10 +1164,9 @@ static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *re
         HIPCHK(c, hipGetLastError());
     }
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[4], c->stream));
-    if (mat) {
-        gather_csr(c, c->stream, vals);
-        HIPCHK(c, hipGetLastError());
-    }
+    if (mat) gather_csr(c, c->stream, vals);
+    if (resid) gather_resid(c, c->stream, resid);
+    HIPCHK(c, hipGetLastError());
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[5], c->stream));
     return VMS_OK;
 }
@@ -1169,10 +1214,10 @@ static int jv_impl(vms_ctx *c, const double *const fp[7], const double *x, doubl
         HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
     }
     const bool fp64 = c->prm.precision == VMS_FP64;
-    vmsk::launch_fill_f64(c->stream, y, 4 * c->mesh.n_nodes, 0.0);
     vmsk::AsmArgs a = base_args(c);
     for (int k = 0; k < 7; ++k) a.f[k] = fp[k];
-    a.resid = y;
+    a.rrec = c->d_rrec;
+    a.slot0 = 0;
     if (tm) HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
     a.n_items = c->n_std;
     a.items = c->d_std;
@@ -1185,6 +1230,7 @@ static int jv_impl(vms_ctx *c, const double *const fp[7], const double *x, doubl
         a.pt_off = c->d_sub_off;
         a.pt_cnt = c->d_sub_cnt;
         a.entries = c->d_entries;
+        a.slot0 = c->n_std;
         vmsk::launch_jacobian_action(c->stream, a, true, fp64, x);
         HIPCHK(c, hipGetLastError());
     }
@@ -1193,6 +1239,7 @@ static int jv_impl(vms_ctx *c, const double *const fp[7], const double *x, doubl
         HIPCHK(c, hipGetLastError());
     }
     if (tm) HIPCHK(c, hipEventRecord(c->ev[4], c->stream));
+    gather_resid(c, c->stream, y);
     vmsk::launch_copy_rows(c->stream, x, y, c->d_inact, c->n_inact);
     HIPCHK(c, hipGetLastError());
     if (tm) HIPCHK(c, hipEventRecord(c->ev[5], c->stream));
@@ -1674,6 +1721,7 @@ struct vms_batch {
     int tile = 4, groups_per_cu = 8, n_cu = 256;
     std::vector<vmsk::AsmArgs> h_std, h_sub;
     std::vector<void *> h_vals;  // CSR values of each tree
+    std::vector<double *> h_resid;  // residual of each tree (or null)
     vmsk::AsmArgs *d_std = nullptr, *d_sub = nullptr;
     vmsk::BatchUnit *d_units = nullptr;
     int64_t n_units = 0, n_sub_units = 0, units_cap = 0;
@@ -1736,7 +1784,8 @@ int batch_tables(vms_batch *b, const vms_fields *f, void *const *vals, double *c
         vmsk::AsmArgs a = base_args(c);
         for (int k = 0; k < 7; ++k) a.f[k] = fp[k];
         b->h_vals[t] = vals[t];
-        a.resid = resid ? resid[t] : nullptr;
+        b->h_resid[t] = resid ? resid[t] : nullptr;
+        a.rrec = resid ? c->d_rrec : nullptr;
         a.em = c->d_em;
         a.slot0 = 0;
         a.n_items = c->n_std;
@@ -1757,19 +1806,19 @@ int batch_tables(vms_batch *b, const vms_fields *f, void *const *vals, double *c
     return VMS_OK;
 }
 
-// fills, identity rows and the persistent assembly (all kernels; no memset).
-// With timed set, events bracket the fills and the persistent kernel.
+// persistent assembly, then each tree's CSR values (with identity rows) and
+// residual summed from its records (all kernels; no memset). With timed set,
+// events bracket the persistent kernel and the summations.
 void batch_enqueue(vms_batch *b, bool timed) {
     if (timed) (void)hipEventRecord(b->ev[0], b->stream);
-    for (size_t t = 0; t < b->ctx.size(); ++t) {
-        const vmsk::AsmArgs &a = b->h_std[t];
-        if (a.resid) vmsk::launch_fill_f64(b->stream, a.resid, 4 * b->ctx[t]->mesh.n_nodes, 0.0);
-    }
     if (timed) (void)hipEventRecord(b->ev[1], b->stream);
     vmsk::launch_assemble_batch(b->stream, b->precision, b->d_std, b->d_sub, b->d_units, b->n_sub_units,
                                 b->n_units, b->d_counter, b->n_cu * b->groups_per_cu);
     if (timed) (void)hipEventRecord(b->ev[2], b->stream);
-    for (size_t t = 0; t < b->ctx.size(); ++t) gather_csr(b->ctx[t], b->stream, b->h_vals[t]);
+    for (size_t t = 0; t < b->ctx.size(); ++t) {
+        gather_csr(b->ctx[t], b->stream, b->h_vals[t]);
+        if (b->h_resid[t]) gather_resid(b->ctx[t], b->stream, b->h_resid[t]);
+    }
     if (timed) (void)hipEventRecord(b->ev[3], b->stream);
     b->timed = timed;
 }
@@ -1810,6 +1859,7 @@ int vms_batch_create(vms_batch **out, vms_ctx *const *ctxs, int n, void *stream)
     b->h_std.resize(n);
     b->h_sub.resize(n);
     b->h_vals.assign(n, nullptr);
+    b->h_resid.assign(n, nullptr);
     if (b->buf.alloc(&b->d_std, (size_t)n) || b->buf.alloc(&b->d_sub, (size_t)n) ||
         b->buf.alloc(&b->d_counter, 2)) {
         delete b;

@@ -823,15 +823,17 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
             }
         }
     }
+    // residual record of the work item (entry 4 a + i); the residual is summed
+    // from the records by node, in a fixed order
     if (RES_MFMA) {
         const int blk = (lane >> 2) & 3;
-        if (blk < 2 && a.resid) {
+        if (blk < 2 && a.rrec) {
             const int av = 4 * blk + (lane >> 4), i = lane & 3;
-            if (sM[av] >= 0) atomicAdd(a.resid + 4 * (int64_t)sM[av] + i, accr);
+            a.rrec[(a.slot0 + item) * 32 + 4 * av + i] = accr;
         }
-    } else if (lane < 32 && a.resid) {
+    } else if (lane < 32 && a.rrec) {
         const int av = lane & 7, i = lane >> 3;
-        if (sM[av] >= 0) atomicAdd(a.resid + 4 * (int64_t)sM[av] + i, (double)R);
+        a.rrec[(a.slot0 + item) * 32 + 4 * av + i] = (double)R;
     }
 }
 
@@ -950,6 +952,34 @@ __global__ void k_gather(const T *em, const int64_t *cb_off, const int32_t *cont
     }
     T *dst = vals + base + (int64_t)(e0 >> 2) * stride + (e0 & 3);
     for (int q = 0; q < V; ++q) dst[q] = (T)s[q];
+}
+
+// residual by node from the residual records (one thread per node, its
+// entries in ascending record order)
+__global__ void k_res_gather(const double *rrec, const int64_t *roff, const int32_t *rlist, int64_t n_nodes,
+                             double *out) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= n_nodes) return;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int64_t c = roff[n]; c < roff[n + 1]; ++c) {
+        const int64_t q = rlist[c];
+        const v4d v = *(const v4d *)(rrec + (q >> 3) * 32 + 4 * (q & 7));
+        s0 += v[0];
+        s1 += v[1];
+        s2 += v[2];
+        s3 += v[3];
+    }
+    out[4 * n] = s0;
+    out[4 * n + 1] = s1;
+    out[4 * n + 2] = s2;
+    out[4 * n + 3] = s3;
+}
+
+void launch_res_gather(hipStream_t s, const double *rrec, const int64_t *roff, const int32_t *rlist,
+                       int64_t n_nodes, double *out) {
+    if (n_nodes <= 0) return;
+    hipLaunchKernelGGL(k_res_gather, dim3((unsigned)((n_nodes + 255) / 256)), dim3(256), 0, s, rrec, roff,
+                       rlist, n_nodes, out);
 }
 
 void launch_gather_f64(hipStream_t s, const double *em, const int64_t *cb_off, const int32_t *contrib,

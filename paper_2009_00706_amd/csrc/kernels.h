@@ -85,8 +85,10 @@ struct AsmArgs {
     double rho, mu, theta, root_len;
     double idt, irho, two_over_root, tau_a, tau_b;
     // outputs: element-matrix records (1024 entries per work item, record
-    // slot0 + item) and the residual (atomic additions)
-    double *resid;
+    // slot0 + item) and residual records (32 doubles per work item at the
+    // same record index: entry 4 a + i for master slot a, component i); the
+    // CSR values and the residual are summed from them in a fixed order
+    double *rrec;
     void *em;
     int64_t slot0;
 };
@@ -153,16 +155,22 @@ struct SurfArgs {
     const double *xi, *w, *n, *tau;
     const double *f[7];
     double rho, mu, theta, root_len, g[3];
-    double *resid;
+    double *rrec;  // residual records, as in AsmArgs
     void *em;
     int64_t slot0;
 };
-// mode 0: records (+ residual if resid), 1: residual only, 2: Jacobian action
-// along x into resid; fp64 selects FP64 records (else FP32)
+// mode 0: records (+ residual records if rrec), 1: residual records only, 2:
+// Jacobian action along x into the residual records; fp64 selects FP64
+// element-matrix records (else FP32)
 void launch_surface(hipStream_t s, const SurfArgs &a, int mode, bool fp64, const double *x);
-// Jacobian action along x: FP64 point work if fp64, else FP32; a.resid
-// receives y (atomic additions, zeroed by the caller)
+// Jacobian action along x: FP64 point work if fp64, else FP32; the residual
+// records receive the element contributions to y
 void launch_jacobian_action(hipStream_t s, const AsmArgs &a, bool sub, bool fp64, const double *x);
+// residual (or Jacobian action) from the residual records: out[4 n + i] = sum,
+// over node n's entries rlist[roff[n] .. roff[n + 1]) (8 record + slot,
+// ascending), of rrec[32 record + 4 slot + i]; 0 for a node without entries
+void launch_res_gather(hipStream_t s, const double *rrec, const int64_t *roff, const int32_t *rlist,
+                       int64_t n_nodes, double *out);
 // y[4 n + c] = x[4 n + c] for the listed nodes (identity rows)
 void launch_copy_rows(hipStream_t s, const double *x, double *y, const int32_t *nodes, int64_t n);
 // y = A x for the CSR of 4x4 node blocks: node row n has blocks

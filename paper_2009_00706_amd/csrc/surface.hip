@@ -153,10 +153,10 @@ __global__ __launch_bounds__(64) void k_surface(SurfArgs a, const double *x) {
         // y_a = sum_b K_ab x_b: reduce over the 8 lanes of slot a
         for (int off = 1; off < 8; off <<= 1)
             for (int i = 0; i < 4; ++i) acc[i] += __shfl_xor(acc[i], off, 8);
-        if (bb == 0 && sM[aa] >= 0)
-            for (int i = 0; i < 4; ++i) atomicAdd(a.resid + 4 * (int64_t)sM[aa] + i, acc[i]);
-    } else if (a.resid && lane < 32 && sM[ra] >= 0) {
-        atomicAdd(a.resid + 4 * (int64_t)sM[ra] + ri, R);
+        if (bb == 0 && a.rrec)
+            for (int i = 0; i < 4; ++i) a.rrec[(a.slot0 + k) * 32 + 4 * aa + i] = acc[i];
+    } else if (a.rrec && lane < 32) {
+        a.rrec[(a.slot0 + k) * 32 + 4 * ra + ri] = R;
     }
 }
 

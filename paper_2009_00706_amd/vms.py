@@ -381,7 +381,7 @@ def vms_set_timing(ctx, on=True):
 
 
 def vms_last_timing(ctx):
-    """ms of the last call: relabel, zeroing, OUT-element kernel, INTERCEPTED kernel,
+    """ms of the last call: relabel, argument set-up (empty), OUT-element kernel, INTERCEPTED kernel,
     CSR summation (with identity rows)."""
     v = (C.c_float * 5)()
     _check(lib().vms_last_timing(ctx, v), ctx)
@@ -496,7 +496,7 @@ def vms_batch_autotune(b, fields, vals, resid=None):
 
 
 def vms_batch_last_timing(b):
-    """ms of the last eager batched call: zeroing, persistent kernel, CSR summations."""
+    """ms of the last eager batched call: empty interval, persistent kernel, record summations."""
     ms = (C.c_float * 3)()
     _check(lib().vms_batch_last_timing(b, ms), None)
     return list(ms)
