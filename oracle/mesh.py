@@ -21,7 +21,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from paper_2009_00706_amd.inputs import morton_key
+MORTON_BITS = 21   # per axis; 3 x 21 bits fit a uint64 key
 
 # corner c of a leaf: offset ((c>>0)&1, (c>>1)&1, (c>>2)&1) times the side
 CORNER_OFF = np.array([[(c >> 0) & 1, (c >> 1) & 1, (c >> 2) & 1] for c in range(8)], dtype=np.int64)
@@ -176,17 +176,31 @@ def derive_mesh(ax, ay, az, level, max_level, active=None):
     return ms
 
 
-def _compact1by2(v):
-    v = v & np.uint64(0x1249249249249249)
-    v = (v ^ (v >> np.uint64(2))) & np.uint64(0x10C30C30C30C30C3)
-    v = (v ^ (v >> np.uint64(4))) & np.uint64(0x100F00F00F00F00F)
-    v = (v ^ (v >> np.uint64(8))) & np.uint64(0x1F0000FF0000FF)
-    v = (v ^ (v >> np.uint64(16))) & np.uint64(0x1F00000000FFFF)
-    v = (v ^ (v >> np.uint64(32))) & np.uint64(0x1FFFFF)
-    return v
+def morton_key(x, y, z):
+    """Morton key of integer coordinates, x in the lowest bit.
+
+    Written bit by bit (bit b of x goes to key bit 3b, of y to 3b+1, of z to
+    3b+2): the node-numbering convention of the CSR, independent of any other
+    implementation of the interleave.
+    """
+    x = np.asarray(x, np.int64); y = np.asarray(y, np.int64); z = np.asarray(z, np.int64)
+    if x.size and (min(x.min(), y.min(), z.min()) < 0 or
+                   max(x.max(), y.max(), z.max()) >= (1 << MORTON_BITS)):
+        raise ValueError("coordinate outside the 21-bit Morton range")
+    key = np.zeros(np.broadcast(x, y, z).shape, np.uint64)
+    for b in range(MORTON_BITS):
+        for axis, v in enumerate((x, y, z)):
+            bit = ((v >> b) & 1).astype(np.uint64)
+            key |= bit << np.uint64(3 * b + axis)
+    return key
 
 
 def _decode(keys):
+    """Inverse of morton_key: integer (x, y, z) of each key, bit by bit."""
     k = np.asarray(keys, np.uint64)
-    return np.stack([_compact1by2(k), _compact1by2(k >> np.uint64(1)),
-                     _compact1by2(k >> np.uint64(2))], 1).astype(np.int64)
+    out = np.zeros(k.shape + (3,), np.int64)
+    for b in range(MORTON_BITS):
+        for axis in range(3):
+            bit = ((k >> np.uint64(3 * b + axis)) & np.uint64(1)).astype(np.int64)
+            out[..., axis] |= bit << b
+    return out

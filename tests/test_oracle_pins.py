@@ -818,3 +818,293 @@ def test_dirichlet_nodes_are_the_in_corners(oracle):
     assert np.array_equal(V2[~sel], V[~sel]) and np.array_equal(R2[~rows], R[~rows])
     assert np.array_equal(V2[sel], (ms.col_idx[sel] == rid[sel]).astype(float))
     assert not R2[rows].any()
+
+
+# ---------------------------------------------------------------------------
+# eq. (vms): the momentum SUPG, cross-stress and tau-bar terms at a state
+# where every one of them is non-zero in closed form. u = u_prev = c (uniform
+# flow) and p linear with gradient g: grad u = 0, a_t = 0, so r_M = g and
+# u' = -tau_M g is constant; tau_M, tau_C, taubar are the same at every point.
+# ---------------------------------------------------------------------------
+
+
+def _uniform_flow_state(h, c, g):
+    corners = np.array([[(a >> d) & 1 for d in range(3)] for a in range(8)]) * h
+    U = np.zeros((8, 4)); U[:, :3] = c; U[:, 3] = corners @ g + 0.2
+    return U, np.tile(c, (8, 1))
+
+
+UF = dict(h=0.2, dt=0.05, mu=0.03, rho=1.3, th=0.5, c=np.array([0.6, -0.9, 0.4]),
+          g=np.array([0.7, -0.4, 1.3]))
+
+
+def _uf_taus():
+    h, dt, mu, rho, c, g = (UF[k] for k in ("h", "dt", "mu", "rho", "c", "g"))
+    nu = mu / rho
+    tauM = (4 / dt ** 2 + 4 * (c @ c) / h ** 2 + 36 * nu ** 2 * 48 / h ** 4) ** -0.5
+    up = -tauM * g
+    taubar = h / (2 * np.linalg.norm(up))      # (u'.G.u')^(-1/2) with G = (2/h)^2 I
+    return tauM, up, taubar
+
+
+def test_taubar_closed_form_uniform_flow(oracle):
+    h, dt, mu, rho, th, c, g = (UF[k] for k in ("h", "dt", "mu", "rho", "th", "c", "g"))
+    prm = oracle.params(rho=rho, mu=mu, dt=dt, theta=th)
+    xi, _ = oracle.std_points(h)
+    U, U0 = _uniform_flow_state(h, c, g)
+    t = oracle.taus(prm, h, xi, U, U0)
+    tauM, up, taubar = _uf_taus()
+    np.testing.assert_allclose(t[:, 0], tauM, rtol=1e-14)
+    np.testing.assert_allclose(t[:, 1], h ** 2 / (12 * tauM), rtol=1e-14)
+    np.testing.assert_allclose(t[:, 2], taubar, rtol=1e-14)
+
+
+def _uf_element(oracle, bit):
+    h, dt, mu, rho, th, c, g = (UF[k] for k in ("h", "dt", "mu", "rho", "th", "c", "g"))
+    prm = oracle.params(rho=rho, mu=mu, dt=dt, theta=th, term_mask=1 << bit)
+    xi, w = oracle.std_points(h)
+    U, U0 = _uniform_flow_state(h, c, g)
+    R, J = oracle.element(prm, h, xi, w, np.eye(8), U, U0)
+    return R.reshape(8, 4), blocks(J)
+
+
+def test_supg_term_uniform_flow_closed_form(oracle):
+    """Term 5 of eq. (vms), -(u.grad w + grad q / rho) . u': residual and its
+    frozen-tau Jacobian (u' varies through r_M = rho (a_t + u.grad u) + grad p)."""
+    h, dt, rho, th, c = (UF[k] for k in ("h", "dt", "rho", "th", "c"))
+    tauM, up, _ = _uf_taus()
+    R, B = _uf_element(oracle, 5)
+    gradN = np.stack([integral(h, k, None).sum(1) for k in range(3)], 1)    # int d_k N_a
+    cgrad = gradN @ c                                                       # int c.grad N_a
+    for i in range(3):
+        np.testing.assert_allclose(R[:, i], -cgrad * up[i], rtol=1e-13, atol=1e-16)
+    np.testing.assert_allclose(R[:, 3], -(1 / rho) * gradN @ up, rtol=1e-13, atol=1e-16)
+    cN = sum(c[k] * integral(h, k, None) for k in range(3))                # int (c.grad N_a) N_b
+    cc = sum(c[k] * c[l] * integral(h, k, l) for k in range(3) for l in range(3))
+    L = sum(integral(h, k, k) for k in range(3))
+    sc = 1e-12 * max(np.abs(B[i][j]).max() for i in range(4) for j in range(4))
+    for i, j in itertools.product(range(3), range(3)):
+        ref = -th * up[i] * integral(h, j, None) + (i == j) * tauM * rho * (cN / dt + th * cc)
+        np.testing.assert_allclose(B[i][j], ref, rtol=0, atol=sc)
+        np.testing.assert_allclose(B[i][3], tauM * sum(c[k] * integral(h, k, i) for k in range(3)),
+                                   rtol=0, atol=sc)
+        np.testing.assert_allclose(B[3][j], tauM * (integral(h, j, None) / dt
+                                                    + th * sum(c[k] * integral(h, j, k) for k in range(3))),
+                                   rtol=0, atol=sc)
+    np.testing.assert_allclose(B[3][3], tauM / rho * L, rtol=0, atol=sc)
+
+
+def test_cross_stress_term_uniform_flow_closed_form(oracle):
+    """Term 7, w . (u' . grad u): zero residual at grad u = 0, Jacobian
+    delta_ij theta sum_k u'_k int N_a d_k N_b (the u' derivative meets grad u = 0)."""
+    h, th = UF["h"], UF["th"]
+    _, up, _ = _uf_taus()
+    R, B = _uf_element(oracle, 7)
+    assert np.abs(R).max() < 1e-16
+    ref = th * sum(up[k] * integral(h, None, k) for k in range(3))
+    sc = 1e-12 * np.abs(ref).max()
+    for i, j in itertools.product(range(4), range(4)):
+        want = ref if (i == j and i < 3) else 0 * ref
+        np.testing.assert_allclose(B[i][j], want, rtol=0, atol=sc)
+
+
+def test_taubar_term_uniform_flow_closed_form(oracle):
+    """Term 9, (u' . grad w) taubar (u' . grad u): zero residual at grad u = 0,
+    Jacobian delta_ij taubar theta sum_kl u'_k u'_l int d_k N_a d_l N_b."""
+    h, th = UF["h"], UF["th"]
+    _, up, taubar = _uf_taus()
+    R, B = _uf_element(oracle, 9)
+    assert np.abs(R).max() < 1e-16
+    ref = taubar * th * sum(up[k] * up[l] * integral(h, k, l) for k in range(3) for l in range(3))
+    sc = 1e-12 * np.abs(ref).max()
+    for i, j in itertools.product(range(4), range(4)):
+        want = ref if (i == j and i < 3) else 0 * ref
+        np.testing.assert_allclose(B[i][j], want, rtol=0, atol=sc)
+
+
+# ---------------------------------------------------------------------------
+# eq. (weakbc): Nitsche consistency, adjoint consistency and penalty terms on
+# an axis-aligned box. Weighting the node rows by phi(x_node) for phi in the
+# trilinear space turns the residual into the surface integral with test
+# function phi; the divergence theorem (fluid normal = minus the box's outward
+# normal) gives each integral in closed form.
+# ---------------------------------------------------------------------------
+
+BOX_LO = np.array([37, 43, 51]) / 128.0
+BOX_HI = np.array([91, 85, 77]) / 128.0
+
+
+def _box_moments():
+    V = float(np.prod(BOX_HI - BOX_LO))
+    cen = (BOX_LO + BOX_HI) / 2
+    return V, cen
+
+
+def _box_setup(oracle, surf):
+    t = I.uniform_octree(4)
+    ms0 = oracle.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level)
+    mk, _, _ = oracle.markers(t, ms0, surf)
+    ms = oracle.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level, active=mk != oracle.IN)
+    xyz = ms.node_xyz_int.astype(np.float64) / float(1 << t.max_level)
+    return t, mk, ms, xyz
+
+
+def _linear_fields(xyz, A, b, q=np.zeros(3), p0=0.0):
+    u = xyz @ A.T + b
+    f = {"ux": u[:, 0].copy(), "uy": u[:, 1].copy(), "uz": u[:, 2].copy(), "p": xyz @ q + p0}
+    f.update({"ux0": f["ux"].copy(), "uy0": f["uy"].copy(), "uz0": f["uz"].copy()})
+    return f
+
+
+def test_weak_bc_consistency_and_adjoint_moments(oracle):
+    """u = u_prev = A x + b, g = 0, p = 0, rho = 0 (no inflow term), no penalty:
+    what remains are -w.(2 mu eps(u) n) and -(2 mu eps(w) n).(u - g), and the
+    continuity row -q n.(u - g). With S = A + A^T, V the box volume and c its
+    centre, for m != l:
+      sum_n x_m R_(n,i)      = 2 mu V S_im
+      sum_n x_m x_l R_(n,i)  = mu V [2 S_im c_l + 2 S_il c_m + d_il v_m(c) + d_im v_l(c)]
+      sum_n x_m R_(n,p)      = V [v_m(c) + c_m tr A]
+    (every integrand is a polynomial of degree <= 2 on the faces, which the
+    three-point triangle rule integrates exactly)."""
+    s = I.box_surface(BOX_LO, BOX_HI)
+    t, mk, ms, xyz = _box_setup(oracle, s)
+    rng = np.random.default_rng(11)
+    A = rng.normal(size=(3, 3)); b = rng.normal(size=3)
+    mu = 0.7
+    prm = oracle.params(rho=0.0, mu=mu)
+    _, R, _ = oracle.weak_bc(t, ms, s, mk, _linear_fields(xyz, A, b), c_b=0.0, prm=prm, vals=False)
+    R = R.reshape(-1, 4)
+    V, cen = _box_moments()
+    S = A + A.T
+    vc = A @ cen + b
+    scale = mu * V * np.abs(S).max()
+    for i in range(3):
+        for m in range(3):
+            got = xyz[:, m] @ R[:, i]
+            assert abs(got - 2 * mu * V * S[i, m]) <= 1e-12 * scale, (i, m)
+            for l in range(3):
+                if l == m:
+                    continue
+                want = mu * V * (2 * S[i, m] * cen[l] + 2 * S[i, l] * cen[m]
+                                 + (i == l) * vc[m] + (i == m) * vc[l])
+                got = (xyz[:, m] * xyz[:, l]) @ R[:, i]
+                assert abs(got - want) <= 1e-12 * scale, (i, m, l)
+    for m in range(3):
+        want = V * (vc[m] + cen[m] * np.trace(A))
+        assert abs(xyz[:, m] @ R[:, 3] - want) <= 1e-12 * V * np.abs(A).max()
+    # the continuity row's plain sum is the net flux of a linear field: V tr A
+    assert abs(R[:, 3].sum() - V * np.trace(A)) <= 1e-12 * V * np.abs(A).max()
+
+
+def test_weak_bc_pressure_moment(oracle):
+    """u = g, p = q.x + p0: only w.(p n) remains;
+    sum_n x_m R_(n,i) = -V (d_im p(c) + c_m q_i)."""
+    s = I.box_surface(BOX_LO, BOX_HI)
+    t, mk, ms, xyz = _box_setup(oracle, s)
+    gv = np.array([0.3, -0.2, 0.5]); q = np.array([0.9, -1.4, 0.6]); p0 = 0.35
+    _, R, _ = oracle.weak_bc(t, ms, s, mk, _linear_fields(xyz, np.zeros((3, 3)), gv, q, p0),
+                             c_b=4.0, g=tuple(gv), prm=oracle.params(mu=0.5), vals=False)
+    R = R.reshape(-1, 4)
+    V, cen = _box_moments()
+    pc = q @ cen + p0
+    for i, m in itertools.product(range(3), range(3)):
+        want = -V * ((i == m) * pc + cen[m] * q[i])
+        assert abs(xyz[:, m] @ R[:, i] - want) <= 1e-12 * V, (i, m)
+    assert np.abs(R[:, 3]).max() < 1e-16
+
+
+def _grid_box_surface(h):
+    """The box's faces cut into rectangles on the element grid lines (spacing h),
+    two outward triangles each, so that every triangle lies in one element's
+    footprint. Returns the surface and the rectangles (centre, area)."""
+    verts, tris, rects = [], [], []
+    for k in range(3):
+        a1, a2 = [d for d in range(3) if d != k]
+        cuts = []
+        for d in (a1, a2):
+            inner = np.arange(np.floor(BOX_LO[d] / h) + 1, np.ceil(BOX_HI[d] / h)) * h
+            cuts.append(np.concatenate([[BOX_LO[d]], inner[(inner > BOX_LO[d]) & (inner < BOX_HI[d])],
+                                        [BOX_HI[d]]]))
+        for side, x0 in ((-1, BOX_LO[k]), (1, BOX_HI[k])):
+            for i in range(len(cuts[0]) - 1):
+                for j in range(len(cuts[1]) - 1):
+                    quad = []
+                    for (u, v) in ((i, j), (i + 1, j), (i + 1, j + 1), (i, j + 1)):
+                        p = np.zeros(3); p[k] = x0; p[a1] = cuts[0][u]; p[a2] = cuts[1][v]
+                        quad.append(p)
+                    base = len(verts)
+                    verts += quad
+                    # orientation: normal along side * e_k
+                    n = np.cross(quad[1] - quad[0], quad[2] - quad[0])
+                    if np.sign(n[k]) == side:
+                        tris += [[base, base + 1, base + 2], [base, base + 2, base + 3]]
+                    else:
+                        tris += [[base, base + 2, base + 1], [base, base + 3, base + 2]]
+                    area = (cuts[0][i + 1] - cuts[0][i]) * (cuts[1][j + 1] - cuts[1][j])
+                    rects.append((np.mean(quad, 0), area))
+    return I.Surface(np.array(verts), np.array(tris, np.int32), {"kind": "grid box"}), rects
+
+
+def test_weak_bc_penalty_closed_form(oracle):
+    """u = u_prev = g + d (constant), p = 0, rho = 0: consistency, adjoint and
+    continuity parts sum to zero over a closed surface, and the penalty
+    (tau_T = tau_N = tau_B) leaves sum_n phi(x_n) R_(n,i) = d_i sum over
+    surface pieces of tau_B(e) int phi, with tau_B = c_b mu / max(h_b, h/100)
+    and h_b the largest distance from the element's fluid corners to the box."""
+    t = I.uniform_octree(4)
+    h = 1.0 / 16
+    s, rects = _grid_box_surface(h)
+    t, mk, ms, xyz = _box_setup(oracle, s)
+    gv = np.array([0.1, 0.0, -0.2]); d = np.array([0.4, -0.7, 0.25])
+    mu, c_b = 0.05, 6.0
+    _, R, _ = oracle.weak_bc(t, ms, s, mk, _linear_fields(xyz, np.zeros((3, 3)), gv + d), c_b=c_b,
+                             g=tuple(gv), prm=oracle.params(rho=0.0, mu=mu), vals=False)
+    R = R.reshape(-1, 4)
+    off = np.array([[(v >> k) & 1 for k in range(3)] for v in range(8)], np.float64)
+    tot0, tot1 = 0.0, np.zeros(3)
+    for cen, area in rects:
+        lo = np.floor(cen / h) * h
+        corners = lo + h * off
+        outside = np.any((corners < BOX_LO) | (corners > BOX_HI), axis=1)
+        dist = np.linalg.norm(corners - np.clip(corners, BOX_LO, BOX_HI), axis=1)
+        hb = max(dist[outside].max(), 0.01 * h)
+        tau = c_b * mu / hb
+        tot0 += tau * area
+        tot1 += tau * area * cen          # int x_m over a rectangle = area * centre
+    for i in range(3):
+        assert abs(R[:, i].sum() - d[i] * tot0) <= 1e-12 * abs(d[i] * tot0)
+        for m in range(3):
+            assert abs(xyz[:, m] @ R[:, i] - d[i] * tot1[m]) <= 1e-12 * abs(d[i]) * tot0
+    assert abs(R[:, 3].sum()) <= 1e-15
+
+
+# ---------------------------------------------------------------------------
+# Independence of the reference and its node-numbering convention
+# ---------------------------------------------------------------------------
+
+
+def test_oracle_imports_nothing_from_the_product_package():
+    import subprocess
+    import sys
+    code = ("import sys; import oracle.core, oracle.mesh, oracle.mlp; "
+            "bad = [m for m in sys.modules if m.startswith('paper_2009_00706_amd')]; "
+            "print(bad); sys.exit(1 if bad else 0)")
+    root = __import__("os").path.dirname(__import__("os").path.dirname(__import__("os").path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+
+
+def test_morton_key_known_values_and_round_trip(oracle):
+    from oracle import mesh as M
+    # x in bit 0, y in bit 1, z in bit 2, then the next bit of each
+    assert M.morton_key(1, 0, 0) == 1 and M.morton_key(0, 1, 0) == 2 and M.morton_key(0, 0, 1) == 4
+    assert M.morton_key(2, 0, 0) == 8 and M.morton_key(3, 3, 3) == 63 and M.morton_key(5, 0, 0) == 0b1000001
+    assert M.morton_key(1 << 20, 0, 0) == 1 << 60 and M.morton_key(0, 0, 1 << 20) == 1 << 62
+    # ordering: sorting by key visits the 2x2x2 children of a cube with x fastest
+    pts = np.array([(x, y, z) for z in range(2) for y in range(2) for x in range(2)])
+    assert list(M.morton_key(pts[:, 0], pts[:, 1], pts[:, 2])) == list(range(8))
+    rng = np.random.default_rng(4)
+    p = rng.integers(0, 1 << 21, size=(1000, 3))
+    assert np.array_equal(M._decode(M.morton_key(p[:, 0], p[:, 1], p[:, 2])), p)
+    with pytest.raises(ValueError):
+        M.morton_key(1 << 21, 0, 0)
