@@ -262,7 +262,9 @@ int vms_solve(vms_ctx *ctx, const void *csr_vals, const vms_fields *fields, cons
  * slip). The Jacobian freezes tau_B and the inflow indicator. Builds the
  * surface points, h_b and the record lists on the first call (allocates;
  * synchronises the stream); enable = 0 switches the terms off. Contexts with
- * the terms on cannot join a vms_batch. Errors: VMS_EINVAL (no surface, c_b < 0
+ * the terms on cannot join a vms_batch, and a batch whose context has them
+ * switched on later refuses to assemble (VMS_EUNSUPPORTED, before any launch).
+ * Errors: VMS_EINVAL (no surface, c_b < 0
  * or non-finite values), VMS_ENOMEM, VMS_EHIP. */
 int vms_set_weak_bc(vms_ctx *ctx, int enable, double c_b, const double *g);
 
@@ -288,11 +290,17 @@ int inout_classify(const vms_surface *surf, const double *px, const double *py, 
                    int64_t n, uint8_t *labels, uint32_t mode, const void *mlp, void *stream);
 
 /* Reusable in-out handle: the surface's acceleration structure built once
- * (host pointers read during the call; device memory owned by the handle).
- * inout_classify_prepared has the semantics of inout_classify without any
- * allocation; the handle is bound to stream. */
+ * (host pointers read during the call; device memory owned by the handle);
+ * the handle is bound to stream. inout_classify_prepared has the semantics of
+ * inout_classify. In VMS_INOUT_EXACT mode it allocates nothing. In
+ * VMS_INOUT_LEARNED mode it uses 20 bytes of handle-owned scratch per point
+ * (network outputs, the indices sent to the exact test, their count):
+ * inout_reserve(h, n) allocates it for up to n points beforehand, so that
+ * later calls of at most n points allocate nothing; a call with more points
+ * than reserved grows it (allocates, synchronising). */
 typedef struct inout_handle inout_handle;
 int inout_prepare(const vms_surface *surf, void *stream, inout_handle **out);
+int inout_reserve(inout_handle *h, int64_t n);
 int inout_classify_prepared(inout_handle *h, const double *px, const double *py, const double *pz,
                             int64_t n, uint8_t *labels, uint32_t mode, const void *mlp);
 void inout_release(inout_handle *h);
@@ -370,7 +378,11 @@ int vms_sdf_sample(inout_handle *h, const double *px, const double *py, const do
  * candidate on the given buffers and keeps the fastest. With
  * vms_batch_use_graph(b, 1) the launch sequence (zeroing kernels and the
  * persistent assembly) is captured into a HIP graph at the first call and
- * replayed while the buffer pointers stay the same. The queue puts the sub-cell
+ * replayed while the buffer pointers stay the same. Every call re-checks its
+ * contexts: one whose record buffers were rebuilt since (weak boundary terms
+ * switched on and off again) is re-read and the captured graph dropped; one
+ * with weak boundary terms on makes the call return VMS_EUNSUPPORTED before
+ * any launch. The queue puts the sub-cell
  * work first: INTERCEPTED elements carry more quadrature points and in-out
  * work, the load imbalance that the paper's weighted partition (eq. Wpart,
  * section on dynamic load balancing) addresses across processes.

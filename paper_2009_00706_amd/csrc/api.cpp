@@ -19,6 +19,7 @@
 #include "mesh.h"
 #include "par.h"
 #include "mlp.h"
+#include "surface_pack.h"
 
 using vmsk::SurfDev;
 
@@ -31,6 +32,114 @@ int vmsm_sdf(hipStream_t s, const vmsk::SurfDev &S, const std::vector<double> &t
 #ifndef VMS_ITEM_PTS
 #define VMS_ITEM_PTS 64
 #endif
+
+namespace vms {
+
+// Watertightness and orientation: every directed edge appears once and its
+// reverse appears too.
+int check_watertight(const vms_surface *s, std::string &err) {
+    const int64_t nt = s->n_tri;
+    std::vector<uint64_t> fwd;
+    fwd.reserve(3 * nt);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int k = 0; k < 3; ++k) {
+            int64_t a = s->tri[3 * t + k], b = s->tri[3 * t + (k + 1) % 3];
+            if (a < 0 || b < 0 || a >= s->n_vert || b >= s->n_vert || a == b) {
+                err = "triangle with an invalid vertex index";
+                return VMS_EINVAL;
+            }
+            fwd.push_back(((uint64_t)a << 32) | (uint64_t)b);
+        }
+    std::sort(fwd.begin(), fwd.end());
+    for (size_t i = 1; i < fwd.size(); ++i)
+        if (fwd[i] == fwd[i - 1]) { err = "surface not consistently oriented (repeated edge)"; return VMS_EMESH; }
+    for (uint64_t e : fwd) {
+        uint64_t r = ((e & 0xffffffffull) << 32) | (e >> 32);
+        if (!std::binary_search(fwd.begin(), fwd.end(), r)) {
+            err = "surface not watertight (edge without its opposite)";
+            return VMS_EMESH;
+        }
+    }
+    return VMS_OK;
+}
+
+// bin index, the same arithmetic as the device query
+static inline int host_bin(double v, double v0, double inv, int n) {
+    volatile double d = v - v0;
+    volatile double t = d * inv;
+    int b = (int)std::floor(t);
+    return b < 0 ? 0 : (b >= n ? n - 1 : b);
+}
+
+int pack_surface(const vms_surface *s, SurfacePack &P, std::string &err) {
+    if (!s || s->n_tri <= 0 || s->n_vert <= 0 || !s->verts || !s->tri) {
+        err = "empty or null surface";
+        return VMS_EINVAL;
+    }
+    int rc = check_watertight(s, err);
+    if (rc) return rc;
+    const int64_t nt = s->n_tri;
+    if (nt > INT32_MAX) { err = "too many triangles"; return VMS_EINVAL; }
+    P.tv.resize(9 * nt);
+    P.tbox.resize(6 * nt);
+    SurfDev &S = P.S;
+    S = SurfDev{};
+    for (int k = 0; k < 3; ++k) { S.lo[k] = INFINITY; S.hi[k] = -INFINITY; }
+    for (int64_t v = 0; v < s->n_vert; ++v)
+        for (int k = 0; k < 3; ++k) {
+            double x = s->verts[3 * v + k];
+            if (!std::isfinite(x)) { err = "non-finite surface vertex"; return VMS_EINVAL; }
+            S.lo[k] = std::min(S.lo[k], x);
+            S.hi[k] = std::max(S.hi[k], x);
+        }
+    for (int64_t t = 0; t < nt; ++t) {
+        for (int c = 0; c < 3; ++c)
+            for (int k = 0; k < 3; ++k) P.tv[9 * t + 3 * c + k] = s->verts[3 * s->tri[3 * t + c] + k];
+        for (int k = 0; k < 3; ++k) {
+            double a = P.tv[9 * t + k], b = P.tv[9 * t + 3 + k], c = P.tv[9 * t + 6 + k];
+            P.tbox[6 * t + k] = std::min(a, std::min(b, c));
+            P.tbox[6 * t + 3 + k] = std::max(a, std::max(b, c));
+        }
+    }
+    // (y, z) bins for +x rays
+    int nb = (int)std::ceil(std::sqrt((double)nt));
+    nb = std::max(1, std::min(nb, 1024));
+    S.n_tri = (int32_t)nt;
+    S.nby = S.nbz = nb;
+    S.y0 = S.lo[1];
+    S.z0 = S.lo[2];
+    double wy = S.hi[1] - S.lo[1], wz = S.hi[2] - S.lo[2];
+    S.iny = wy > 0 ? nb / wy : 0.0;
+    S.inz = wz > 0 ? nb / wz : 0.0;
+    P.off.assign((size_t)nb * nb + 1, 0);
+    auto range = [&](int64_t t, int &y0, int &y1, int &z0, int &z1) {
+        y0 = host_bin(P.tbox[6 * t + 1], S.y0, S.iny, nb);
+        y1 = host_bin(P.tbox[6 * t + 4], S.y0, S.iny, nb);
+        z0 = host_bin(P.tbox[6 * t + 2], S.z0, S.inz, nb);
+        z1 = host_bin(P.tbox[6 * t + 5], S.z0, S.inz, nb);
+    };
+    for (int64_t t = 0; t < nt; ++t) {
+        int y0, y1, z0, z1;
+        range(t, y0, y1, z0, z1);
+        for (int z = z0; z <= z1; ++z)
+            for (int y = y0; y <= y1; ++y) P.off[(size_t)z * nb + y + 1]++;
+    }
+    for (size_t i = 1; i < P.off.size(); ++i) P.off[i] += P.off[i - 1];
+    P.ids.assign(P.off.back(), 0);
+    std::vector<int32_t> fillp(P.off.begin(), P.off.end() - 1);
+    for (int64_t t = 0; t < nt; ++t) {
+        int y0, y1, z0, z1;
+        range(t, y0, y1, z0, z1);
+        for (int z = z0; z <= z1; ++z)
+            for (int y = y0; y <= y1; ++y) P.ids[fillp[(size_t)z * nb + y]++] = (int32_t)t;
+    }
+    return VMS_OK;
+}
+
+}  // namespace vms
+
+using vms::check_watertight;
+using vms::host_bin;
 
 namespace {
 
@@ -76,120 +185,33 @@ struct SurfaceHost {
     double lo[3], hi[3];
 };
 
-int check_watertight(const vms_surface *s, std::string &err) {
-    const int64_t nt = s->n_tri;
-    std::vector<uint64_t> fwd;
-    fwd.reserve(3 * nt);
-    for (int64_t t = 0; t < nt; ++t)
-        for (int k = 0; k < 3; ++k) {
-            int64_t a = s->tri[3 * t + k], b = s->tri[3 * t + (k + 1) % 3];
-            if (a < 0 || b < 0 || a >= s->n_vert || b >= s->n_vert || a == b) {
-                err = "triangle with an invalid vertex index";
-                return VMS_EINVAL;
-            }
-            fwd.push_back(((uint64_t)a << 32) | (uint64_t)b);
-        }
-    std::sort(fwd.begin(), fwd.end());
-    for (size_t i = 1; i < fwd.size(); ++i)
-        if (fwd[i] == fwd[i - 1]) { err = "surface not consistently oriented (repeated edge)"; return VMS_EMESH; }
-    for (uint64_t e : fwd) {
-        uint64_t r = ((e & 0xffffffffull) << 32) | (e >> 32);
-        if (!std::binary_search(fwd.begin(), fwd.end(), r)) {
-            err = "surface not watertight (edge without its opposite)";
-            return VMS_EMESH;
-        }
-    }
-    return VMS_OK;
-}
-
-// bin index, the same arithmetic as the device query
-inline int host_bin(double v, double v0, double inv, int n) {
-    volatile double d = v - v0;
-    volatile double t = d * inv;
-    int b = (int)std::floor(t);
-    return b < 0 ? 0 : (b >= n ? n - 1 : b);
-}
-
 int build_surface(const vms_surface *s, hipStream_t st, SurfaceHost &H, std::string &err) {
-    if (!s || s->n_tri <= 0 || s->n_vert <= 0 || !s->verts || !s->tri) {
-        err = "empty or null surface";
-        return VMS_EINVAL;
-    }
-    int rc = check_watertight(s, err);
+    vms::SurfacePack P;
+    int rc = vms::pack_surface(s, P, err);
     if (rc) return rc;
-    const int64_t nt = s->n_tri;
-    H.tv.resize(9 * nt);
-    H.tbox.resize(6 * nt);
-    for (int k = 0; k < 3; ++k) { H.lo[k] = INFINITY; H.hi[k] = -INFINITY; }
-    for (int64_t v = 0; v < s->n_vert; ++v)
-        for (int k = 0; k < 3; ++k) {
-            double x = s->verts[3 * v + k];
-            if (!std::isfinite(x)) { err = "non-finite surface vertex"; return VMS_EINVAL; }
-            H.lo[k] = std::min(H.lo[k], x);
-            H.hi[k] = std::max(H.hi[k], x);
-        }
-    for (int64_t t = 0; t < nt; ++t) {
-        for (int c = 0; c < 3; ++c)
-            for (int k = 0; k < 3; ++k) H.tv[9 * t + 3 * c + k] = s->verts[3 * s->tri[3 * t + c] + k];
-        for (int k = 0; k < 3; ++k) {
-            double a = H.tv[9 * t + k], b = H.tv[9 * t + 3 + k], c = H.tv[9 * t + 6 + k];
-            H.tbox[6 * t + k] = std::min(a, std::min(b, c));
-            H.tbox[6 * t + 3 + k] = std::max(a, std::max(b, c));
-        }
-    }
-    // (y, z) bins for +x rays
-    int nb = (int)std::ceil(std::sqrt((double)nt));
-    nb = std::max(1, std::min(nb, 1024));
-    SurfDev &S = H.S;
-    S.n_tri = (int32_t)nt;
-    S.nby = S.nbz = nb;
-    for (int k = 0; k < 3; ++k) { S.lo[k] = H.lo[k]; S.hi[k] = H.hi[k]; }
-    S.y0 = H.lo[1];
-    S.z0 = H.lo[2];
-    double wy = H.hi[1] - H.lo[1], wz = H.hi[2] - H.lo[2];
-    S.iny = wy > 0 ? nb / wy : 0.0;
-    S.inz = wz > 0 ? nb / wz : 0.0;
-    std::vector<int32_t> cnt((size_t)nb * nb + 1, 0);
-    auto range = [&](int64_t t, int &y0, int &y1, int &z0, int &z1) {
-        y0 = host_bin(H.tbox[6 * t + 1], S.y0, S.iny, nb);
-        y1 = host_bin(H.tbox[6 * t + 4], S.y0, S.iny, nb);
-        z0 = host_bin(H.tbox[6 * t + 2], S.z0, S.inz, nb);
-        z1 = host_bin(H.tbox[6 * t + 5], S.z0, S.inz, nb);
-    };
-    for (int64_t t = 0; t < nt; ++t) {
-        int y0, y1, z0, z1;
-        range(t, y0, y1, z0, z1);
-        for (int z = z0; z <= z1; ++z)
-            for (int y = y0; y <= y1; ++y) cnt[(size_t)z * nb + y + 1]++;
-    }
-    for (size_t i = 1; i < cnt.size(); ++i) cnt[i] += cnt[i - 1];
-    std::vector<int32_t> ids(cnt.back());
-    std::vector<int32_t> fillp(cnt.begin(), cnt.end() - 1);
-    for (int64_t t = 0; t < nt; ++t) {
-        int y0, y1, z0, z1;
-        range(t, y0, y1, z0, z1);
-        for (int z = z0; z <= z1; ++z)
-            for (int y = y0; y <= y1; ++y) ids[fillp[(size_t)z * nb + y]++] = (int32_t)t;
-    }
+    H.S = P.S;
+    for (int k = 0; k < 3; ++k) { H.lo[k] = P.S.lo[k]; H.hi[k] = P.S.hi[k]; }
     double *dtv, *dtb;
     int32_t *doff, *dids;
-    if (H.buf.alloc(&dtv, H.tv.size()) || H.buf.alloc(&dtb, H.tbox.size()) ||
-        H.buf.alloc(&doff, cnt.size()) || H.buf.alloc(&dids, ids.size())) {
+    if (H.buf.alloc(&dtv, P.tv.size()) || H.buf.alloc(&dtb, P.tbox.size()) ||
+        H.buf.alloc(&doff, P.off.size()) || H.buf.alloc(&dids, P.ids.size())) {
         err = "device allocation failed (surface)";
         return VMS_ENOMEM;
     }
-    if (hipMemcpyAsync(dtv, H.tv.data(), H.tv.size() * 8, hipMemcpyHostToDevice, st) ||
-        hipMemcpyAsync(dtb, H.tbox.data(), H.tbox.size() * 8, hipMemcpyHostToDevice, st) ||
-        hipMemcpyAsync(doff, cnt.data(), cnt.size() * 4, hipMemcpyHostToDevice, st) ||
-        (ids.size() && hipMemcpyAsync(dids, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, st)) ||
+    if (hipMemcpyAsync(dtv, P.tv.data(), P.tv.size() * 8, hipMemcpyHostToDevice, st) ||
+        hipMemcpyAsync(dtb, P.tbox.data(), P.tbox.size() * 8, hipMemcpyHostToDevice, st) ||
+        hipMemcpyAsync(doff, P.off.data(), P.off.size() * 4, hipMemcpyHostToDevice, st) ||
+        (P.ids.size() && hipMemcpyAsync(dids, P.ids.data(), P.ids.size() * 4, hipMemcpyHostToDevice, st)) ||
         hipStreamSynchronize(st)) {
         err = "device copy failed (surface)";
         return VMS_EHIP;
     }
-    S.tv = dtv;
-    S.tbox = dtb;
-    S.bin_off = doff;
-    S.bin_tri = dids;
+    H.S.tv = dtv;
+    H.S.tbox = dtb;
+    H.S.bin_off = doff;
+    H.S.bin_tri = dids;
+    H.tv = std::move(P.tv);
+    H.tbox = std::move(P.tbox);
     return VMS_OK;
 }
 
@@ -275,6 +297,9 @@ struct vms_ctx {
     int32_t *d_rlist = nullptr;
     int64_t *d_cb_off = nullptr, *d_vbase = nullptr;
     int32_t *d_contrib = nullptr, *d_vstride = nullptr;
+    // bumped whenever the record buffers and gather lists are rebuilt, so that
+    // a batch holding this context re-reads them (and drops a captured graph)
+    uint64_t gen = 0;
     unsigned long long *d_counters = nullptr;  // 0: labelled points, 1: degenerate directions
     unsigned int *d_flag = nullptr;            // device-side overflow flag
     double *d_norm = nullptr;
@@ -582,6 +607,7 @@ static int build_gather(vms_ctx *c, const std::vector<int32_t> &stdl) {
         return fail(c, VMS_ENOMEM, "device allocation failed (element-matrix records)");
     c->d_em = em;
     c->d_rrec = rrec;
+    ++c->gen;
     return VMS_OK;
 }
 
@@ -1585,6 +1611,12 @@ int inout_prepare(const vms_surface *s, void *stream, inout_handle **out) {
     return VMS_OK;
 }
 
+int inout_reserve(inout_handle *h, int64_t n) {
+    if (!h || n < 0) return fail(nullptr, VMS_EINVAL, "null handle or negative size");
+    if (vmsm::reserve_filter(h->filter, n)) return fail(nullptr, VMS_ENOMEM, "device allocation failed");
+    return VMS_OK;
+}
+
 void inout_release(inout_handle *h) {
     if (!h) return;
     (void)hipStreamSynchronize(h->stream);
@@ -1732,6 +1764,7 @@ struct vms_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<const void *> cap_ptrs;
+    std::vector<uint64_t> gens;  // generation of each context's buffers when last read
     // timing of the last eager launch sequence
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     bool timed = false;
@@ -1750,6 +1783,33 @@ int bfail(vms_batch *b, int code, const std::string &m) {
     if (b) b->err = m;
     set_global_err(m);
     return code;
+}
+
+int batch_units(vms_batch *b);
+
+void drop_graph(vms_batch *b) {
+    if (!b->captured) return;
+    (void)hipGraphExecDestroy(b->exec);
+    (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->captured = false;
+}
+
+// Every call re-checks its contexts: weak boundary terms switched on after
+// the batch was made are refused, and rebuilt record buffers (a new
+// generation) invalidate the unit list and any captured graph.
+int batch_check(vms_batch *b) {
+    for (vms_ctx *c : b->ctx)
+        if (c->wbc) return bfail(b, VMS_EUNSUPPORTED, "the batched form has no weak boundary terms");
+    bool stale = false;
+    for (size_t t = 0; t < b->ctx.size(); ++t) stale |= b->ctx[t]->gen != b->gens[t];
+    if (!stale) return VMS_OK;
+    drop_graph(b);
+    int rc = batch_units(b);
+    if (rc) return rc;
+    for (size_t t = 0; t < b->ctx.size(); ++t) b->gens[t] = b->ctx[t]->gen;
+    return VMS_OK;
 }
 
 int batch_units(vms_batch *b) {
@@ -1867,6 +1927,7 @@ int vms_batch_create(vms_batch **out, vms_ctx *const *ctxs, int n, void *stream)
     }
     int rc = batch_units(b);
     if (rc) { delete b; return rc; }
+    for (vms_ctx *c : b->ctx) b->gens.push_back(c->gen);
     *out = b;
     return VMS_OK;
 }
@@ -1876,13 +1937,7 @@ int vms_batch_set_config(vms_batch *b, int tile, int groups_per_cu) {
     b->groups_per_cu = groups_per_cu;
     if (tile != b->tile) {
         b->tile = tile;
-        if (b->captured) {  // the captured graph refers to the old unit list
-            (void)hipGraphExecDestroy(b->exec);
-            (void)hipGraphDestroy(b->graph);
-            b->exec = nullptr;
-            b->graph = nullptr;
-            b->captured = false;
-        }
+        drop_graph(b);  // the captured graph refers to the old unit list
         return batch_units(b);
     }
     return VMS_OK;
@@ -1904,6 +1959,8 @@ int vms_batch_use_graph(vms_batch *b, int on) {
 
 int vms_batch_assemble(vms_batch *b, const vms_fields *f, void *const *vals, double *const *resid) {
     if (!b || !f || !vals) return bfail(b, VMS_EINVAL, "null argument");
+    int rc0 = batch_check(b);
+    if (rc0) return rc0;
     const size_t n = b->ctx.size();
     std::vector<const void *> ptrs;
     for (size_t t = 0; t < n; ++t) {
@@ -1923,13 +1980,7 @@ int vms_batch_assemble(vms_batch *b, const vms_fields *f, void *const *vals, dou
         if (hipGetLastError() != hipSuccess) return bfail(b, VMS_EHIP, "launch failed");
         return VMS_OK;
     }
-    if (b->captured) {
-        (void)hipGraphExecDestroy(b->exec);
-        (void)hipGraphDestroy(b->graph);
-        b->exec = nullptr;
-        b->graph = nullptr;
-        b->captured = false;
-    }
+    drop_graph(b);
     if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return bfail(b, VMS_EHIP, "stream capture failed to start");
     batch_enqueue(b, false);

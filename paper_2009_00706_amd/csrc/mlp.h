@@ -53,6 +53,9 @@ void launch_decide(hipStream_t s, const float *pred, int64_t n, float margin, co
                    const double *px, const double *py, const double *pz, uint8_t *labels,
                    int64_t *idx, unsigned long long *count);
 
+// Grow the filter's scratch to n points (no-op if it holds that many).
+int reserve_filter(Filter &f, int64_t n);
+
 int classify_learned(hipStream_t s, Filter &f, const MlpHandle *net, const vmsk::SurfDev &S,
                      const double *px, const double *py, const double *pz, int64_t n,
                      uint8_t *labels);

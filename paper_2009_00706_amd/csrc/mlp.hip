@@ -421,18 +421,29 @@ struct vmsm::MlpHandle {
 };
 
 namespace vmsm {
+__global__ void k_zero_count(unsigned long long *c) {
+    if (threadIdx.x == 0) *c = 0ull;
+}
+
+int reserve_filter(Filter &f, int64_t n) {
+    if (n <= f.cap) return VMS_OK;
+    f.release();
+    if (hipMalloc(&f.d_idx, n * sizeof(int64_t)) || hipMalloc(&f.d_count, sizeof(unsigned long long)) ||
+        hipMalloc(&f.d_pred, n * sizeof(float))) {
+        f.release();
+        return VMS_ENOMEM;
+    }
+    f.cap = n;
+    return VMS_OK;
+}
+
 int classify_learned(hipStream_t s, Filter &f, const MlpHandle *h, const vmsk::SurfDev &S,
                      const double *px, const double *py, const double *pz, int64_t n,
                      uint8_t *labels) {
     if (n <= 0) return VMS_OK;
-    if (f.cap < n) {
-        f.release();
-        if (hipMalloc(&f.d_idx, n * sizeof(int64_t)) || hipMalloc(&f.d_count, sizeof(unsigned long long)) ||
-            hipMalloc(&f.d_pred, n * sizeof(float)))
-            return VMS_ENOMEM;
-        f.cap = n;
-    }
-    if (hipMemsetAsync(f.d_count, 0, sizeof(unsigned long long), s)) return VMS_EHIP;
+    int rc = reserve_filter(f, n);  // allocates only beyond the reserved capacity
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, s, f.d_count);
     launch_predict(s, h->net(), px, py, pz, n, f.d_pred);
     launch_decide(s, f.d_pred, n, h->margin, h->grid(), px, py, pz, labels, f.d_idx, f.d_count);
     vmsk::launch_point_labels_list(s, S, f.d_idx, f.d_count, n, px, py, pz, labels, nullptr);

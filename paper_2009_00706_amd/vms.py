@@ -31,6 +31,7 @@ EXPORTED = ["vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply"
             "vms_set_weak_bc", "vms_element_weights",
             "inout_classify",
             "inout_prepare", "inout_classify_prepared", "inout_release", "vms_stats",
+            "inout_reserve",
             "vms_mesh_create", "vms_mesh_sizes", "vms_mesh_export", "vms_mesh_destroy",
             "vms_set_timing", "vms_last_timing", "vms_mlp_create", "vms_mlp_get_params",
             "vms_mlp_set_margin", "vms_mlp_set_margin_grid", "vms_mlp_grad", "vms_mlp_train", "vms_mlp_adam_step",
@@ -97,6 +98,8 @@ def lib():
         L.inout_classify_prepared.argtypes = [p, p, p, p, i64, p, u32, p]
         L.inout_release.argtypes = [p]
         L.inout_release.restype = None
+        L.inout_reserve.argtypes = [p, i64]
+        L.inout_reserve.restype = C.c_int
         L.vms_stats.argtypes = [p, p]
         L.vms_mesh_create.argtypes = [C.POINTER(p), C.POINTER(Octree), p]
         L.vms_mesh_sizes.argtypes = [p, p, p, p]
@@ -370,6 +373,10 @@ def inout_classify_prepared(h, px, py, pz, labels, mode=VMS_INOUT_EXACT, mlp=Non
     rc = lib().inout_classify_prepared(h, _ptr(px), _ptr(py), _ptr(pz), px.numel(), _ptr(labels),
                                        mode, C.c_void_p(mlp) if mlp else None)
     _check(rc, None)
+
+
+def inout_reserve(h, n):
+    _check(lib().inout_reserve(h, int(n)), None)
 
 
 def inout_release(h):

@@ -118,6 +118,36 @@ def test_batch_graph_replays(env):
         vms.vms_destroy(c)
 
 
+def test_batch_refuses_weak_bc_switched_on_later(env):
+    """Weak boundary terms switched on for a context after it joined a batch:
+    the batch refuses to assemble (before any launch); switched off again, the
+    rebuilt records are re-read and the (graph-replayed) batch equals the single
+    assemblies."""
+    torch, vms = env
+    stream, ctxs, fields, vals, resid, _, masks = build(torch, vms, 0, n_trees=3, seed=5)
+    with torch.cuda.stream(stream):
+        b = vms.vms_batch_create(ctxs, stream.cuda_stream)
+        vms.vms_batch_use_graph(b, True)
+        vms.vms_batch_assemble(b, fields, vals, resid)
+        stream.synchronize()
+        vms.vms_set_weak_bc(ctxs[1], True, 4.0, (0.0, 0.0, 0.0))
+        with pytest.raises(vms.VmsError) as e:
+            vms.vms_batch_assemble(b, fields, vals, resid)
+        assert e.value.code == vms.VMS_EUNSUPPORTED
+        vms.vms_set_weak_bc(ctxs[1], False, 0.0, (0.0, 0.0, 0.0))
+        for v in vals:
+            v.fill_(7.0)
+        vms.vms_batch_assemble(b, fields, vals, resid)
+        stream.synchronize()
+        got = [(v.cpu().numpy().copy(), r.cpu().numpy().copy()) for v, r in zip(vals, resid)]
+        vms.vms_batch_destroy(b)
+    ref = singles(torch, vms, stream, ctxs, fields, vals, resid)
+    for (rv, rr), (gv, gr), m in zip(ref, got, masks):
+        assert close_mat(gv, rv, m, 1e-13) and close(gr, rr, 1e-13)
+    for c in ctxs:
+        vms.vms_destroy(c)
+
+
 def test_batch_tree_against_reference(env, oracle):
     torch, vms = env
     stream, ctxs, fields, vals, resid, trees, masks = build(torch, vms, 0, n_trees=3, seed=11)
