@@ -305,6 +305,26 @@ int inout_classify_prepared(inout_handle *h, const double *px, const double *py,
                             int64_t n, uint8_t *labels, uint32_t mode, const void *mlp);
 void inout_release(inout_handle *h);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the exact
+ * labels of inout_classify (mode VMS_INOUT_EXACT) with the surface's staging
+ * (packed triangles, their boxes and the (y, z) bin grid, about 120 bytes per
+ * triangle plus the bins) in a static device array of VMS_STATIC_SCRATCH_MIB
+ * MiB that each GPU holds from the first call on it until the process ends.
+ * Allocates no device memory. surf: HOST arrays (read during the call);
+ * px, py, pz, labels: DEVICE arrays of n entries on the current device;
+ * stream: a hipStream_t of the current device. The staging is copied in on
+ * stream and the call synchronises stream before returning. All calls on one
+ * GPU share the array and each overwrites it: calls that overlap on one GPU
+ * (other threads) race. Errors: VMS_EINVAL (null argument, negative n,
+ * invalid surface), VMS_EMESH (surface not closed / not consistently
+ * oriented), VMS_EOVERFLOW (staging larger than the array; nothing is
+ * launched), VMS_EHIP. Message: inout_static_last_error(). */
+#define VMS_STATIC_SCRATCH_MIB 32
+int inout_classify_static(const vms_surface *surf, const double *px, const double *py,
+                          const double *pz, int64_t n, uint8_t *labels, void *stream);
+const char *inout_static_last_error(void);
+
 /* Host-only mesh derivation (no device involved): the node numbering,
  * hanging constraints and CSR pattern that vms_create derives, for checks on
  * machines without a GPU. markers (HOST, nullable) excludes IN elements

@@ -31,7 +31,7 @@ EXPORTED = ["vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply"
             "vms_set_weak_bc", "vms_element_weights",
             "inout_classify",
             "inout_prepare", "inout_classify_prepared", "inout_release", "vms_stats",
-            "inout_reserve",
+            "inout_reserve", "inout_classify_static", "inout_static_last_error",
             "vms_mesh_create", "vms_mesh_sizes", "vms_mesh_export", "vms_mesh_destroy",
             "vms_set_timing", "vms_last_timing", "vms_mlp_create", "vms_mlp_get_params",
             "vms_mlp_set_margin", "vms_mlp_set_margin_grid", "vms_mlp_grad", "vms_mlp_train", "vms_mlp_adam_step",
@@ -98,6 +98,10 @@ def lib():
         L.inout_classify_prepared.argtypes = [p, p, p, p, i64, p, u32, p]
         L.inout_release.argtypes = [p]
         L.inout_release.restype = None
+        L.inout_classify_static.argtypes = [C.POINTER(Surface), p, p, p, i64, p, p]
+        L.inout_classify_static.restype = C.c_int
+        L.inout_static_last_error.argtypes = []
+        L.inout_static_last_error.restype = C.c_char_p
         L.inout_reserve.argtypes = [p, i64]
         L.inout_reserve.restype = C.c_int
         L.vms_stats.argtypes = [p, p]
@@ -360,6 +364,16 @@ def inout_classify(surf, px, py, pz, labels, mode=VMS_INOUT_EXACT, mlp=None, str
     rc = lib().inout_classify(C.byref(s), _ptr(px), _ptr(py), _ptr(pz), px.numel(), _ptr(labels),
                               mode, C.c_void_p(mlp) if mlp else None, _stream(stream))
     _check(rc, None)
+
+
+def inout_classify_static(surf, px, py, pz, labels, stream=None):
+    """Exact labels with the surface staged in the library's static device
+    array (no device allocation)."""
+    s = make_surface(surf.verts, surf.tris)
+    rc = lib().inout_classify_static(C.byref(s), _ptr(px), _ptr(py), _ptr(pz), px.numel(), _ptr(labels),
+                                     _stream(stream))
+    if rc != VMS_OK:
+        raise VmsError(rc, lib().inout_static_last_error().decode())
 
 
 def inout_prepare(surf, stream=None):
