@@ -87,9 +87,14 @@ enum {
                                   level, double [n_subgp][3] xyz; canonical order (elements
                                   ascending, depth-first, children and Gauss points x fastest) */
     VMS_EXPORT_MASTERS = 7,    /* int32 [n_oct][8] master nodes per element slot (-1 unused) */
-    VMS_EXPORT_SURFGP = 8      /* surface points of the weak boundary terms, n = stats[6]:
+    VMS_EXPORT_SURFGP = 8,     /* surface points of the weak boundary terms, n = stats[6]:
                                   int64 [n] element, double [n][3] reference coordinates,
                                   double [n] weight, double [n][3] unit normal of the fluid */
+    VMS_EXPORT_NODE_ROW_PTR = 9, /* int64 [n_nodes + 1]: the CSR at node level (4x4 blocks),
+                                    block-row offsets; nnz / 16 blocks in all */
+    VMS_EXPORT_NODE_COL = 10     /* int32 [nnz / 16]: block columns (column nodes), ascending
+                                    within each block row; dof row 4 n + i holds the columns
+                                    4 m + j (j = 0..3) of the block columns m of node row n */
 };
 
 /* Linear octree leaves, HOST pointers (copied at vms_create). A leaf at level L
@@ -123,7 +128,13 @@ typedef struct {
 typedef struct {
     double rho, mu, dt, theta, c_t, c_i;
     int32_t quad_depth;
-    uint32_t precision; /* VMS_FP64 | VMS_MIXED_BF16 | VMS_MIXED_FP16 */
+    uint32_t precision;      /* VMS_FP64 | VMS_MIXED_BF16 | VMS_MIXED_FP16 */
+    uint32_t inout_mode;     /* in-out test of the sub-cell quadrature points on relabel:
+                                VMS_INOUT_EXACT, or VMS_INOUT_LEARNED (the network given by
+                                vms_set_inout decides where |prediction| >= margin) */
+    int32_t learned_min_bt;  /* LEARNED: the network is used on INTERCEPTED elements with at
+                                least this many background triangles, the exact test alone
+                                on the others */
 } vms_params;
 
 /* Nodal fields, DEVICE pointers, SoA over independent nodes (length n_nodes):
@@ -390,29 +401,35 @@ int vms_sdf_sample(inout_handle *h, const double *px, const double *py, const do
                    double trunc, double *sdf);
 
 /* Batched assembly of many contexts (independent octrees, one precision) in
- * one persistent launch: workgroups take units of work (runs of `tile` OUT
- * elements, or sub-cell work items) from a device counter until the queue is
- * empty. fields/vals/resid are arrays with one entry per context (resid
+ * one persistent launch: workgroups take units of work from a device counter
+ * until the queue is empty. A unit is a run of OUT elements or of sub-cell
+ * work items of one tree, cut at about `tile` element weights of eq. (Wpart)
+ * (§"Estimation of Weight for the INTERCEPTED Elements": an OUT element weighs
+ * 1, an INTERCEPTED element's work item its points over 8), and the queue
+ * holds the units heaviest first, so that it ends on light units (the load
+ * balance that the paper's weighted partition gives across processes).
+ * vms_batch_set_order(b, 0) selects the fixed order instead (every sub-cell
+ * item a unit of its own, all of them first, then runs of `tile` OUT
+ * elements). After the persistent launch one batched gather sums every
+ * tree's CSR values (identity rows of inactive nodes included) and one its
+ * residual. fields/vals/resid are arrays with one entry per context (resid
  * entries nullable), with the meaning of vms_assemble (labels are not
  * recomputed). vms_batch_autotune times every (tile, workgroups per CU)
  * candidate on the given buffers and keeps the fastest. With
- * vms_batch_use_graph(b, 1) the launch sequence (zeroing kernels and the
- * persistent assembly) is captured into a HIP graph at the first call and
+ * vms_batch_use_graph(b, 1) the launch sequence (counter reset, persistent
+ * assembly, gathers) is captured into a HIP graph at the first call and
  * replayed while the buffer pointers stay the same. Every call re-checks its
  * contexts: one whose record buffers were rebuilt since (weak boundary terms
  * switched on and off again) is re-read and the captured graph dropped; one
  * with weak boundary terms on makes the call return VMS_EUNSUPPORTED before
- * any launch. The queue puts the sub-cell
- * work first: INTERCEPTED elements carry more quadrature points and in-out
- * work, the load imbalance that the paper's weighted partition (eq. Wpart,
- * section on dynamic load balancing) addresses across processes.
- * vms_batch_last_timing writes HOST ms[3] (an empty interval before the
- * kernels, persistent assembly kernel, summations of the records into CSR
- * values and residuals) of the last eager (not graph-replayed)
- * vms_batch_assemble, synchronising on it; VMS_EINVAL if there was none. */
+ * any launch. vms_batch_last_timing writes HOST ms[3] (an empty interval
+ * before the kernels, persistent assembly kernel, gathers) of the last eager
+ * (not graph-replayed) vms_batch_assemble, synchronising on it; VMS_EINVAL if
+ * there was none. */
 typedef struct vms_batch vms_batch;
 int vms_batch_create(vms_batch **out, vms_ctx *const *ctxs, int n, void *stream);
 int vms_batch_set_config(vms_batch *b, int tile, int groups_per_cu);
+int vms_batch_set_order(vms_batch *b, int by_weight);
 int vms_batch_get_config(vms_batch *b, int *tile, int *groups_per_cu, int64_t *n_units);
 int vms_batch_use_graph(vms_batch *b, int on);
 int vms_batch_assemble(vms_batch *b, const vms_fields *fields, void *const *vals,
@@ -421,6 +438,22 @@ int vms_batch_autotune(vms_batch *b, const vms_fields *fields, void *const *vals
                        double *const *resid, float *ms);
 int vms_batch_last_timing(vms_batch *b, float *ms);
 void vms_batch_destroy(vms_batch *b);
+
+/* In-out test of the sub-cell quadrature on relabel (§"Adaptive Quadrature";
+ * Alg. 5's question answered with a learned filter in front of the exact
+ * test): mode VMS_INOUT_EXACT, or VMS_INOUT_LEARNED with mlp a trained and
+ * calibrated vms_mlp handle (kept by reference: it must outlive its use by
+ * the context). On INTERCEPTED elements with at least min_bt background
+ * triangles each candidate point goes through the network first; a point
+ * whose |prediction| reaches its margin takes the network's sign, every other
+ * point the exact test. Labels equal the exact ones wherever the margin
+ * exceeds the network's error; a relabel whose kept-point count of an
+ * element differs from the set-up's exact count reports VMS_EOVERFLOW at the
+ * next vms_sizes. Errors: VMS_EINVAL. vms_relabel_stats writes HOST out[2]:
+ * candidate points of the sub-cell quadrature (set-up pass) and those
+ * labelled by the exact test in the last relabel (synchronises). */
+int vms_set_inout(vms_ctx *ctx, uint32_t mode, const vms_mlp *mlp, int32_t min_bt);
+int vms_relabel_stats(vms_ctx *ctx, int64_t *out);
 
 /* Counters of a context (HOST out[7]): OUT elements, INTERCEPTED elements,
  * points labelled by the last sub-cell quadrature, degenerate directions

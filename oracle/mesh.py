@@ -35,16 +35,12 @@ class Mesh:
     pass
 
 
-def derive_mesh(ax, ay, az, level, max_level, active=None):
-    """Node table, hanging constraints, per-element masters and CSR pattern.
-
-    active: optional bool mask of elements that contribute (non-IN); the
-    pattern couples masters of active elements only.
-    """
+def _vertices_and_hanging(ax, ay, az, level, max_level):
+    """Corner keys of every leaf, the unique vertex keys, and the hanging
+    vertices (key, up to 4 master keys, weights)."""
     M = int(max_level)
     ax = np.asarray(ax, np.int64); ay = np.asarray(ay, np.int64); az = np.asarray(az, np.int64)
     lev = np.asarray(level, np.int64)
-    E = ax.shape[0]
     side = np.int64(1) << (M - lev)
     anc = np.stack([ax, ay, az], 1)
     corners = anc[:, None, :] + CORNER_OFF[None, :, :] * side[:, None, None]   # (E, 8, 3)
@@ -83,6 +79,24 @@ def derive_mesh(ax, ay, az, level, max_level, active=None):
     mk = hang_masters[hang_w > 0]
     if np.isin(mk, hk).any():
         raise ValueError("chained hanging constraint: tree is not 2:1 balanced")
+    return ckey, all_keys, inv, hk, hang_masters, hang_w
+
+
+def independent_node_keys(ax, ay, az, level, max_level):
+    """Morton keys of the independent nodes of a tree, ascending: position k
+    of a key is that node's number (the numbering of the CSR rows)."""
+    _, all_keys, _, hk, _, _ = _vertices_and_hanging(ax, ay, az, level, max_level)
+    return all_keys[~np.isin(all_keys, hk)]
+
+
+def derive_mesh(ax, ay, az, level, max_level, active=None):
+    """Node table, hanging constraints, per-element masters and CSR pattern.
+
+    active: optional bool mask of elements that contribute (non-IN); the
+    pattern couples masters of active elements only.
+    """
+    E = np.asarray(ax).shape[0]
+    ckey, all_keys, inv, hk, hang_masters, hang_w = _vertices_and_hanging(ax, ay, az, level, max_level)
 
     # --- independent nodes, Morton order ---
     is_hang = np.isin(all_keys, hk)
@@ -176,22 +190,35 @@ def derive_mesh(ax, ay, az, level, max_level, active=None):
     return ms
 
 
+def _spread_table():
+    """T[v] for 7-bit v: bit b of v moved to bit 3b, written bit by bit."""
+    t = np.zeros(128, np.uint64)
+    for v in range(128):
+        k = 0
+        for b in range(7):
+            k |= ((v >> b) & 1) << (3 * b)
+        t[v] = k
+    return t
+
+
+_SPREAD = _spread_table()
+
+
 def morton_key(x, y, z):
     """Morton key of integer coordinates, x in the lowest bit.
 
-    Written bit by bit (bit b of x goes to key bit 3b, of y to 3b+1, of z to
-    3b+2): the node-numbering convention of the CSR, independent of any other
-    implementation of the interleave.
+    Bit b of x goes to key bit 3b, of y to 3b+1, of z to 3b+2 (the
+    node-numbering convention of the CSR), seven bits at a time through a
+    table that is itself written bit by bit.
     """
     x = np.asarray(x, np.int64); y = np.asarray(y, np.int64); z = np.asarray(z, np.int64)
     if x.size and (min(x.min(), y.min(), z.min()) < 0 or
                    max(x.max(), y.max(), z.max()) >= (1 << MORTON_BITS)):
         raise ValueError("coordinate outside the 21-bit Morton range")
     key = np.zeros(np.broadcast(x, y, z).shape, np.uint64)
-    for b in range(MORTON_BITS):
+    for c in range(MORTON_BITS // 7):
         for axis, v in enumerate((x, y, z)):
-            bit = ((v >> b) & 1).astype(np.uint64)
-            key |= bit << np.uint64(3 * b + axis)
+            key |= _SPREAD[(v >> (7 * c)) & 127] << np.uint64(21 * c + axis)
     return key
 
 

@@ -1001,3 +1001,220 @@ void or_element_frozen(const or_params *P, double h, int npt, const double *xi, 
         }
     free(tau);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Triquadratic (Q2, 27-node) elements on a uniform octree                   */
+/*                                                                           */
+/* The paper's matrix-assembly comparison (Table of matrix assembly times)   */
+/* runs linear and quadratic bases on a uniform mesh; App. A tabulates the   */
+/* basis values and gradients at the (bf+1)^d Gauss points. Node a of an     */
+/* element is (a % 3, a / 3 % 3, a / 9) on the reference grid {-1, 0, 1}^3   */
+/* (x fastest); the 1D basis on [-1, 1] is the Lagrange quadratic of the     */
+/* nodes -1, 0, 1. The integrand is the same VMS residual as above (second   */
+/* derivatives dropped from the strong residual, G = (2/h)^2 I), integrated  */
+/* with the 3-point Gauss rule per axis; the Jacobian by complex step with   */
+/* the stabilisation parameters frozen. No hanging nodes (all leaves on one  */
+/* level), so nodes are the element nodes themselves.                        */
+/* ------------------------------------------------------------------------ */
+
+#define Q2_NB 27
+
+static void q2_basis_1d(double x, double f[3], double g[3]) {
+    f[0] = 0.5 * x * (x - 1.0);
+    f[1] = 1.0 - x * x;
+    f[2] = 0.5 * x * (x + 1.0);
+    g[0] = x - 0.5;
+    g[1] = -2.0 * x;
+    g[2] = x + 0.5;
+}
+
+static void q2_basis(const double xi[3], double h, double N[Q2_NB], double dN[Q2_NB][3]) {
+    double f[3][3], g[3][3];
+    for (int k = 0; k < 3; ++k) q2_basis_1d(xi[k], f[k], g[k]);
+    const double s = 2.0 / h;
+    for (int a = 0; a < Q2_NB; ++a) {
+        const int i = a % 3, j = (a / 3) % 3, l = a / 9;
+        N[a] = f[0][i] * f[1][j] * f[2][l];
+        dN[a][0] = s * g[0][i] * f[1][j] * f[2][l];
+        dN[a][1] = s * f[0][i] * g[1][j] * f[2][l];
+        dN[a][2] = s * f[0][i] * f[1][j] * g[2][l];
+    }
+}
+
+/* the same integrand as element_residual, over the 27 nodes */
+static void q2_residual(const or_params *P, double h, int npt, const double *xi, const double *w,
+                        const taus *tau, cplx Uv[Q2_NB][4], const double U0v[Q2_NB][3],
+                        cplx Rv[Q2_NB][4]) {
+    const double rho = P->rho, mu = P->mu, dt = P->dt, th = P->theta;
+    const int m = P->term_mask;
+    for (int a = 0; a < Q2_NB; ++a)
+        for (int c = 0; c < 4; ++c) Rv[a][c] = 0;
+    for (int q = 0; q < npt; ++q) {
+        double N[Q2_NB], dN[Q2_NB][3];
+        q2_basis(xi + 3 * q, h, N, dN);
+        const double W = w[q];
+        cplx ut[3] = {0, 0, 0}, gu[3][3] = {{0}}, at[3] = {0, 0, 0}, p = 0, gp[3] = {0, 0, 0};
+        for (int a = 0; a < Q2_NB; ++a) {
+            for (int i = 0; i < 3; ++i) {
+                cplx uth = th * Uv[a][i] + (1.0 - th) * U0v[a][i];
+                ut[i] += N[a] * uth;
+                at[i] += N[a] * (Uv[a][i] - U0v[a][i]) / dt;
+                for (int j = 0; j < 3; ++j) gu[i][j] += dN[a][j] * uth;
+            }
+            p += N[a] * Uv[a][3];
+            for (int j = 0; j < 3; ++j) gp[j] += dN[a][j] * Uv[a][3];
+        }
+        cplx rM[3], rC = gu[0][0] + gu[1][1] + gu[2][2];
+        for (int i = 0; i < 3; ++i) {
+            cplx conv = ut[0] * gu[i][0] + ut[1] * gu[i][1] + ut[2] * gu[i][2];
+            rM[i] = rho * (at[i] + conv) + gp[i];
+        }
+        cplx up[3];
+        for (int i = 0; i < 3; ++i) up[i] = -tau[q].tauM * rM[i];
+        cplx pp = -rho * tau[q].tauC * rC;
+        const double tb = tau[q].taubar;
+        for (int a = 0; a < Q2_NB; ++a) {
+            cplx u_dot_gradNa = ut[0] * dN[a][0] + ut[1] * dN[a][1] + ut[2] * dN[a][2];
+            cplx up_dot_gradNa = up[0] * dN[a][0] + up[1] * dN[a][1] + up[2] * dN[a][2];
+            for (int i = 0; i < 3; ++i) {
+                cplx r = 0;
+                cplx conv_i = ut[0] * gu[i][0] + ut[1] * gu[i][1] + ut[2] * gu[i][2];
+                cplx upgu_i = up[0] * gu[i][0] + up[1] * gu[i][1] + up[2] * gu[i][2];
+                if (m & (1 << 0)) r += N[a] * rho * at[i];
+                if (m & (1 << 1)) r += N[a] * rho * conv_i;
+                if (m & (1 << 2)) {
+                    cplx v = 0;
+                    for (int j = 0; j < 3; ++j) v += dN[a][j] * (gu[i][j] + gu[j][i]);
+                    r += mu * v;
+                }
+                if (m & (1 << 3)) r += -p * dN[a][i];
+                if (m & (1 << 5)) r += -u_dot_gradNa * up[i];
+                if (m & (1 << 6)) r += -pp * dN[a][i];
+                if (m & (1 << 7)) r += N[a] * upgu_i;
+                if (m & (1 << 8)) r += -(1.0 / rho) * up_dot_gradNa * up[i];
+                if (m & (1 << 9)) r += up_dot_gradNa * tb * upgu_i;
+                Rv[a][i] += W * r;
+            }
+            cplx rc = 0;
+            if (m & (1 << 4)) rc += N[a] * rC;
+            if (m & (1 << 5)) rc += -(1.0 / rho) * up_dot_gradNa;
+            Rv[a][3] += W * rc;
+        }
+    }
+}
+
+static void q2_taus(const or_params *P, double h, int npt, const double *xi,
+                    const double Uv[Q2_NB][4], const double U0v[Q2_NB][3], taus *tau) {
+    const double rho = P->rho, dt = P->dt, th = P->theta, nu = P->mu / P->rho;
+    const double g = 4.0 / (h * h);
+    for (int q = 0; q < npt; ++q) {
+        double N[Q2_NB], dN[Q2_NB][3];
+        q2_basis(xi + 3 * q, h, N, dN);
+        double ut[3] = {0, 0, 0}, gu[3][3] = {{0}}, at[3] = {0, 0, 0}, gp[3] = {0, 0, 0};
+        for (int a = 0; a < Q2_NB; ++a) {
+            for (int i = 0; i < 3; ++i) {
+                double uth = th * Uv[a][i] + (1.0 - th) * U0v[a][i];
+                ut[i] += N[a] * uth;
+                at[i] += N[a] * (Uv[a][i] - U0v[a][i]) / dt;
+                for (int j = 0; j < 3; ++j) gu[i][j] += dN[a][j] * uth;
+            }
+            for (int j = 0; j < 3; ++j) gp[j] += dN[a][j] * Uv[a][3];
+        }
+        double uGu = g * (ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
+        double GG = 3.0 * g * g, trG = 3.0 * g;
+        double tauM = 1.0 / sqrt(P->c_t / (dt * dt) + uGu + P->c_i * nu * nu * GG);
+        double tauC = 1.0 / (tauM * trG);
+        double up[3];
+        for (int i = 0; i < 3; ++i) {
+            double conv = ut[0] * gu[i][0] + ut[1] * gu[i][1] + ut[2] * gu[i][2];
+            up[i] = -tauM * (rho * (at[i] + conv) + gp[i]);
+        }
+        double upGup = g * (up[0] * up[0] + up[1] * up[1] + up[2] * up[2]);
+        tau[q].tauM = tauM;
+        tau[q].tauC = tauC;
+        tau[q].taubar = (upGup > 0.0) ? 1.0 / sqrt(upGup) : 0.0;
+    }
+}
+
+/* One Q2 element: node values U (27 x 4), U0 (27 x 3); residual R (108) and
+ * Jacobian J (108 x 108, row-major, dof 4 a + c) at the given points. */
+void or_q2_element(const or_params *P, double h, int npt, const double *xi, const double *w,
+                   const double *U, const double *U0, double *R, double *J) {
+    double Uv[Q2_NB][4], U0v[Q2_NB][3];
+    for (int a = 0; a < Q2_NB; ++a) {
+        for (int c = 0; c < 4; ++c) Uv[a][c] = U[4 * a + c];
+        for (int c = 0; c < 3; ++c) U0v[a][c] = U0[3 * a + c];
+    }
+    taus *tau = (taus *)malloc(sizeof(taus) * (npt > 0 ? npt : 1));
+    q2_taus(P, h, npt, xi, (const double(*)[4])Uv, (const double(*)[3])U0v, tau);
+    const double eps = 1e-30;
+    cplx Ucv[Q2_NB][4], Rv[Q2_NB][4];
+    for (int col = -1; col < 4 * Q2_NB; ++col) {
+        for (int a = 0; a < Q2_NB; ++a)
+            for (int c = 0; c < 4; ++c) Ucv[a][c] = Uv[a][c] + ((4 * a + c) == col ? I * eps : 0.0);
+        q2_residual(P, h, npt, xi, w, tau, Ucv, (const double(*)[3])U0v, Rv);
+        for (int a = 0; a < Q2_NB; ++a)
+            for (int c = 0; c < 4; ++c) {
+                if (col < 0) { if (R) R[4 * a + c] = creal(Rv[a][c]); }
+                else if (J) J[(4 * a + c) * (4 * Q2_NB) + col] = cimag(Rv[a][c]) / eps;
+            }
+    }
+    free(tau);
+}
+
+/* The real residual with the stabilisation parameters frozen at the state
+ * Ub (for central differences of the frozen-tau Jacobian in tests). */
+void or_q2_element_frozen(const or_params *P, double h, int npt, const double *xi, const double *w,
+                          const double *Ub, const double *U, const double *U0, double *R) {
+    double Bv[Q2_NB][4], U0v[Q2_NB][3];
+    cplx Ucv[Q2_NB][4], Rv[Q2_NB][4];
+    for (int a = 0; a < Q2_NB; ++a) {
+        for (int c = 0; c < 4; ++c) { Bv[a][c] = Ub[4 * a + c]; Ucv[a][c] = U[4 * a + c]; }
+        for (int c = 0; c < 3; ++c) U0v[a][c] = U0[3 * a + c];
+    }
+    taus *tau = (taus *)malloc(sizeof(taus) * (npt > 0 ? npt : 1));
+    q2_taus(P, h, npt, xi, (const double(*)[4])Bv, (const double(*)[3])U0v, tau);
+    q2_residual(P, h, npt, xi, w, tau, Ucv, (const double(*)[3])U0v, Rv);
+    for (int a = 0; a < Q2_NB; ++a)
+        for (int c = 0; c < 4; ++c) R[4 * a + c] = creal(Rv[a][c]);
+    free(tau);
+}
+
+/* Global Q2 assembly: element e's nodes el_node[27 e ..] (global ids), size
+ * el_h[e], the same npt points (xi, w scaled by the caller) in every element.
+ * Outputs accumulated (+=) into the CSR of the node pairs. Returns 0 or
+ * -(e+1) if an entry is missing from the pattern. */
+int64_t or_q2_assemble(const or_params *P, int64_t n_el, const int32_t *el_node, const double *el_h,
+                       int npt, const double *xi, const double *w_ref, const double *ux,
+                       const double *uy, const double *uz, const double *pr, const double *ux0,
+                       const double *uy0, const double *uz0, const int64_t *row_ptr,
+                       const int32_t *col, double *vals, double *resid) {
+    double U[4 * Q2_NB], U0[3 * Q2_NB], R[4 * Q2_NB];
+    double *J = (double *)malloc(sizeof(double) * 16 * Q2_NB * Q2_NB);
+    double *w = (double *)malloc(sizeof(double) * (npt > 0 ? npt : 1));
+    for (int64_t e = 0; e < n_el; ++e) {
+        const int32_t *nd = el_node + Q2_NB * e;
+        const double d3 = (el_h[e] / 2.0) * (el_h[e] / 2.0) * (el_h[e] / 2.0);
+        for (int q = 0; q < npt; ++q) w[q] = w_ref[q] * d3;
+        for (int a = 0; a < Q2_NB; ++a) {
+            const int32_t n = nd[a];
+            U[4 * a] = ux[n]; U[4 * a + 1] = uy[n]; U[4 * a + 2] = uz[n]; U[4 * a + 3] = pr[n];
+            U0[3 * a] = ux0[n]; U0[3 * a + 1] = uy0[n]; U0[3 * a + 2] = uz0[n];
+        }
+        or_q2_element(P, el_h[e], npt, xi, w, U, U0, R, vals ? J : NULL);
+        for (int r = 0; r < 4 * Q2_NB; ++r) {
+            const int64_t grow = 4 * (int64_t)nd[r / 4] + (r % 4);
+            if (resid) resid[grow] += R[r];
+            if (!vals) continue;
+            for (int c = 0; c < 4 * Q2_NB; ++c) {
+                const int32_t gcol = 4 * nd[c / 4] + (c % 4);
+                const int64_t k = csr_find(row_ptr, col, grow, gcol);
+                if (k < 0) { free(J); free(w); return -(e + 1); }
+                vals[k] += J[r * 4 * Q2_NB + c];
+            }
+        }
+    }
+    free(J);
+    free(w);
+    return 0;
+}

@@ -244,6 +244,12 @@ struct vms_ctx {
     int32_t *d_sq_el = nullptr, *d_sq_ax = nullptr, *d_sq_ay = nullptr, *d_sq_az = nullptr;
     uint8_t *d_sq_level = nullptr, *d_sq_clab = nullptr;
     int64_t *d_bt_off = nullptr;
+    std::vector<int32_t> sq_nbt;  // background triangles of each INTERCEPTED element (host)
+    // learned mode: the INTERCEPTED elements (list positions) at or above the
+    // threshold on the background-triangle count, and the others
+    int32_t split_bt = -1;
+    int64_t n_sq_net = 0, n_sq_exact = 0;
+    int32_t *d_sq_net = nullptr, *d_sq_exact = nullptr;
     int32_t *d_bt_ids = nullptr;
     int32_t *d_sq_cnt = nullptr;
     int64_t *d_sq_off = nullptr;
@@ -252,6 +258,7 @@ struct vms_ctx {
     // assembly work items over the sub-cell points: at most ITEM_PTS points each
     int64_t n_sub_items = 0;
     std::vector<int32_t> sub_item_el;  // element of each item (host copy)
+    std::vector<int32_t> sub_item_cnt; // points of each item (host copy)
     int32_t *d_sub_el = nullptr, *d_sub_cnt = nullptr;
     int64_t *d_sub_off = nullptr;
     std::vector<int32_t> std_el;  // host copy of the OUT-element list
@@ -266,9 +273,7 @@ struct vms_ctx {
     int32_t *d_surf_el = nullptr;
     int64_t *d_surf_off = nullptr;
     double *d_surf_xi = nullptr, *d_surf_w = nullptr, *d_surf_n = nullptr, *d_surf_tau = nullptr;
-    // identity rows of inactive nodes: their CSR places and the node ids
-    int64_t n_ones = 0;
-    int64_t *d_ones = nullptr;
+    // inactive nodes (no non-IN element): identity rows
     int64_t n_inact = 0;
     int32_t *d_inact = nullptr;
     // node-level CSR (block rows, block columns) for the product with the matrix
@@ -300,7 +305,11 @@ struct vms_ctx {
     // bumped whenever the record buffers and gather lists are rebuilt, so that
     // a batch holding this context re-reads them (and drops a captured graph)
     uint64_t gen = 0;
-    unsigned long long *d_counters = nullptr;  // 0: labelled points, 1: degenerate directions
+    // 0: labelled points (set-up pass), 1: degenerate directions, 2: points
+    // labelled by the exact test in the last relabel
+    unsigned long long *d_counters = nullptr;
+    // learned in-out filter of the sub-cell quadrature (prm.inout_mode)
+    const vmsm::MlpHandle *mlp = nullptr;
     unsigned int *d_flag = nullptr;            // device-side overflow flag
     double *d_norm = nullptr;
     // optional per-stage timing with events on the context stream
@@ -341,6 +350,14 @@ bool params_ok(const vms_params *p, std::string &why) {
     if (p->rho <= 0 || p->dt <= 0 || p->mu < 0 || p->c_t <= 0 || p->c_i < 0 || p->theta < 0 ||
         p->theta > 1) {
         why = "parameter out of range (rho > 0, dt > 0, mu >= 0, c_t > 0, c_i >= 0, 0 <= theta <= 1)";
+        return false;
+    }
+    if (p->inout_mode != VMS_INOUT_EXACT && p->inout_mode != VMS_INOUT_LEARNED) {
+        why = "unknown in-out mode";
+        return false;
+    }
+    if (p->learned_min_bt < 0) {
+        why = "learned_min_bt must be >= 0";
         return false;
     }
     return true;
@@ -466,7 +483,40 @@ int run_subquad(vms_ctx *c, bool first) {
     }
     a.off = c->d_sq_off;
     a.entries = c->d_entries;
-    vmsk::launch_subquad(c->stream, c->surf.S, g, a, 1);
+    a.nexact = c->d_counters + 2;
+    vmsk::launch_zero_u64(c->stream, a.nexact);
+    // the set-up pass is exact; relabels use the learned filter in LEARNED
+    // mode on the elements at or above the threshold (their own launch), the
+    // exact kernel on the others
+    if (!first && c->prm.inout_mode == VMS_INOUT_LEARNED) {
+        if (!c->mlp) return fail(c, VMS_EINVAL, "learned in-out mode needs a network (vms_set_inout)");
+        if (c->split_bt != c->prm.learned_min_bt) {
+            std::vector<int32_t> net, ex;
+            for (int64_t i = 0; i < c->n_sq; ++i)
+                (c->sq_nbt[i] >= c->prm.learned_min_bt ? net : ex).push_back((int32_t)i);
+            c->buf.free(c->d_sq_net);
+            c->buf.free(c->d_sq_exact);
+            c->d_sq_net = c->d_sq_exact = nullptr;
+            if ((net.size() && upload(c, &c->d_sq_net, net)) || (ex.size() && upload(c, &c->d_sq_exact, ex)))
+                return fail(c, VMS_ENOMEM, "device allocation failed (element lists)");
+            c->n_sq_net = (int64_t)net.size();
+            c->n_sq_exact = (int64_t)ex.size();
+            c->split_bt = c->prm.learned_min_bt;
+        }
+        vmsk::SubqArgs ae = a, an = a;
+        ae.order = c->d_sq_exact;
+        ae.n_order = c->n_sq_exact;
+        an.order = c->d_sq_net;
+        an.n_order = c->n_sq_net;
+        an.learned.net = vmsm::mlp_net(c->mlp);
+        an.learned.grid = vmsm::mlp_grid(c->mlp);
+        an.learned.margin = vmsm::mlp_margin(c->mlp);
+        an.learned.min_bt = 0;
+        if (ae.n_order) vmsk::launch_subquad(c->stream, c->surf.S, g, ae, 1);
+        if (an.n_order) vmsk::launch_subquad(c->stream, c->surf.S, g, an, 1);
+    } else {
+        vmsk::launch_subquad(c->stream, c->surf.S, g, a, 1);
+    }
     HIPCHK(c, hipGetLastError());
     return VMS_OK;
 }
@@ -553,6 +603,9 @@ static int build_gather(vms_ctx *c, const std::vector<int32_t> &stdl) {
                 vbase[b] = 16 * b0 + 4 * (b - b0);
                 vstride[b] = (int32_t)(4 * deg);
             }
+            // the diagonal block of a node of no non-IN element (its only
+            // block, with no records): the gather writes an identity block
+            if (!m.node_active[n]) vstride[b0 + m.diag_pos[n]] = -(int32_t)(4 * deg);
         }
     });
     // residual lists: node n receives slot s of every record whose element has
@@ -795,17 +848,15 @@ static void gather_resid(vms_ctx *c, hipStream_t st, double *out) {
     vmsk::launch_res_gather(st, c->d_rrec, c->d_roff, c->d_rlist, c->mesh.n_nodes, out);
 }
 
-// CSR values = sums of the element-matrix records, then identity blocks
+// CSR values = sums of the element-matrix records; the identity blocks of
+// inactive nodes are written by the same gather
 static void gather_csr(vms_ctx *c, hipStream_t st, void *vals) {
-    if (c->prm.precision == VMS_FP64) {
+    if (c->prm.precision == VMS_FP64)
         vmsk::launch_gather_f64(st, (const double *)c->d_em, c->d_cb_off, c->d_contrib, c->d_vbase,
                                 c->d_vstride, c->n_blocks, (double *)vals);
-        vmsk::launch_set_ones_f64(st, (double *)vals, c->d_ones, c->n_ones);
-    } else {
+    else
         vmsk::launch_gather_f32(st, (const float *)c->d_em, c->d_cb_off, c->d_contrib, c->d_vbase,
                                 c->d_vstride, c->n_blocks, (float *)vals);
-        vmsk::launch_set_ones_f32(st, (float *)vals, c->d_ones, c->n_ones);
-    }
 }
 
 extern "C" {
@@ -889,7 +940,7 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
     stage("nodes and constraints");
     if (rc) { c->err = err; return bail(rc == -2 ? VMS_EMESH : VMS_EINVAL); }
     vms::MeshHost &m = c->mesh;
-    if (c->buf.alloc(&c->d_counters, 2) || c->buf.alloc(&c->d_norm, 1) ||
+    if (c->buf.alloc(&c->d_counters, 4) || c->buf.alloc(&c->d_norm, 1) ||
         c->buf.alloc(&c->d_flag, 1) || hipMemsetAsync(c->d_flag, 0, 4, c->stream) != hipSuccess) {
         c->err = "device allocation failed";
         return bail(VMS_ENOMEM);
@@ -925,7 +976,7 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
         if (hipMemcpyAsync(dix, ix.data(), NV * 4, hipMemcpyHostToDevice, c->stream) ||
             hipMemcpyAsync(diy, iy.data(), NV * 4, hipMemcpyHostToDevice, c->stream) ||
             hipMemcpyAsync(diz, iz.data(), NV * 4, hipMemcpyHostToDevice, c->stream) ||
-            hipMemsetAsync(c->d_counters, 0, 16, c->stream)) {
+            hipMemsetAsync(c->d_counters, 0, 32, c->stream)) {
             c->err = "device copy failed (vertex labels)";
             return bail(VMS_EHIP);
         }
@@ -968,6 +1019,8 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
         std::vector<int64_t> bt_off;
         std::vector<int32_t> bt_ids;
         gather_bt(c, bt_off, bt_ids);
+        c->sq_nbt.resize(c->n_sq);
+        for (int64_t i = 0; i < c->n_sq; ++i) c->sq_nbt[i] = (int32_t)(bt_off[i + 1] - bt_off[i]);
         std::vector<int32_t> sax(c->n_sq), say(c->n_sq), saz(c->n_sq);
         std::vector<uint8_t> slev(c->n_sq), sclab(8 * c->n_sq);
         for (int64_t i = 0; i < c->n_sq; ++i) {
@@ -986,7 +1039,7 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
         if (rc) return bail(rc);
         stage("sub-cell quadrature");
         // split every element's point list into work items of at most ITEM_PTS
-        // points (partial element matrices are summed by the atomic scatter)
+        // points (each item writes its own record; the gathers sum them)
         const int ITEM_PTS = VMS_ITEM_PTS;
         std::vector<int32_t> iel, icnt;
         std::vector<int64_t> ioff;
@@ -998,6 +1051,7 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
             }
         c->n_sub_items = (int64_t)iel.size();
         c->sub_item_el = iel;
+        c->sub_item_cnt = icnt;
         if (upload(c, &c->d_sub_el, iel) || upload(c, &c->d_sub_off, ioff) ||
             upload(c, &c->d_sub_cnt, icnt))
             return bail(VMS_ENOMEM);
@@ -1015,18 +1069,13 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
     for (int64_t e = 0; e < E; ++e)
         if (c->markers[e] == 0) stdl.push_back((int32_t)e);
     c->n_std = (int64_t)stdl.size();
-    std::vector<int64_t> ones;
     std::vector<int32_t> inact;
-    for (int64_t n = 0; n < m.n_nodes; ++n) {
-        if (m.node_active[n]) continue;
-        inact.push_back((int32_t)n);
-        for (int cc = 0; cc < 4; ++cc) ones.push_back(m.row_ptr[4 * n + cc] + 4 * (int64_t)m.diag_pos[n] + cc);
-    }
-    c->n_ones = (int64_t)ones.size();
+    for (int64_t n = 0; n < m.n_nodes; ++n)
+        if (!m.node_active[n]) inact.push_back((int32_t)n);
     c->n_inact = (int64_t)inact.size();
     if (upload(c, &c->d_masters, m.masters) || upload(c, &c->d_ccode, m.ccode) ||
         upload(c, &c->d_hang, m.has_hang) || upload(c, &c->d_level, c->level) ||
-        upload(c, &c->d_std, stdl) || upload(c, &c->d_ones, ones) ||
+        upload(c, &c->d_std, stdl) ||
         upload(c, &c->d_inact, inact) || upload(c, &c->d_nrow_ptr, m.nrow_ptr) ||
         upload(c, &c->d_ncol, m.ncol))
         return bail(VMS_ENOMEM);
@@ -1075,6 +1124,12 @@ int vms_export(vms_ctx *c, uint32_t what, void *dst) {
             return VMS_OK;
         case VMS_EXPORT_COL_IDX:
             vms::fill_col_idx(m, (int32_t *)dst);
+            return VMS_OK;
+        case VMS_EXPORT_NODE_ROW_PTR:
+            std::memcpy(dst, m.nrow_ptr.data(), m.nrow_ptr.size() * 8);
+            return VMS_OK;
+        case VMS_EXPORT_NODE_COL:
+            std::memcpy(dst, m.ncol.data(), m.ncol.size() * 4);
             return VMS_OK;
         case VMS_EXPORT_MARKERS:
             std::memcpy(dst, c->markers.data(), E);
@@ -1574,6 +1629,29 @@ int vms_element_weights(vms_ctx *c, double ts_over_tv, double *w) {
     return VMS_OK;
 }
 
+int vms_set_inout(vms_ctx *c, uint32_t mode, const vms_mlp *mlp, int32_t min_bt) {
+    if (!c) return fail(nullptr, VMS_EINVAL, "null context");
+    if (mode != VMS_INOUT_EXACT && mode != VMS_INOUT_LEARNED) return fail(c, VMS_EINVAL, "unknown in-out mode");
+    if (mode == VMS_INOUT_LEARNED && !mlp) return fail(c, VMS_EINVAL, "learned in-out mode needs a network");
+    if (min_bt < 0) return fail(c, VMS_EINVAL, "min_bt must be >= 0");
+    c->prm.inout_mode = mode;
+    c->prm.learned_min_bt = min_bt;
+    c->mlp = (const vmsm::MlpHandle *)mlp;
+    return VMS_OK;
+}
+
+int vms_relabel_stats(vms_ctx *c, int64_t *out) {
+    if (!c || !out) return fail(c, VMS_EINVAL, "null argument");
+    unsigned long long v = 0;
+    if (c->n_sq) {
+        HIPCHK(c, hipMemcpyAsync(&v, c->d_counters + 2, sizeof v, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    out[0] = (int64_t)c->n_labelled;
+    out[1] = (int64_t)v;
+    return VMS_OK;
+}
+
 int vms_stats(vms_ctx *c, int64_t *out) {
     if (!c || !out) return fail(c, VMS_EINVAL, "null argument");
     out[0] = c->n_std;
@@ -1751,13 +1829,20 @@ struct vms_batch {
     std::vector<vms_ctx *> ctx;
     int precision = 0;
     int tile = 4, groups_per_cu = 8, n_cu = 256;
+    bool by_weight = true;  // eq. (Wpart) units, heaviest first; else the fixed order
     std::vector<vmsk::AsmArgs> h_std, h_sub;
     std::vector<void *> h_vals;  // CSR values of each tree
     std::vector<double *> h_resid;  // residual of each tree (or null)
     vmsk::AsmArgs *d_std = nullptr, *d_sub = nullptr;
     vmsk::BatchUnit *d_units = nullptr;
-    int64_t n_units = 0, n_sub_units = 0, units_cap = 0;
+    int64_t n_units = 0, units_cap = 0;
+    double unit_weight_max = 0, unit_weight_sum = 0;
     unsigned long long *d_counter = nullptr;
+    // batched gathers: per-tree lists, first block / node of each tree
+    std::vector<vmsk::GatherTab> h_tabs;
+    vmsk::GatherTab *d_tabs = nullptr;
+    int64_t *d_blk_prefix = nullptr, *d_node_prefix = nullptr;
+    int64_t tot_blocks = 0, tot_nodes = 0;
     DevBuf buf;
     // graph replay
     bool use_graph = false, captured = false;
@@ -1813,22 +1898,59 @@ int batch_check(vms_batch *b) {
 }
 
 int batch_units(vms_batch *b) {
+    // Units of about `tile` element weights of eq. (Wpart): an OUT element
+    // weighs n_Vgp / n_Tgp = 1, a sub-cell work item its points / 8 (the
+    // batch has no surface terms). Runs of consecutive items of one kind and
+    // one tree are cut when they reach the target weight; the list is ordered
+    // by decreasing weight (longest first) so that the queue ends on light
+    // units.
+    // Fixed order (by_weight false): every sub-cell work item a unit of its
+    // own, all of them first, then runs of `tile` OUT elements.
+    const double target = b->by_weight ? (double)b->tile : 0.0;
     std::vector<vmsk::BatchUnit> u;
-    // sub-cell work first (heavier units), then runs of `tile` OUT elements
-    for (size_t t = 0; t < b->ctx.size(); ++t)
-        for (int64_t i = 0; i < b->ctx[t]->n_sub_items; ++i) u.push_back({(int32_t)t, 1, i, 1, 0});
-    b->n_sub_units = (int64_t)u.size();
-    for (size_t t = 0; t < b->ctx.size(); ++t)
-        for (int64_t i = 0; i < b->ctx[t]->n_std; i += b->tile)
-            u.push_back({(int32_t)t, 0, i, (int32_t)std::min<int64_t>(b->tile, b->ctx[t]->n_std - i), 0});
-    b->n_units = (int64_t)u.size();
+    std::vector<double> w;
+    for (size_t t = 0; t < b->ctx.size(); ++t) {
+        const vms_ctx *c = b->ctx[t];
+        int64_t first = 0;
+        double acc = 0;
+        for (int64_t i = 0; i < c->n_sub_items; ++i) {
+            acc += c->sub_item_cnt[i] / 8.0;
+            if (acc >= target || i + 1 == c->n_sub_items) {
+                u.push_back({(int32_t)t, 1, first, (int32_t)(i + 1 - first), 0});
+                w.push_back(acc);
+                first = i + 1;
+                acc = 0;
+            }
+        }
+        for (int64_t i = 0; i < c->n_std; i += b->tile) {
+            const int64_t n = std::min<int64_t>(b->tile, c->n_std - i);
+            u.push_back({(int32_t)t, 0, i, (int32_t)n, 0});
+            w.push_back((double)n);
+        }
+    }
+    std::vector<int64_t> ord(u.size());
+    for (size_t k = 0; k < ord.size(); ++k) ord[k] = (int64_t)k;
+    if (b->by_weight)
+        std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return w[x] > w[y]; });
+    else
+        std::stable_partition(ord.begin(), ord.end(), [&](int64_t x) { return u[x].sub != 0; });
+    std::vector<vmsk::BatchUnit> us(u.size());
+    b->unit_weight_max = 0;
+    b->unit_weight_sum = 0;
+    for (size_t k = 0; k < ord.size(); ++k) {
+        us[k] = u[ord[k]];
+        b->unit_weight_max = std::max(b->unit_weight_max, w[ord[k]]);
+        b->unit_weight_sum += w[ord[k]];
+    }
+    b->n_units = (int64_t)us.size();
     if (b->n_units > b->units_cap) {
+        b->buf.free(b->d_units);
         if (b->buf.alloc(&b->d_units, (size_t)b->n_units)) return bfail(b, VMS_ENOMEM, "device allocation failed");
         b->units_cap = b->n_units;
     }
-    if (hipMemcpyAsync(b->d_units, u.data(), u.size() * sizeof(vmsk::BatchUnit), hipMemcpyHostToDevice,
-                       b->stream) ||
-        hipStreamSynchronize(b->stream))
+    if (b->n_units && (hipMemcpyAsync(b->d_units, us.data(), us.size() * sizeof(vmsk::BatchUnit),
+                                      hipMemcpyHostToDevice, b->stream) ||
+                       hipStreamSynchronize(b->stream)))
         return bfail(b, VMS_EHIP, "device copy failed (units)");
     return VMS_OK;
 }
@@ -1858,9 +1980,31 @@ int batch_tables(vms_batch *b, const vms_fields *f, void *const *vals, double *c
         a.entries = c->d_entries;
         a.slot0 = c->n_std;
         b->h_sub[t] = a;
+        vmsk::GatherTab &G = b->h_tabs[t];
+        G.em = c->d_em;
+        G.cb_off = c->d_cb_off;
+        G.contrib = c->d_contrib;
+        G.vbase = c->d_vbase;
+        G.vstride = c->d_vstride;
+        G.vals = vals[t];
+        G.rrec = c->d_rrec;
+        G.roff = c->d_roff;
+        G.rlist = c->d_rlist;
+        G.resid = resid ? resid[t] : nullptr;
     }
+    std::vector<int64_t> bp(n + 1, 0), np(n + 1, 0);
+    for (size_t t = 0; t < n; ++t) {
+        bp[t + 1] = bp[t] + b->ctx[t]->n_blocks;
+        np[t + 1] = np[t] + b->ctx[t]->mesh.n_nodes;
+    }
+    b->tot_blocks = bp[n];
+    b->tot_nodes = np[n];
     if (hipMemcpyAsync(b->d_std, b->h_std.data(), n * sizeof(vmsk::AsmArgs), hipMemcpyHostToDevice, b->stream) ||
         hipMemcpyAsync(b->d_sub, b->h_sub.data(), n * sizeof(vmsk::AsmArgs), hipMemcpyHostToDevice, b->stream) ||
+        hipMemcpyAsync(b->d_tabs, b->h_tabs.data(), n * sizeof(vmsk::GatherTab), hipMemcpyHostToDevice,
+                       b->stream) ||
+        hipMemcpyAsync(b->d_blk_prefix, bp.data(), bp.size() * 8, hipMemcpyHostToDevice, b->stream) ||
+        hipMemcpyAsync(b->d_node_prefix, np.data(), np.size() * 8, hipMemcpyHostToDevice, b->stream) ||
         hipStreamSynchronize(b->stream))
         return bfail(b, VMS_EHIP, "device copy failed (tables)");
     return VMS_OK;
@@ -1872,13 +2016,11 @@ int batch_tables(vms_batch *b, const vms_fields *f, void *const *vals, double *c
 void batch_enqueue(vms_batch *b, bool timed) {
     if (timed) (void)hipEventRecord(b->ev[0], b->stream);
     if (timed) (void)hipEventRecord(b->ev[1], b->stream);
-    vmsk::launch_assemble_batch(b->stream, b->precision, b->d_std, b->d_sub, b->d_units, b->n_sub_units,
-                                b->n_units, b->d_counter, b->n_cu * b->groups_per_cu);
+    vmsk::launch_assemble_batch(b->stream, b->precision, b->d_std, b->d_sub, b->d_units, b->n_units,
+                                b->d_counter, b->n_cu * b->groups_per_cu);
     if (timed) (void)hipEventRecord(b->ev[2], b->stream);
-    for (size_t t = 0; t < b->ctx.size(); ++t) {
-        gather_csr(b->ctx[t], b->stream, b->h_vals[t]);
-        if (b->h_resid[t]) gather_resid(b->ctx[t], b->stream, b->h_resid[t]);
-    }
+    vmsk::launch_gather_batch(b->stream, b->precision, b->d_tabs, b->d_blk_prefix, b->tot_blocks,
+                              b->d_node_prefix, b->tot_nodes, (int)b->ctx.size());
     if (timed) (void)hipEventRecord(b->ev[3], b->stream);
     b->timed = timed;
 }
@@ -1920,8 +2062,10 @@ int vms_batch_create(vms_batch **out, vms_ctx *const *ctxs, int n, void *stream)
     b->h_sub.resize(n);
     b->h_vals.assign(n, nullptr);
     b->h_resid.assign(n, nullptr);
+    b->h_tabs.assign(n, vmsk::GatherTab{});
     if (b->buf.alloc(&b->d_std, (size_t)n) || b->buf.alloc(&b->d_sub, (size_t)n) ||
-        b->buf.alloc(&b->d_counter, 2)) {
+        b->buf.alloc(&b->d_counter, 2) || b->buf.alloc(&b->d_tabs, (size_t)n) ||
+        b->buf.alloc(&b->d_blk_prefix, (size_t)n + 1) || b->buf.alloc(&b->d_node_prefix, (size_t)n + 1)) {
         delete b;
         return bfail(nullptr, VMS_ENOMEM, "device allocation failed");
     }
@@ -1941,6 +2085,14 @@ int vms_batch_set_config(vms_batch *b, int tile, int groups_per_cu) {
         return batch_units(b);
     }
     return VMS_OK;
+}
+
+int vms_batch_set_order(vms_batch *b, int by_weight) {
+    if (!b) return bfail(nullptr, VMS_EINVAL, "null batch");
+    if ((by_weight != 0) == b->by_weight) return VMS_OK;
+    b->by_weight = by_weight != 0;
+    drop_graph(b);
+    return batch_units(b);
 }
 
 int vms_batch_get_config(vms_batch *b, int *tile, int *groups_per_cu, int64_t *n_units) {

@@ -873,27 +873,32 @@ __global__ VMS_ASM_BOUNDS(1) void k_asm2_jv(AsmArgs a, const double *x) {
     asm_item<T, MODE, SUB, false, MODE == 0 ? 4 : 8, true>(a, blockIdx.x, sm, x);
 }
 
-// Persistent form over many contexts: every workgroup takes units from a
-// device counter until none is left; one launch per kind of unit (runs of OUT
-// elements, or sub-cell work items), each unit from one tree. Units
-// [first, last) of the list are this launch's.
-template <typename T, int MODE, bool SUB>
-__global__ VMS_ASM_BOUNDS(MODE) void k_asm_batch(const AsmArgs *args, const BatchUnit *units,
-                                                 int64_t first, int64_t last,
+// Persistent form over many contexts: every workgroup takes units of work
+// from a device counter until none is left, in the order of the unit list
+// (heaviest first); a unit is a run of OUT elements or of sub-cell work items
+// of one tree. One launch for all units.
+template <typename T, int MODE>
+__global__ VMS_ASM_BOUNDS(MODE) void k_asm_batch(const AsmArgs *std_args, const AsmArgs *sub_args,
+                                                 const BatchUnit *units, int64_t n_units,
                                                  unsigned long long *counter) {
-    __shared__ Smem<T, MODE == 0 ? 4 : 8, true, 7> sm;
+    constexpr int PTS = MODE == 0 ? 4 : 8;
+    __shared__ Smem<T, PTS, true, 7> sm;
     __shared__ int64_t su;
     __shared__ AsmArgs sa;  // the unit's tree, read from LDS where used
     for (;;) {
         __syncthreads();
-        if (threadIdx.x == 0) su = first + (int64_t)atomicAdd(counter, 1ull);
+        if (threadIdx.x == 0) su = (int64_t)atomicAdd(counter, 1ull);
         __syncthreads();
         const int64_t u = su;
-        if (u >= last) break;
+        if (u >= n_units) break;
         const BatchUnit U = units[u];
-        if (threadIdx.x == 0) sa = args[U.tree];
+        if (threadIdx.x == 0) sa = U.sub ? sub_args[U.tree] : std_args[U.tree];
         __syncthreads();
-        for (int k = 0; k < U.count; ++k) asm_item<T, MODE, SUB, true, MODE == 0 ? 4 : 8>(sa, U.first + k, sm);
+        if (U.sub) {
+            for (int k = 0; k < U.count; ++k) asm_item<T, MODE, true, true, PTS>(sa, U.first + k, sm);
+        } else {
+            for (int k = 0; k < U.count; ++k) asm_item<T, MODE, false, true, PTS>(sa, U.first + k, sm);
+        }
     }
 }
 
@@ -902,44 +907,40 @@ __global__ void k_reset_counter(unsigned long long *c) {
 }
 
 void launch_assemble_batch(hipStream_t s, int precision, const AsmArgs *std_args,
-                           const AsmArgs *sub_args, const BatchUnit *units, int64_t n_sub_units,
-                           int64_t n_units, unsigned long long *counter, int n_groups) {
+                           const AsmArgs *sub_args, const BatchUnit *units, int64_t n_units,
+                           unsigned long long *counter, int n_groups) {
     hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, counter);
+    if (n_units <= 0) return;
     dim3 grid((unsigned)n_groups), block(64);
-#define VMS_B(T, MODE)                                                                           \
-    do {                                                                                         \
-        if (n_sub_units > 0)                                                                     \
-            hipLaunchKernelGGL((k_asm_batch<T, MODE, true>), grid, block, 0, s, sub_args, units, \
-                               (int64_t)0, n_sub_units, counter);                                \
-        if (n_units > n_sub_units)                                                               \
-            hipLaunchKernelGGL((k_asm_batch<T, MODE, false>), grid, block, 0, s, std_args, units, \
-                               n_sub_units, n_units, counter + 1);                               \
-    } while (0)
-    if (precision == 0) VMS_B(double, 0);
-    else if (precision == 1) VMS_B(float, 1);
-    else VMS_B(float, 2);
-#undef VMS_B
+    if (precision == 0)
+        hipLaunchKernelGGL((k_asm_batch<double, 0>), grid, block, 0, s, std_args, sub_args, units, n_units,
+                           counter);
+    else if (precision == 1)
+        hipLaunchKernelGGL((k_asm_batch<float, 1>), grid, block, 0, s, std_args, sub_args, units, n_units,
+                           counter);
+    else
+        hipLaunchKernelGGL((k_asm_batch<float, 2>), grid, block, 0, s, std_args, sub_args, units, n_units,
+                           counter);
 }
 
 // CSR values from the element-matrix records. A thread takes V consecutive
 // entries of one row of a CSR block B (entries e0 .. e0+V-1, e = 4 i + j) and
 // sums them over B's contributions in list order (ascending record), fetching
 // the record entries V at a time and four contributions at a time; the CSR
-// place of entry (i, j) is vbase[B] + i vstride[B] + j.
+// place of entry (i, j) is vbase[B] + i |vstride[B]| + j. A negative stride
+// marks the diagonal block of an inactive node: it has no records and becomes
+// an identity block.
 template <typename T, int V>
-__global__ void k_gather(const T *em, const int64_t *cb_off, const int32_t *contrib,
-                         const int64_t *vbase, const int32_t *vstride, int64_t nb, T *vals) {
+__device__ inline void gather_block(const T *em, const int64_t *cb_off, const int32_t *contrib,
+                                    const int64_t *vbase, const int32_t *vstride, int64_t B, int e0,
+                                    T *vals) {
     typedef T vec __attribute__((ext_vector_type(V)));
-    constexpr int TPB = 16 / V;  // threads per block
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t B = g / TPB;
-    if (B >= nb) return;
-    const int e0 = (int)(g % TPB) * V;
     const int64_t c0 = cb_off[B], c1 = cb_off[B + 1];
     const int64_t base = vbase[B];
-    const int stride = vstride[B];
+    const int st = vstride[B];
+    const int stride = st < 0 ? -st : st;
     double s[V];
-    for (int q = 0; q < V; ++q) s[q] = 0.0;
+    for (int q = 0; q < V; ++q) s[q] = (st < 0 && ((e0 + q) >> 2) == ((e0 + q) & 3)) ? 1.0 : 0.0;
     for (int64_t c = c0; c < c1; c += 4) {
         int32_t r[4];
         for (int u = 0; u < 4; ++u) r[u] = c + u < c1 ? contrib[c + u] : -1;
@@ -954,12 +955,45 @@ __global__ void k_gather(const T *em, const int64_t *cb_off, const int32_t *cont
     for (int q = 0; q < V; ++q) dst[q] = (T)s[q];
 }
 
+template <typename T, int V>
+__global__ void k_gather(const T *em, const int64_t *cb_off, const int32_t *contrib,
+                         const int64_t *vbase, const int32_t *vstride, int64_t nb, T *vals) {
+    constexpr int TPB = 16 / V;  // threads per block
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t B = g / TPB;
+    if (B >= nb) return;
+    gather_block<T, V>(em, cb_off, contrib, vbase, vstride, B, (int)(g % TPB) * V, vals);
+}
+
+// The same summations for every tree of a batch in one launch: the blocks of
+// all trees one after the other (prefix[t] = first block of tree t), then the
+// nodes of all trees for the residual (node_prefix).
+__device__ inline int tree_of(const int64_t *prefix, int n, int64_t g) {
+    int lo = 0, hi = n;  // prefix[lo] <= g < prefix[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <typename T, int V>
+__global__ void k_gather_batch(const GatherTab *tabs, const int64_t *prefix, int n_trees) {
+    constexpr int TPB = 16 / V;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t Bg = g / TPB;
+    if (Bg >= prefix[n_trees]) return;
+    const int t = tree_of(prefix, n_trees, Bg);
+    const GatherTab &G = tabs[t];
+    gather_block<T, V>((const T *)G.em, G.cb_off, G.contrib, G.vbase, G.vstride, Bg - prefix[t],
+                       (int)(g % TPB) * V, (T *)G.vals);
+}
+
 // residual by node from the residual records (one thread per node, its
 // entries in ascending record order)
-__global__ void k_res_gather(const double *rrec, const int64_t *roff, const int32_t *rlist, int64_t n_nodes,
-                             double *out) {
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= n_nodes) return;
+__device__ inline void res_node(const double *rrec, const int64_t *roff, const int32_t *rlist, int64_t n,
+                                double *out) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     for (int64_t c = roff[n]; c < roff[n + 1]; ++c) {
         const int64_t q = rlist[c];
@@ -973,6 +1007,36 @@ __global__ void k_res_gather(const double *rrec, const int64_t *roff, const int3
     out[4 * n + 1] = s1;
     out[4 * n + 2] = s2;
     out[4 * n + 3] = s3;
+}
+
+__global__ void k_res_gather(const double *rrec, const int64_t *roff, const int32_t *rlist, int64_t n_nodes,
+                             double *out) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= n_nodes) return;
+    res_node(rrec, roff, rlist, n, out);
+}
+
+__global__ void k_res_gather_batch(const GatherTab *tabs, const int64_t *prefix, int n_trees) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= prefix[n_trees]) return;
+    const int t = tree_of(prefix, n_trees, g);
+    const GatherTab &G = tabs[t];
+    if (G.resid) res_node(G.rrec, G.roff, G.rlist, g - prefix[t], G.resid);
+}
+
+void launch_gather_batch(hipStream_t s, int precision, const GatherTab *tabs, const int64_t *blk_prefix,
+                         int64_t n_blocks, const int64_t *node_prefix, int64_t n_nodes, int n_trees) {
+    if (n_blocks > 0) {
+        if (precision == 0)
+            hipLaunchKernelGGL((k_gather_batch<double, 2>), dim3((unsigned)((8 * n_blocks + 255) / 256)),
+                               dim3(256), 0, s, tabs, blk_prefix, n_trees);
+        else
+            hipLaunchKernelGGL((k_gather_batch<float, 4>), dim3((unsigned)((4 * n_blocks + 255) / 256)),
+                               dim3(256), 0, s, tabs, blk_prefix, n_trees);
+    }
+    if (n_nodes > 0)
+        hipLaunchKernelGGL(k_res_gather_batch, dim3((unsigned)((n_nodes + 255) / 256)), dim3(256), 0, s, tabs,
+                           node_prefix, n_trees);
 }
 
 void launch_res_gather(hipStream_t s, const double *rrec, const int64_t *roff, const int32_t *rlist,

@@ -17,6 +17,7 @@
 // Gauss points are all fluid is kept whole, all solid dropped, mixed split
 // again, and at the maximum level only fluid points are kept.
 #include "inout_dev.h"
+#include "mlp_dev.h"
 
 namespace vmsk {
 using namespace vmsd;
@@ -127,6 +128,11 @@ __device__ static int local_label_lds(const SurfDev &S, const double *P, const d
 // level; a kept point sets the bit of its key (and records its level) in a
 // bitmap over the key space, so that the canonical (ascending key) position
 // of every kept point is the number of set bits below it: no sort is needed.
+// LEARNED: on elements with at least min_bt background triangles the 64
+// candidate points of a batch first go through the signed-distance network;
+// a point whose |prediction| reaches its margin takes the network's sign,
+// every other point the exact test.
+template <bool LEARNED>
 __global__ __launch_bounds__(64) void k_subquad(SurfDev S, GeoArgs g, SubqArgs a, int pass) {
     __shared__ uint32_t cells[2][SQ_MAXCELL];  // path digits, level 1 most significant
     __shared__ unsigned long long kbits[SQ_KEYS / 64];
@@ -136,8 +142,9 @@ __global__ __launch_bounds__(64) void k_subquad(SurfDev S, GeoArgs g, SubqArgs a
     __shared__ uint8_t vl[8];
     __shared__ double tv[SQ_BTMAX][9];
     __shared__ double tb[SQ_BTMAX][6];
+    __shared__ __attribute__((aligned(16))) _Float16 act[LEARNED ? 64 : 1][vmsm::LDH];
     const int lane = threadIdx.x;
-    const int64_t i = blockIdx.x;
+    const int64_t i = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
     if (i >= a.n) return;
     const int D = g.depth;
     const int M = g.max_level;
@@ -160,6 +167,7 @@ __global__ __launch_bounds__(64) void k_subquad(SurfDev S, GeoArgs g, SubqArgs a
     const int32_t *bt = a.bt_ids + a.bt_off[i];
     const int nbt = (int)(a.bt_off[i + 1] - a.bt_off[i]);
     const bool staged = nbt <= SQ_BTMAX;
+    const bool use_net = LEARNED && nbt >= a.learned.min_bt;  // uniform over the workgroup
     if (staged)
         for (int t = lane; t < nbt; t += 64) {
             const int id = bt[t];
@@ -190,6 +198,8 @@ __global__ __launch_bounds__(64) void k_subquad(SurfDev S, GeoArgs g, SubqArgs a
             const int c = idx >> 3, gp = idx & 7;
             int lab = 1;
             uint32_t path = 0;
+            double P[3] = {0.0, 0.0, 0.0};
+            int v0 = 0;
             if (valid) {
                 path = cells[cur][c];
                 int64_t A[3] = {A0[0], A0[1], A0[2]};
@@ -198,15 +208,25 @@ __global__ __launch_bounds__(64) void k_subquad(SurfDev S, GeoArgs g, SubqArgs a
                     for (int ax = 0; ax < 3; ++ax)
                         if ((dgt >> ax) & 1u) A[ax] += SE >> k;
                 }
-                double P[3];
                 for (int ax = 0; ax < 3; ++ax)
                     P[ax] = point_coord(g.origin[ax], g.root_len, scF, A[ax], S_l,
                                         ((gp >> ax) & 1) ? VMS_GP : VMS_GM);
                 // the corner nearest P: the element octant of P's sub-cell (a
                 // sub-cell of level 1 or deeper never straddles the element's midplanes)
-                int v0 = 0;
                 for (int ax = 0; ax < 3; ++ax)
                     if (2 * (A[ax] - A0[ax]) + S_l > SE) v0 |= 1 << ax;
+            }
+            bool decided = false;
+            if constexpr (LEARNED) {
+                if (use_net) {
+                    const float y = vmsm::net_output64(a.learned.net, P, valid, act);
+                    if (valid && fabsf(y) >= vmsm::point_margin(a.learned.grid, a.learned.margin, P)) {
+                        lab = y < 0.f ? 1 : 0;
+                        decided = true;
+                    }
+                }
+            }
+            if (valid && !decided) {
                 lab = staged ? local_label_lds(S, P, V, vl, tv, tb, nbt, a.ndeg, v0)
                              : local_label(S, P, V, vl, bt, nbt, a.ndeg, v0);
                 ++nlab;
@@ -231,6 +251,7 @@ __global__ __launch_bounds__(64) void k_subquad(SurfDev S, GeoArgs g, SubqArgs a
         cur = nxt;
     }
     if (nlab && pass == 0) atomicAdd(a.nlabel, nlab);
+    if (nlab && pass == 1 && a.nexact) atomicAdd(a.nexact, nlab);
     // kept points: set bits of the bitmap; lane w owns word w
     const unsigned long long word = kbits[lane];
     const int cw = __popcll(word);
@@ -262,10 +283,22 @@ __global__ __launch_bounds__(64) void k_subquad(SurfDev S, GeoArgs g, SubqArgs a
     }
 }
 
+__global__ void k_zero_u64(unsigned long long *c) {
+    if (threadIdx.x == 0) *c = 0ull;
+}
+
+void launch_zero_u64(hipStream_t s, unsigned long long *c) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, c);
+}
+
 void launch_subquad(hipStream_t s, const SurfDev &S, const GeoArgs &g, const SubqArgs &a,
                     int pass) {
-    if (a.n <= 0) return;
-    hipLaunchKernelGGL(k_subquad, dim3((unsigned)a.n), dim3(64), 0, s, S, g, a, pass);
+    const int64_t n = a.order ? a.n_order : a.n;
+    if (n <= 0) return;
+    if (a.learned.net.theta)
+        hipLaunchKernelGGL(k_subquad<true>, dim3((unsigned)n), dim3(64), 0, s, S, g, a, pass);
+    else
+        hipLaunchKernelGGL(k_subquad<false>, dim3((unsigned)n), dim3(64), 0, s, S, g, a, pass);
 }
 
 }  // namespace vmsk

@@ -42,6 +42,32 @@ void launch_point_labels_list(hipStream_t s, const SurfDev &S, const int64_t *id
                               const double *py, const double *pz, uint8_t *lab,
                               unsigned long long *ndeg);
 
+// Learned in-out filter (signed-distance network) as the kernels see it.
+// Parameters (float): W1 (64x64, out x in), b1, W2, b2, W3, b3, w4 (64), b4 (1).
+struct Net {
+    const float *theta;      // FP32 parameters (null: no network)
+    const _Float16 *w16;     // FP16 copies of W1, W2, W3 (3 x 64 x 64)
+    const float *B;          // 32 x 3 Fourier matrix
+    float lo[3], inv[3];     // xh = 2 (x - lo) * inv - 1 with inv = 1 / (hi - lo)
+    double blo[3], bhi[3];   // the box itself
+};
+
+// Per-cell margins over the network box (m == nullptr: the scalar margin)
+struct MarginGrid {
+    const float *m;
+    int n[3];
+    double lo[3], inv[3];  // cell of x along k: floor((x - lo) inv), clamped
+};
+
+// The network in front of the exact test of the sub-cell quadrature: used on
+// the elements with at least min_bt background triangles.
+struct LearnedArgs {
+    Net net;
+    MarginGrid grid;
+    float margin;
+    int32_t min_bt;
+};
+
 // Adaptive sub-cell quadrature of INTERCEPTED elements. pass 0 counts kept
 // points per element into cnt; pass 1 writes the sorted entries
 // (key << 2 | level) at off[i]. Per element i of the list: element id,
@@ -60,8 +86,13 @@ struct SubqArgs {
     unsigned long long *nlabel;
     unsigned long long *ndeg;
     unsigned int *flag;  // bit 0: a relabelled element changed its point count
+    unsigned long long *nexact;  // pass 1: points labelled by the exact test (added to)
+    LearnedArgs learned; // learned.net.theta null: exact labels only
+    const int32_t *order;  // non-null: only the n_order elements order[..] of the list
+    int64_t n_order;
 };
 void launch_subquad(hipStream_t s, const SurfDev &S, const GeoArgs &g, const SubqArgs &a, int pass);
+void launch_zero_u64(hipStream_t s, unsigned long long *c);
 
 // Assembly.
 struct AsmArgs {
@@ -116,11 +147,11 @@ struct BatchUnit {
     int32_t count;
     int32_t pad;
 };
-// units [0, n_sub_units) are sub-cell units, the rest runs of OUT elements;
-// counter: two device counters (reset by the launch sequence)
+// one persistent launch of n_groups workgroups over all units, in list order;
+// counter: a device counter (reset by the launch sequence)
 void launch_assemble_batch(hipStream_t s, int precision, const AsmArgs *std_args,
-                           const AsmArgs *sub_args, const BatchUnit *units, int64_t n_sub_units,
-                           int64_t n_units, unsigned long long *counter, int n_groups);
+                           const AsmArgs *sub_args, const BatchUnit *units, int64_t n_units,
+                           unsigned long long *counter, int n_groups);
 void launch_assemble_mixed(hipStream_t s, const AsmArgs &a, bool sub, bool mat, int fp16);
 
 // CSR values from element-matrix records (see k_gather)
@@ -130,8 +161,24 @@ void launch_gather_f32(hipStream_t s, const float *em, const int64_t *cb_off, co
                        const int64_t *vbase, const int32_t *vstride, int64_t nb, float *vals);
 void launch_fill_f64(hipStream_t s, double *p, int64_t n, double v);
 void launch_fill_f32(hipStream_t s, float *p, int64_t n, float v);
-void launch_set_ones_f64(hipStream_t s, double *vals, const int64_t *idx, int64_t n);
-void launch_set_ones_f32(hipStream_t s, float *vals, const int64_t *idx, int64_t n);
+// One tree's summation lists and outputs, for the batched gathers.
+struct GatherTab {
+    const void *em;           // element-matrix records (double or float)
+    const int64_t *cb_off;
+    const int32_t *contrib;
+    const int64_t *vbase;
+    const int32_t *vstride;
+    void *vals;
+    const double *rrec;
+    const int64_t *roff;
+    const int32_t *rlist;
+    double *resid;            // null: no residual for this tree
+};
+// CSR values (identity blocks of inactive nodes included) and residuals of
+// every tree: blk_prefix / node_prefix [n_trees + 1] are the trees' first
+// blocks / nodes in the concatenation; n_blocks / n_nodes their totals
+void launch_gather_batch(hipStream_t s, int precision, const GatherTab *tabs, const int64_t *blk_prefix,
+                         int64_t n_blocks, const int64_t *node_prefix, int64_t n_nodes, int n_trees);
 // rows of the listed nodes -> identity rows (diag_pos: block index of the
 // diagonal in each node row), their residual entries (if resid) -> 0
 void launch_dirichlet_rows_f64(hipStream_t s, double *vals, const int64_t *nrow_ptr, const int32_t *diag_pos,

@@ -16,21 +16,8 @@ constexpr int H = 64, NF = 32;
 constexpr int OFF_W1 = 0, OFF_B1 = 4096, OFF_W2 = 4160, OFF_B2 = 8256, OFF_W3 = 8320, OFF_B3 = 12416,
               OFF_W4 = 12480, OFF_B4 = 12544, N_PARAMS = 12545;
 
-// Device view of a network (passed by value to kernels).
-struct Net {
-    const float *theta;      // FP32 parameters
-    const _Float16 *w16;     // FP16 copies of W1, W2, W3 (3 x 64 x 64)
-    const float *B;          // 32 x 3 Fourier matrix
-    float lo[3], inv[3];     // xh = 2 (x - lo) * inv - 1 with inv = 1 / (hi - lo)
-    double blo[3], bhi[3];   // the box itself
-};
-
-// Per-cell margins over the network box (m == nullptr: none)
-struct MarginGrid {
-    const float *m;
-    int n[3];
-    double lo[3], inv[3];  // cell of x along k: floor((x - lo) inv), clamped
-};
+using vmsk::MarginGrid;
+using vmsk::Net;
 
 // Scratch kept by an in-out handle for the learned mode.
 struct Filter {
@@ -55,6 +42,11 @@ void launch_decide(hipStream_t s, const float *pred, int64_t n, float margin, co
 
 // Grow the filter's scratch to n points (no-op if it holds that many).
 int reserve_filter(Filter &f, int64_t n);
+
+// The handle's network, margin grid and scalar margin as the kernels see them.
+Net mlp_net(const MlpHandle *h);
+MarginGrid mlp_grid(const MlpHandle *h);
+float mlp_margin(const MlpHandle *h);
 
 int classify_learned(hipStream_t s, Filter &f, const MlpHandle *net, const vmsk::SurfDev &S,
                      const double *px, const double *py, const double *pz, int64_t n,

@@ -17,15 +17,13 @@
 #include "../../include/vms.h"
 #include "inout_dev.h"
 #include "mlp.h"
+#include "mlp_dev.h"
 
 #include <cmath>
 #include <string>
 #include <vector>
 
 namespace vmsm {
-
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 
 void Filter::release() {
     if (d_idx) (void)hipFree(d_idx);
@@ -37,7 +35,6 @@ void Filter::release() {
     cap = 0;
 }
 
-__device__ inline float silu(float a) { return a / (1.0f + __expf(-a)); }
 __device__ inline float dsilu(float a) {
     const float s = 1.0f / (1.0f + __expf(-a));
     return s * (1.0f + a * (1.0f - s));
@@ -192,79 +189,15 @@ __global__ void k_to_half(const float *theta, _Float16 *w16) {
 // inference: FP16 MFMA, 64 points per wave
 // ---------------------------------------------------------------------------
 
-constexpr int LDH = 72;  // fp16 row length (padding)
-
 __global__ __launch_bounds__(64) void k_predict(Net net, const double *px, const double *py,
                                                 const double *pz, int64_t n, float *pred) {
     __shared__ __attribute__((aligned(16))) _Float16 act[64][LDH];
-    const int l = threadIdx.x;
-    const int64_t i0 = (int64_t)blockIdx.x * 64;
-    const int64_t gi = i0 + l;
-    // features of point l (sin / cos of 2 pi z, z in revolutions)
-    {
-        float xh[3] = {0.f, 0.f, 0.f};
-        if (gi < n) {
-            const double P[3] = {px[gi], py[gi], pz[gi]};
-            for (int k = 0; k < 3; ++k) xh[k] = (float)(2.0 * (P[k] - (double)net.lo[k]) * (double)net.inv[k] - 1.0);
-        }
-        for (int j = 0; j < NF; ++j) {
-            const float z = net.B[3 * j] * xh[0] + net.B[3 * j + 1] * xh[1] + net.B[3 * j + 2] * xh[2];
-            act[l][j] = (_Float16)__builtin_amdgcn_sinf(z);
-            act[l][NF + j] = (_Float16)__builtin_amdgcn_cosf(z);
-        }
-    }
-    __syncthreads();
-    const int row = l & 15, g = l >> 4;
-    const int offB[3] = {OFF_B1, OFF_B2, OFF_B3};
-    for (int L = 0; L < 3; ++L) {
-        // B operands: X[i][s] = act[s][i], lane holds s = 16 nt + row, i = 32 ks + 8 g + 0..7
-        v8h X[4][2];
-        for (int nt = 0; nt < 4; ++nt)
-            for (int ks = 0; ks < 2; ++ks)
-                X[nt][ks] = *(const v8h *)&act[16 * nt + row][32 * ks + 8 * g];
-        __syncthreads();
-        const _Float16 *W = net.w16 + L * H * H;
-        for (int mt = 0; mt < 4; ++mt) {
-            v8h A[2];
-            for (int ks = 0; ks < 2; ++ks) A[ks] = *(const v8h *)&W[(16 * mt + row) * H + 32 * ks + 8 * g];
-            float bias[4];
-            for (int r = 0; r < 4; ++r) bias[r] = net.theta[offB[L] + 16 * mt + 4 * g + r];
-            for (int nt = 0; nt < 4; ++nt) {
-                v4f acc = {0.f, 0.f, 0.f, 0.f};
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[0], X[nt][0], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A[1], X[nt][1], acc, 0, 0, 0);
-                // output rows = neurons 16 mt + 4 g + r, column = point 16 nt + row
-                for (int r = 0; r < 4; ++r) act[16 * nt + row][16 * mt + 4 * g + r] = (_Float16)silu(acc[r] + bias[r]);
-            }
-        }
-        __syncthreads();
-    }
-    if (gi < n) {
-        float y = net.theta[OFF_B4];
-        for (int i = 0; i < H; i += 8) {
-            const v8h a8 = *(const v8h *)&act[l][i];
-            for (int e = 0; e < 8; ++e) y += net.theta[OFF_W4 + i + e] * (float)a8[e];
-        }
-        // outside the network's box (which contains the surface's box) a point
-        // is outside the body: report it as far outside
-        const double P[3] = {px[gi], py[gi], pz[gi]};
-        for (int k = 0; k < 3; ++k)
-            if (P[k] < net.blo[k] || P[k] > net.bhi[k]) y = INFINITY;
-        pred[gi] = y;
-    }
-}
-
-// margin of a point: the scalar margin, or with a margin grid over the
-// network box the margin of the point's cell
-__device__ inline float point_margin(const MarginGrid &g, float margin, double x, double y, double z) {
-    if (!g.m) return margin;
-    const double P[3] = {x, y, z};
-    int c[3];
-    for (int k = 0; k < 3; ++k) {
-        const int v = (int)floor((P[k] - g.lo[k]) * g.inv[k]);
-        c[k] = v < 0 ? 0 : (v >= g.n[k] ? g.n[k] - 1 : v);
-    }
-    return g.m[((int64_t)c[2] * g.n[1] + c[1]) * g.n[0] + c[0]];
+    const int64_t gi = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const bool valid = gi < n;
+    double P[3] = {0.0, 0.0, 0.0};
+    if (valid) { P[0] = px[gi]; P[1] = py[gi]; P[2] = pz[gi]; }
+    const float y = net_output64(net, P, valid, act);
+    if (valid) pred[gi] = y;
 }
 
 __global__ void k_decide(const float *pred, int64_t n, float margin, MarginGrid grid,
@@ -273,7 +206,8 @@ __global__ void k_decide(const float *pred, int64_t n, float margin, MarginGrid 
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float y = pred[i];
-    if (fabsf(y) >= point_margin(grid, margin, px[i], py[i], pz[i])) {
+    const double P[3] = {px[i], py[i], pz[i]};
+    if (fabsf(y) >= point_margin(grid, margin, P)) {
         labels[i] = y < 0.f ? 1 : 0;
     } else {
         const unsigned long long k = atomicAdd(count, 1ull);
@@ -436,6 +370,10 @@ int reserve_filter(Filter &f, int64_t n) {
     f.cap = n;
     return VMS_OK;
 }
+
+Net mlp_net(const MlpHandle *h) { return h->net(); }
+MarginGrid mlp_grid(const MlpHandle *h) { return h->grid(); }
+float mlp_margin(const MlpHandle *h) { return h->margin; }
 
 int classify_learned(hipStream_t s, Filter &f, const MlpHandle *h, const vmsk::SurfDev &S,
                      const double *px, const double *py, const double *pz, int64_t n,

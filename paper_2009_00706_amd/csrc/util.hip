@@ -14,12 +14,6 @@ __global__ void k_fill(T *p, int64_t n, T v) {
         p[i] = v;
 }
 
-template <typename T>
-__global__ void k_set_ones(T *vals, const int64_t *idx, int64_t n) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) vals[idx[i]] = (T)1;
-}
-
 static unsigned grid_for(int64_t n, int bs) {
     int64_t g = (n + bs - 1) / bs;
     if (g > 65536) g = 65536;
@@ -33,17 +27,6 @@ void launch_fill_f64(hipStream_t s, double *p, int64_t n, double v) {
 void launch_fill_f32(hipStream_t s, float *p, int64_t n, float v) {
     if (n > 0) hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, p, n, v);
 }
-void launch_set_ones_f64(hipStream_t s, double *vals, const int64_t *idx, int64_t n) {
-    if (n > 0)
-        hipLaunchKernelGGL(k_set_ones<double>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                           vals, idx, n);
-}
-void launch_set_ones_f32(hipStream_t s, float *vals, const int64_t *idx, int64_t n) {
-    if (n > 0)
-        hipLaunchKernelGGL(k_set_ones<float>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                           vals, idx, n);
-}
-
 // Dirichlet rows: node nodes[blockIdx.x]'s four rows (entries 16 nrow_ptr[n]
 // .. 16 nrow_ptr[n + 1]) become identity rows; its residual entries zero
 template <typename T>

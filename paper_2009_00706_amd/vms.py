@@ -23,6 +23,7 @@ VMS_RELABEL = 1
 VMS_KSP_BCGS, VMS_KSP_GMRES = 0, 1
 VMS_SOLVE_DIRICHLET = 1
 VMS_EXPORT_SURFGP = 8
+VMS_EXPORT_NODE_ROW_PTR, VMS_EXPORT_NODE_COL = 9, 10
 (VMS_EXPORT_NODE_XYZ, VMS_EXPORT_ROW_PTR, VMS_EXPORT_COL_IDX, VMS_EXPORT_MARKERS,
  VMS_EXPORT_VERTEX_LAB, VMS_EXPORT_SUBGP, VMS_EXPORT_MASTERS) = range(1, 8)
 
@@ -31,7 +32,8 @@ EXPORTED = ["vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply"
             "vms_set_weak_bc", "vms_element_weights",
             "inout_classify",
             "inout_prepare", "inout_classify_prepared", "inout_release", "vms_stats",
-            "inout_reserve", "inout_classify_static", "inout_static_last_error",
+            "inout_classify_static", "inout_static_last_error", "inout_reserve",
+            "vms_set_inout", "vms_relabel_stats", "vms_batch_set_order",
             "vms_mesh_create", "vms_mesh_sizes", "vms_mesh_export", "vms_mesh_destroy",
             "vms_set_timing", "vms_last_timing", "vms_mlp_create", "vms_mlp_get_params",
             "vms_mlp_set_margin", "vms_mlp_set_margin_grid", "vms_mlp_grad", "vms_mlp_train", "vms_mlp_adam_step",
@@ -61,7 +63,8 @@ class Surface(C.Structure):
 class Params(C.Structure):
     _fields_ = [("rho", C.c_double), ("mu", C.c_double), ("dt", C.c_double),
                 ("theta", C.c_double), ("c_t", C.c_double), ("c_i", C.c_double),
-                ("quad_depth", C.c_int32), ("precision", C.c_uint32)]
+                ("quad_depth", C.c_int32), ("precision", C.c_uint32),
+                ("inout_mode", C.c_uint32), ("learned_min_bt", C.c_int32)]
 
 
 class Fields(C.Structure):
@@ -98,12 +101,16 @@ def lib():
         L.inout_classify_prepared.argtypes = [p, p, p, p, i64, p, u32, p]
         L.inout_release.argtypes = [p]
         L.inout_release.restype = None
+        L.vms_set_inout.argtypes = [p, u32, p, i32]
+        L.vms_set_inout.restype = C.c_int
+        L.vms_relabel_stats.argtypes = [p, p]
+        L.vms_relabel_stats.restype = C.c_int
+        L.inout_reserve.argtypes = [p, i64]
+        L.inout_reserve.restype = C.c_int
         L.inout_classify_static.argtypes = [C.POINTER(Surface), p, p, p, i64, p, p]
         L.inout_classify_static.restype = C.c_int
         L.inout_static_last_error.argtypes = []
         L.inout_static_last_error.restype = C.c_char_p
-        L.inout_reserve.argtypes = [p, i64]
-        L.inout_reserve.restype = C.c_int
         L.vms_stats.argtypes = [p, p]
         L.vms_mesh_create.argtypes = [C.POINTER(p), C.POINTER(Octree), p]
         L.vms_mesh_sizes.argtypes = [p, p, p, p]
@@ -126,6 +133,8 @@ def lib():
         L.vms_batch_create.argtypes = [C.POINTER(p), p, C.c_int, p]
         L.vms_batch_set_config.argtypes = [p, C.c_int, C.c_int]
         L.vms_batch_get_config.argtypes = [p, p, p, p]
+        L.vms_batch_set_order.argtypes = [p, C.c_int]
+        L.vms_batch_set_order.restype = C.c_int
         L.vms_batch_use_graph.argtypes = [p, C.c_int]
         L.vms_batch_assemble.argtypes = [p, p, p, p]
         L.vms_batch_autotune.argtypes = [p, p, p, p, p]
@@ -181,8 +190,8 @@ def make_surface(verts, tris):
 
 
 def make_params(rho=1.0, mu=0.01, dt=0.01, theta=0.5, c_t=4.0, c_i=36.0, quad_depth=3,
-                precision=VMS_FP64):
-    return Params(rho, mu, dt, theta, c_t, c_i, quad_depth, precision)
+                precision=VMS_FP64, inout_mode=VMS_INOUT_EXACT, learned_min_bt=0):
+    return Params(rho, mu, dt, theta, c_t, c_i, quad_depth, precision, inout_mode, learned_min_bt)
 
 
 # ---------------------------------------------------------------------------
@@ -256,6 +265,19 @@ def vms_stats(ctx):
             "n_hanging": v[4], "n_subgp": v[5], "n_surfgp": v[6]}
 
 
+def vms_set_inout(ctx, mode, mlp=None, min_bt=0):
+    """In-out test of the sub-cell quadrature on relabel: exact, or the learned
+    filter (a vms_mlp handle) on elements with at least min_bt background triangles."""
+    m = C.c_void_p(mlp.value if isinstance(mlp, C.c_void_p) else mlp) if mlp else None
+    _check(lib().vms_set_inout(ctx, int(mode), m, int(min_bt)), ctx)
+
+
+def vms_relabel_stats(ctx):
+    v = (C.c_int64 * 2)()
+    _check(lib().vms_relabel_stats(ctx, v), ctx)
+    return {"candidates": v[0], "exact_in_last_relabel": v[1]}
+
+
 def vms_element_weights(ctx, n_oct, ts_over_tv):
     """Per-element weights of eq. (Wpart) (host array of n_oct doubles)."""
     w = np.zeros(n_oct, np.float64)
@@ -277,6 +299,10 @@ def vms_export(ctx, what, n_oct=None):
         out = np.zeros(sz["n_rows"] + 1, np.int64)
     elif what == VMS_EXPORT_COL_IDX:
         out = np.zeros(sz["nnz"], np.int32)
+    elif what == VMS_EXPORT_NODE_ROW_PTR:
+        out = np.zeros(sz["n_nodes"] + 1, np.int64)
+    elif what == VMS_EXPORT_NODE_COL:
+        out = np.zeros(sz["nnz"] // 16, np.int32)
     elif what == VMS_EXPORT_MARKERS:
         out = np.zeros(n_oct, np.uint8)
     elif what == VMS_EXPORT_VERTEX_LAB:
@@ -490,6 +516,10 @@ def vms_batch_get_config(b):
     t, g, n = C.c_int(), C.c_int(), C.c_int64()
     _check(lib().vms_batch_get_config(b, C.byref(t), C.byref(g), C.byref(n)), None)
     return {"tile": t.value, "groups_per_cu": g.value, "n_units": n.value}
+
+
+def vms_batch_set_order(b, by_weight=True):
+    _check(lib().vms_batch_set_order(b, 1 if by_weight else 0), None)
 
 
 def vms_batch_use_graph(b, on=True):

@@ -180,20 +180,24 @@ def test_batch_tree_against_reference(env, oracle):
 
 
 @pytest.mark.timeout(900)
-def test_batch_full_size(env):
-    """The 64-tree workload at full size (log-uniform 1e4..5e5 octants, seed 3),
-    BF16x3, autotuned and replayed as a graph (the benchmark's launch): every
-    tree's values and residual equal its single-context assembly (values over
-    the rows of active nodes, identity rows exactly; norms on the device), and
-    a constant state gives a zero residual in every tree."""
+def test_batch_full_size(env, oracle):
+    """The 64-tree workload at full size (log-uniform 1e4..5e5 octants, seed
+    1003), BF16x3, autotuned and replayed as a graph (the benchmark's launch):
+    every tree's values and residual equal its single-context assembly (values
+    over the rows of active nodes, identity rows exactly; norms on the device);
+    the fixed queue order gives the same outputs bit for bit as the eq. (Wpart)
+    order; sampled rows of the largest tree match the CPU reference within the
+    mixed form's bar; a constant state gives a zero residual in every tree."""
     import os
     import time
+    import sampled_rows as SR
     torch, vms = env
     t0 = time.perf_counter()
-    work = I.batch_workload(64, 3, workers=min(16, os.cpu_count() or 1))
+    work = I.batch_workload(64, 1003, workers=min(16, os.cpu_count() or 1))
     print(f"64 trees, {sum(t.n for t, _ in work)} octants ({time.perf_counter() - t0:.1f} s)", flush=True)
+    big = int(np.argmax([t.n for t, _ in work]))
     stream = torch.cuda.Stream()
-    ctxs, fields, vals, resid, ident = [], [], [], [], []
+    ctxs, fields, vals, resid, ident, host_f = [], [], [], [], [], []
     with torch.cuda.stream(stream):
         for k, (tree, surf) in enumerate(work):
             ctx = vms.vms_create(tree, surf, vms.make_params(quad_depth=3, precision=vms.VMS_MIXED_BF16),
@@ -202,6 +206,8 @@ def test_batch_full_size(env):
             xyz = vms.vms_export(ctx, vms.VMS_EXPORT_NODE_XYZ).T.astype(np.float64) / \
                 float(1 << tree.max_level) * tree.root_len + np.asarray(tree.origin)
             f = I.make_fields(xyz, 3000 + k)
+            if k == big:
+                host_f = f
             fields.append({n: torch.as_tensor(f[n], device="cuda") for n in f})
             vals.append(torch.zeros(sz["nnz"], dtype=torch.float32, device="cuda"))
             resid.append(torch.zeros(sz["n_rows"], dtype=torch.float64, device="cuda"))
@@ -217,23 +223,50 @@ def test_batch_full_size(env):
         print(f"contexts ({time.perf_counter() - t0:.1f} s)", flush=True)
         b = vms.vms_batch_create(ctxs, stream.cuda_stream)
         vms.vms_batch_autotune(b, fields, vals, resid)
+        print(f"autotuned: {vms.vms_batch_get_config(b)}", flush=True)
         vms.vms_batch_use_graph(b, True)
         for _ in range(2):
             vms.vms_batch_assemble(b, fields, vals, resid)
         stream.synchronize()
         got = [(v.clone(), r.clone()) for v, r in zip(vals, resid)]
+        # the fixed queue order: the same outputs bit for bit
+        vms.vms_batch_set_order(b, False)
+        vms.vms_batch_assemble(b, fields, vals, resid)
+        stream.synchronize()
+        assert all(torch.equal(gv, v) and torch.equal(gr, r) for (gv, gr), v, r in zip(got, vals, resid))
+        vms.vms_batch_set_order(b, True)
         for c, f, v, r in zip(ctxs, fields, vals, resid):
             vms.vms_assemble(c, f, v, r)
         stream.synchronize()
         worst_j = worst_r = 0.0
+        bitwise = True
         for (gv, gr), v, r, idx in zip(got, vals, resid, ident):
             assert torch.equal(gv[idx], v[idx])
+            bitwise &= bool(torch.equal(gv, v) and torch.equal(gr, r))
             ej = (torch.linalg.vector_norm((gv - v).double()) /
                   (torch.linalg.vector_norm(v.double()) ** 2 - float((v[idx].double() ** 2).sum())) ** 0.5).item()
             er = (torch.linalg.vector_norm(gr - r) / torch.linalg.vector_norm(r)).item()
             worst_j, worst_r = max(worst_j, ej), max(worst_r, er)
-        print(f"batch vs single contexts: worst J {worst_j:.2e}, worst R {worst_r:.2e}", flush=True)
+        print(f"batch vs single contexts: worst J {worst_j:.2e}, worst R {worst_r:.2e}, "
+              f"bit for bit: {bitwise}", flush=True)
         assert worst_j <= 1e-6 and worst_r <= 1e-6
+        # sampled rows of the largest tree against the reference (BF16 bar)
+        tree, surf = work[big]
+        keys = oracle._mesh.independent_node_keys(tree.ax, tree.ay, tree.az, tree.level, tree.max_level)
+        assert np.array_equal(vms.vms_export(ctxs[big], vms.VMS_EXPORT_NODE_XYZ).T, oracle._mesh._decode(keys))
+        rp = vms.vms_export(ctxs[big], vms.VMS_EXPORT_ROW_PTR)
+        mk = vms.vms_export(ctxs[big], vms.VMS_EXPORT_MARKERS, tree.n)
+        ma = vms.vms_export(ctxs[big], vms.VMS_EXPORT_MASTERS, tree.n)
+        cutm = ma[mk == 2].ravel()
+        rng = np.random.default_rng(1)
+        nodes = np.unique(np.concatenate([rng.choice(keys.size, 24, replace=False),
+                                          rng.choice(cutm[cutm >= 0], 8, replace=False)]))
+        rows = SR.reference_rows(oracle, tree, surf, host_f, keys, nodes, depth=3)
+        ev, er, _ = SR.compare_rows(rows, rp, vms.vms_export(ctxs[big], vms.VMS_EXPORT_NODE_ROW_PTR),
+                                    vms.vms_export(ctxs[big], vms.VMS_EXPORT_NODE_COL), got[big][0],
+                                    got[big][1], tol=1e-5)
+        print(f"largest tree ({tree.n} octants): {nodes.size} sampled rows against the reference: "
+              f"values {ev:.2e}, residual {er:.2e}", flush=True)
         # constant state: zero residual in every tree (graph replay)
         for f in fields:
             for n, v in (("ux", 0.7), ("uy", -0.3), ("uz", 0.2), ("p", 0.0), ("ux0", 0.7), ("uy0", -0.3),

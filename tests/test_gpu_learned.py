@@ -129,3 +129,79 @@ def test_learned_labels_bit_exact_and_gain(env, oracle):
           f"exact {tt[False]*1e3:.2f} ms, learned {tt[True]*1e3:.2f} ms, gain {tt[False]/tt[True]:.2f}x")
     assert decided > 0.5
     lf.close()
+
+
+def test_learned_filter_inside_the_assembly(env, oracle):
+    """The learned filter in front of the exact test of the sub-cell quadrature
+    (vms_params.inout_mode / vms_set_inout): a surface much finer than the
+    elements (81,920 triangles, many background triangles per element). The
+    relabelled sub-cell points, the CSR values and the residual equal those of
+    the exact mode bit for bit, and the points of a sample of INTERCEPTED
+    elements equal the reference's. The relabel time is reported for several
+    thresholds on the element's background-triangle count (the network is used
+    only at or above it) and the best one is kept: where the network loses, it
+    is switched off."""
+    torch, vms = env
+    from paper_2009_00706_amd.learned import LearnedFilter
+    c = np.array([0.5, 0.5, 0.5]) + I.BODY_OFFSET
+    s = I.icosphere(6, 0.2, c)
+    tree = I.sphere_refined_octree(tuple(c), 0.2, 3, 6, 1.5)
+    lf = LearnedFilter(s, trunc=0.05, seed=0, sigma=1.0)
+    loss = lf.train(1_000_000, steps=8000, batch=8192, lr=3e-3)
+    held = I.sdf_sample_points(s, LO, HI, 2_000_000, 11, near_frac=0.9, near_dist=0.03)
+    m, _ = lf.calibrate(held, grid=(16, 16, 16))
+    print(f"{tree.n} octants, {s.n_tri} triangles: train loss {loss:.2e}, margin {m:.2e}", flush=True)
+    prm = vms.make_params(quad_depth=3)
+    ex = vms.Assembler(tree, s, prm)
+    ln = vms.Assembler(tree, s, vms.make_params(quad_depth=3, inout_mode=vms.VMS_INOUT_LEARNED))
+    vms.vms_set_inout(ln.ctx, vms.VMS_INOUT_LEARNED, lf.net, 0)
+    xyz = ex.export(vms.VMS_EXPORT_NODE_XYZ).T / float(1 << tree.max_level)
+    f = I.make_fields(xyz, 1000)
+    for a in (ex, ln):
+        a.set_fields(f)
+        a.assemble(flags=vms.VMS_RELABEL)
+    torch.cuda.synchronize()
+    vms.vms_sizes(ln.ctx)                     # raises on a kept-point count changed by the relabel
+    ge, gl = ex.export(vms.VMS_EXPORT_SUBGP), ln.export(vms.VMS_EXPORT_SUBGP)
+    for k in ("el", "key", "lvl", "xyz"):
+        assert np.array_equal(ge[k], gl[k]), k
+    assert torch.equal(ex.vals, ln.vals) and torch.equal(ex.resid, ln.resid)
+    rs = vms.vms_relabel_stats(ln.ctx)
+    decided = 1.0 - rs["exact_in_last_relabel"] / rs["candidates"]
+    print(f"{rs['candidates']} candidate points, decided by the network: {decided:.3f}", flush=True)
+    assert decided > 0.2
+    # the reference's points on a sample of INTERCEPTED elements
+    mk = ex.export(vms.VMS_EXPORT_MARKERS)
+    cut = np.nonzero(mk == 2)[0]
+    pick = np.sort(np.random.default_rng(3).choice(cut, min(40, cut.size), replace=False))
+    ref = oracle.subquad(tree, s, pick, 3)
+    sel = np.isin(gl["el"], pick)
+    for k in ("el", "key", "lvl", "xyz"):
+        assert np.array_equal(gl[k][sel], ref[k]), k
+    # relabel time by threshold on the background-triangle count
+    vms.vms_set_timing(ln.ctx, True)
+    vms.vms_set_timing(ex.ctx, True)
+
+    def relabel_ms(a):
+        for _ in range(2):
+            a.assemble(flags=vms.VMS_RELABEL)
+        t = []
+        for _ in range(5):
+            a.assemble(flags=vms.VMS_RELABEL)
+            t.append(vms.vms_last_timing(a.ctx)[0])
+        return float(np.median(t))
+
+    t_exact = relabel_ms(ex)
+    times = {}
+    for tb in (0, 16, 32, 64, 128, 1 << 30):
+        vms.vms_set_inout(ln.ctx, vms.VMS_INOUT_LEARNED, lf.net, tb)
+        times[tb] = relabel_ms(ln)
+    best = min(times, key=times.get)
+    print(f"relabel: exact {t_exact:.3f} ms; learned by threshold "
+          + ", ".join(f"{k}: {v:.3f}" for k, v in times.items())
+          + f"; best threshold {best} ({t_exact / times[best]:.2f}x)", flush=True)
+    # with the threshold above every element the learned mode is the exact one
+    assert times[1 << 30] <= 1.1 * t_exact + 0.01
+    ex.close()
+    ln.close()
+    lf.close()

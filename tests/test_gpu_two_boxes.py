@@ -6,7 +6,11 @@ the octree root in y and in z.
   entries, node coordinates and CSR indices bit-exact against the CPU
   reference; FP64 values to 1e-12, BF16 to 1e-5.
 * Full size (levels 6-11, about 10^7 octants, 198,744 triangles, more than
-  2^31 CSR nonzeros): properties that hold at any size (a constant state has
+  2^31 CSR nonzeros): node numbering equal to the reference's own numbering of
+  the whole tree; sampled node rows (random ones, rows whose CSR offsets pass
+  2^31, nodes of INTERCEPTED elements, inactive nodes) against the reference's
+  windowed assembly: columns bit-exact, values and residual within 1e-12;
+  properties that hold at any size (a constant state has
   zero residual; the CSR product equals the matrix-free Jacobian action;
   inactive rows are identity rows), BF16 within 1e-5 of FP64 over the rows of
   active nodes, and the learned filter (trained on 4M exact distances) giving
@@ -115,15 +119,43 @@ def test_two_boxes_full_size(env, oracle, monkeypatch):
     rmax = asm.resid.abs().max().item()
     print(f"constant state: max |R| {rmax:.2e}", flush=True)
     assert rmax < 1e-15
-    f = I.make_fields(phys(tree, asm.export(vms.VMS_EXPORT_NODE_XYZ).T), 1001, shortest_side=2.0)
+    # the reference numbers the nodes of the whole tree itself; fields live at
+    # its node positions
+    t1 = time.perf_counter()
+    keys = oracle._mesh.independent_node_keys(tree.ax, tree.ay, tree.az, tree.level, tree.max_level)
+    kxyz = oracle._mesh._decode(keys)
+    assert np.array_equal(asm.export(vms.VMS_EXPORT_NODE_XYZ).T, kxyz)
+    print(f"reference node numbering equal ({time.perf_counter() - t1:.1f} s)", flush=True)
+    f = I.make_fields(phys(tree, kxyz), 1001, shortest_side=2.0)
+    del kxyz
     asm.set_fields(f)
     t1 = time.perf_counter()
     asm.assemble()
     torch.cuda.synchronize()
     print(f"FP64 assembly {1e3 * (time.perf_counter() - t1):.0f} ms (first call)", flush=True)
     ref, rref = asm.vals, asm.resid.clone()
-    # identity rows: a sample of inactive nodes' rows hold a single 1 on the diagonal
+    # ---- sampled rows against the reference (selection may use the exports)
+    import sampled_rows as SR
     rng = np.random.default_rng(0)
+    act_idx = np.nonzero(active)[0]
+    high = act_idx[rp[4 * act_idx] > 2 ** 31]
+    cutm = ma[mk[mk != 1] == 2].ravel()
+    cutm = cutm[cutm >= 0]
+    nodes = np.unique(np.concatenate([rng.choice(act_idx, 24, replace=False),
+                                      rng.choice(high, 24, replace=False),
+                                      rng.choice(cutm, 10, replace=False),
+                                      rng.choice(inact, 4, replace=False)]))
+    t1 = time.perf_counter()
+    rows = SR.reference_rows(oracle, tree, surf, f, keys, nodes, depth=3,
+                             log=lambda m: print(m, flush=True))
+    nrp = asm.export(vms.VMS_EXPORT_NODE_ROW_PTR)
+    ncol = asm.export(vms.VMS_EXPORT_NODE_COL)
+    ev, er, omax = SR.compare_rows(rows, rp, nrp, ncol, ref, rref)
+    print(f"{nodes.size} sampled node rows against the reference ({time.perf_counter() - t1:.1f} s): "
+          f"values {ev:.2e}, residual {er:.2e}, CSR offsets up to {omax} (2^31 = {2 ** 31})", flush=True)
+    assert omax > 2 ** 31
+    del nrp, ncol, keys
+    # identity rows: a sample of inactive nodes' rows hold a single 1 on the diagonal
     for node in rng.choice(inact, min(64, inact.size), replace=False):
         for c in range(4):
             r = 4 * int(node) + c

@@ -1086,7 +1086,7 @@ def test_weak_bc_penalty_closed_form(oracle):
 def test_oracle_imports_nothing_from_the_product_package():
     import subprocess
     import sys
-    code = ("import sys; import oracle.core, oracle.mesh, oracle.mlp; "
+    code = ("import sys; import oracle.core, oracle.mesh, oracle.mlp, oracle.window; "
             "bad = [m for m in sys.modules if m.startswith('paper_2009_00706_amd')]; "
             "print(bad); sys.exit(1 if bad else 0)")
     root = __import__("os").path.dirname(__import__("os").path.dirname(__import__("os").path.abspath(__file__)))
@@ -1108,3 +1108,40 @@ def test_morton_key_known_values_and_round_trip(oracle):
     assert np.array_equal(M._decode(M.morton_key(p[:, 0], p[:, 1], p[:, 2])), p)
     with pytest.raises(ValueError):
         M.morton_key(1 << 21, 0, 0)
+
+
+def test_windowed_rows_equal_the_full_assembly(oracle):
+    """The windowed reference rows used at full size (sampled nodes, local
+    leaves, global numbering from the whole tree) equal the rows of the whole
+    reference assembly on a cut, hanging mesh: same columns, same values."""
+    import sampled_rows as SR
+    c = tuple(0.5 + o for o in I.BODY_OFFSET)
+    t = I.sphere_refined_octree(c, 0.25, 2, 5, 1.5)
+    s = I.icosphere(2, 0.25, c)
+    ms0 = oracle.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level)
+    mk, _, _ = oracle.markers(t, ms0, s)
+    ms = oracle.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level, active=mk != oracle.IN)
+    keys = oracle._mesh.independent_node_keys(t.ax, t.ay, t.az, t.level, t.max_level)
+    assert np.array_equal(keys, ms.node_keys)
+    sub = oracle.subquad(t, s, np.nonzero(mk == oracle.INTERCEPTED)[0], 2)
+    f = I.make_fields(ms.node_xyz_int.astype(np.float64) / float(1 << t.max_level), 4)
+    V, R = oracle.assemble(t, ms, f, mk=mk, sub=sub, depth=2)
+    rng = np.random.default_rng(1)
+    # nodes of INTERCEPTED elements, masters of hanging vertices, inactive nodes, random ones
+    cutm = ms.masters[mk == oracle.INTERCEPTED].ravel()
+    hang_el = np.nonzero((ms.C > 0).sum(2).max(1) > 1)[0]
+    hm = ms.masters[hang_el].ravel()
+    nodes = np.unique(np.concatenate([rng.choice(cutm[cutm >= 0], 6), rng.choice(hm[hm >= 0], 6),
+                                      rng.choice(np.nonzero(~ms.node_active)[0], 2),
+                                      rng.choice(ms.n_nodes, 6)]))
+    ref = SR.reference_rows(oracle, t, s, f, keys, nodes, depth=2)
+    for n in nodes:
+        rows = ref[int(n)]
+        assert rows["active"] == ms.node_active[n]
+        for c in range(4):
+            r = 4 * n + c
+            a, b = ms.row_ptr[r], ms.row_ptr[r + 1]
+            assert np.array_equal(rows["cols"][c], ms.col_idx[a:b])
+            np.testing.assert_allclose(rows["vals"][c], V[a:b], rtol=0,
+                                       atol=1e-14 * max(np.abs(V[a:b]).sum(), 1e-300))
+            assert abs(rows["resid"][c] - R[r]) <= 1e-14 * max(np.abs(R).max(), 1e-300)
