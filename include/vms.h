@@ -336,6 +336,34 @@ int inout_classify_static(const vms_surface *surf, const double *px, const doubl
                           const double *pz, int64_t n, uint8_t *labels, void *stream);
 const char *inout_static_last_error(void);
 
+/* Triquadratic (Q2, 27-node) elements on a uniform octree: the quadratic
+ * basis of the paper's matrix-assembly comparison (the table of assembly
+ * times for linear and quadratic bases on a uniform mesh) with the basis
+ * tabulated at the (bf+1)^d = 27 Gauss points (App. A). Every leaf must be on
+ * one level (no hanging nodes; VMS_EMESH otherwise), max_level <= 19, no
+ * immersed body, precision VMS_FP64 (VMS_EUNSUPPORTED otherwise). The
+ * integrand is that of vms_assemble (eq. (vms), (uprime), (pprime); taus
+ * frozen for the Jacobian) integrated with the 3-point Gauss rule per axis.
+ * Nodes: positions on the grid of half the element side (vms_q2_export
+ * VMS_EXPORT_NODE_XYZ gives these integers, physical x = origin + root_len
+ * (integer / 2^(max_level + 1))), numbered by Morton key; element node a is
+ * (a % 3, a / 3 % 3, a / 9) of its 3 x 3 x 3 node grid. CSR (VMS_EXPORT_ROW_PTR,
+ * VMS_EXPORT_COL_IDX): full 4x4 blocks for every node pair that shares an
+ * element, columns ascending, dof = 4 node + c. vms_q2_assemble: fields
+ * DEVICE arrays over the nodes, csr_vals DEVICE nnz doubles, resid DEVICE
+ * (nullable) 4 n_nodes doubles; both overwritten with sums of element records
+ * in a fixed order; enqueued on the context's stream. Set-up allocates; the
+ * assembly does not. Errors: VMS_EINVAL, VMS_EMESH, VMS_EUNSUPPORTED,
+ * VMS_ENOMEM, VMS_EHIP; message from vms_q2_last_error (null: last failed
+ * create). */
+typedef struct vms_q2 vms_q2;
+int vms_q2_create(vms_q2 **out, const vms_octree *tree, const vms_params *prm, void *stream);
+int vms_q2_sizes(vms_q2 *q, int64_t *n_nodes, int64_t *n_rows, int64_t *nnz);
+int vms_q2_export(vms_q2 *q, uint32_t what, void *dst);
+int vms_q2_assemble(vms_q2 *q, const vms_fields *fields, double *csr_vals, double *resid);
+const char *vms_q2_last_error(vms_q2 *q);
+void vms_q2_destroy(vms_q2 *q);
+
 /* Host-only mesh derivation (no device involved): the node numbering,
  * hanging constraints and CSR pattern that vms_create derives, for checks on
  * machines without a GPU. markers (HOST, nullable) excludes IN elements

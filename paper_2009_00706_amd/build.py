@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvms.so")
 SOURCES = ["api.cpp", "mesh.cpp", "inout.hip", "assemble2.hip", "util.hip", "mlp.hip", "surface.hip",
-           "krylov.hip", "static_scratch.hip"]
+           "krylov.hip", "static_scratch.hip", "q2.cpp", "q2.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

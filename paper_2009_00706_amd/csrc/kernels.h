@@ -161,6 +161,23 @@ void launch_gather_f32(hipStream_t s, const float *em, const int64_t *cb_off, co
                        const int64_t *vbase, const int32_t *vstride, int64_t nb, float *vals);
 void launch_fill_f64(hipStream_t s, double *p, int64_t n, double v);
 void launch_fill_f32(hipStream_t s, float *p, int64_t n, float v);
+// Triquadratic (27-node) elements of a uniform octree, FP64: element node
+// lists, fields, the (uniform) element side and the parameters as in AsmArgs;
+// outputs the element-matrix records ([E][27 x 27 node pairs][16]) and the
+// residual records ([E][27][4]).
+struct Q2Args {
+    int64_t n_el;
+    const int32_t *el_node;   // [E][27]
+    const double *f[7];       // ux uy uz p ux0 uy0 uz0
+    double h;
+    double rho, mu, theta, idt, irho, tau_a, tau_b;
+    double *em;
+    double *rrec;
+};
+void launch_q2(hipStream_t s, const Q2Args &a);
+void launch_q2_res_gather(hipStream_t s, const double *rrec, const int64_t *roff, const int32_t *rlist,
+                          int64_t n_nodes, double *out);
+
 // One tree's summation lists and outputs, for the batched gathers.
 struct GatherTab {
     const void *em;           // element-matrix records (double or float)

@@ -34,6 +34,8 @@ EXPORTED = ["vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply"
             "inout_prepare", "inout_classify_prepared", "inout_release", "vms_stats",
             "inout_classify_static", "inout_static_last_error", "inout_reserve",
             "vms_set_inout", "vms_relabel_stats", "vms_batch_set_order",
+            "vms_q2_create", "vms_q2_sizes", "vms_q2_export", "vms_q2_assemble", "vms_q2_last_error",
+            "vms_q2_destroy",
             "vms_mesh_create", "vms_mesh_sizes", "vms_mesh_export", "vms_mesh_destroy",
             "vms_set_timing", "vms_last_timing", "vms_mlp_create", "vms_mlp_get_params",
             "vms_mlp_set_margin", "vms_mlp_set_margin_grid", "vms_mlp_grad", "vms_mlp_train", "vms_mlp_adam_step",
@@ -101,6 +103,18 @@ def lib():
         L.inout_classify_prepared.argtypes = [p, p, p, p, i64, p, u32, p]
         L.inout_release.argtypes = [p]
         L.inout_release.restype = None
+        L.vms_q2_create.argtypes = [C.POINTER(p), C.POINTER(Octree), C.POINTER(Params), p]
+        L.vms_q2_create.restype = C.c_int
+        L.vms_q2_sizes.argtypes = [p, p, p, p]
+        L.vms_q2_sizes.restype = C.c_int
+        L.vms_q2_export.argtypes = [p, u32, p]
+        L.vms_q2_export.restype = C.c_int
+        L.vms_q2_assemble.argtypes = [p, C.POINTER(Fields), p, p]
+        L.vms_q2_assemble.restype = C.c_int
+        L.vms_q2_last_error.argtypes = [p]
+        L.vms_q2_last_error.restype = C.c_char_p
+        L.vms_q2_destroy.argtypes = [p]
+        L.vms_q2_destroy.restype = None
         L.vms_set_inout.argtypes = [p, u32, p, i32]
         L.vms_set_inout.restype = C.c_int
         L.vms_relabel_stats.argtypes = [p, p]
@@ -263,6 +277,49 @@ def vms_stats(ctx):
     _check(lib().vms_stats(ctx, v), ctx)
     return {"n_out": v[0], "n_intercepted": v[1], "n_labelled": v[2], "n_degenerate": v[3],
             "n_hanging": v[4], "n_subgp": v[5], "n_surfgp": v[6]}
+
+
+def _q2_check(rc, q):
+    if rc != VMS_OK:
+        raise VmsError(rc, lib().vms_q2_last_error(q).decode())
+
+
+def vms_q2_create(tree, params=None, stream=None):
+    """Triquadratic elements of a uniform octree (no body); returns the handle."""
+    o = _octree(tree)
+    prm = params if params is not None else make_params()
+    h = C.c_void_p()
+    _q2_check(lib().vms_q2_create(C.byref(h), C.byref(o), C.byref(prm), _stream(stream)), None)
+    return h
+
+
+def vms_q2_sizes(q):
+    v = [C.c_int64() for _ in range(3)]
+    _q2_check(lib().vms_q2_sizes(q, *(C.byref(x) for x in v)), q)
+    return {"n_nodes": v[0].value, "n_rows": v[1].value, "nnz": v[2].value}
+
+
+def vms_q2_export(q, what):
+    sz = vms_q2_sizes(q)
+    if what == VMS_EXPORT_NODE_XYZ:
+        out = np.zeros((3, sz["n_nodes"]), np.int32)
+    elif what == VMS_EXPORT_ROW_PTR:
+        out = np.zeros(sz["n_rows"] + 1, np.int64)
+    elif what == VMS_EXPORT_COL_IDX:
+        out = np.zeros(sz["nnz"], np.int32)
+    else:
+        raise ValueError("unknown selector")
+    _q2_check(lib().vms_q2_export(q, what, out.ctypes.data), q)
+    return out
+
+
+def vms_q2_assemble(q, fields, vals, resid=None):
+    fs = _fields(fields)
+    _q2_check(lib().vms_q2_assemble(q, C.byref(fs), _ptr(vals), _ptr(resid) if resid is not None else None), q)
+
+
+def vms_q2_destroy(q):
+    lib().vms_q2_destroy(q)
 
 
 def vms_set_inout(ctx, mode, mlp=None, min_bt=0):
