@@ -46,13 +46,21 @@ PEAK_HBM_GBS = 8000.0       # HBM3E
 BATCH_SEED = 1003           # seed of the 64-tree batch workload
 
 
+_T0 = time.perf_counter()
+
+
+def log(msg):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="twoboxes",
-                    choices=["sphere", "uniform16", "precision", "twoboxes", "batch64"])
+                    choices=["sphere", "uniform16", "precision", "twoboxes", "batch64", "q2uniform16"])
     ap.add_argument("--precision", default=None, choices=["fp64", "bf16", "fp16"])
     ap.add_argument("--n-trees", type=int, default=64)
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16/FP16 comparison")
@@ -116,7 +124,7 @@ def node_xyz(vms, ctx, tree):
 
 
 # the sources of the element kernel: the recorded traffic holds for this text only
-KERNEL_SOURCES = ("assemble2.hip", "kernels.h", "geom.h")
+KERNEL_SOURCES = ("assemble2.hip", "kernels.h", "geom.h", "vms_point.h")
 
 
 def traffic_for(path, workload, precision):
@@ -593,10 +601,13 @@ def roofline(k_ms, n_pts, peak, traffic, kname):
 def main_single(args):
     from paper_2009_00706_amd import inputs as I
     tree, surf, cfg = workload(args.workload)
+    log(f"workload {args.workload}: {tree.n} octants")
     # the CPU baseline forks worker processes: it runs before the GPU is touched
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(tree, surf, args.cpu_sample, cfg.get("shortest_side", 1.0), args.cpu_workers)
+        log(f"cpu baseline: {cpu['value']:.1f} elements/s on {cpu['cores']} cores "
+            f"({cpu['single_core_value']:.1f} on one)")
 
     import torch
     from paper_2009_00706_amd import vms
@@ -609,8 +620,10 @@ def main_single(args):
                       1001, cfg.get("shortest_side", 1.0))
     del xyz
     flags = vms.VMS_RELABEL if surf is not None else 0
+    log("fields ready; timing the headline form")
     r = run_single(torch, vms, tree, surf, f, prec, args.steps, args.warmup, flags)
     st, avg = r["stats"], r["stage"]
+    log(f"{pname}: {r['ms_step']:.2f} ms per step")
     out = {
         "metric": "VMS elements assembled/s + in-out tests/s; learned+mixed vs FP64 at err<=1e-5",
         "value": r["value"],
@@ -638,6 +651,7 @@ def main_single(args):
         forms, keep = {}, {}
         for name, p in (("bf16", vms.VMS_MIXED_BF16), ("fp16", vms.VMS_MIXED_FP16)):
             m = run_single(torch, vms, tree, surf, f, p, args.steps, args.warmup, flags)
+            log(f"{name}: {m['ms_step']:.2f} ms per step")
             # matrix error over the rows of active nodes: the identity rows of
             # inactive nodes are exact in every form and would dominate the norm
             forms[name] = dict({"value": m["value"], "ms_per_step": m["ms_step"],
@@ -656,15 +670,19 @@ def main_single(args):
             if k != best:
                 del keep[k]
         if surf is not None and not args.no_learned:
+            log(f"learned + {best}: training the filter")
             out["learned_mixed"] = learned_mixed(torch, vms, tree, surf, f, cfg, args, flags, r,
                                                  best, keep[best])
         keep.clear()
     del r["vals"]
     torch.cuda.empty_cache()
     if not args.no_jv:
+        log("Jacobian products")
         out["jacobian_action"] = jacobian_products(torch, vms, tree, surf, f, prec)
+        log("Newton step")
         out["newton_step"] = newton_step(torch, vms, tree, surf, f, prec)
     if surf is not None and not args.no_jv:
+        log("weak boundary terms")
         out["weak_bc"] = weak_bc_cost(torch, vms, tree, surf, f, prec)
         if prec == vms.VMS_FP64 and args.cost_model != "none":
             out["cost_model"] = cost_model(torch, vms, st, out["weak_bc"], args.cost_model)
@@ -708,6 +726,7 @@ def main_batch(args):
     t0 = time.perf_counter()
     work = I.batch_workload(args.n_trees, BATCH_SEED, workers=min(16, os.cpu_count() or 1))
     gen_s = time.perf_counter() - t0
+    log(f"{len(work)} trees generated")
     cpu = None
     if not args.no_cpu_baseline:   # forks: before the GPU is touched
         big = max(range(len(work)), key=lambda k: work[k][0].n)
@@ -737,15 +756,21 @@ def main_batch(args):
             n_sub += st["n_subgp"]
             n_oct += tree.n
         setup_s = time.perf_counter() - t1
+        log("contexts ready; autotuning")
         b = vms.vms_batch_create(ctxs, stream.cuda_stream)
         tune_ms = vms.vms_batch_autotune(b, fields, vals, resid)
         cfgb = vms.vms_batch_get_config(b)
-        # kernel time of the persistent launch (eager), for the roofline
-        kms = []
-        for _ in range(3):
-            vms.vms_batch_assemble(b, fields, vals, resid)
-            kms.append(vms.vms_batch_last_timing(b))
-        kms = np.array(kms).mean(0)
+        # kernel time of the persistent launch (eager), for the roofline; the
+        # same with the fixed queue order (sub-cell items first, one each)
+        order_ms = {}
+        for by_w in (False, True):
+            vms.vms_batch_set_order(b, by_w)
+            kms = []
+            for _ in range(4):
+                vms.vms_batch_assemble(b, fields, vals, resid)
+                kms.append(vms.vms_batch_last_timing(b))
+            kms = np.array(kms[1:]).mean(0)
+            order_ms["wpart_weighted" if by_w else "fixed"] = float(kms[1])
         vms.vms_batch_use_graph(b, True)
         for _ in range(args.warmup):
             vms.vms_batch_assemble(b, fields, vals, resid)
@@ -779,6 +804,10 @@ def main_batch(args):
                    "precision": pname, "autotuned": cfgb, "autotune_best_ms": tune_ms},
         "stage_ms": {"args": float(kms[0]), "persistent_assembly": float(kms[1]),
                      "csr_gather": float(kms[2])},
+        "queue_order_persistent_ms": order_ms,
+        "queue_note": ("units of about `tile` eq. (Wpart) element weights, heaviest first, against the "
+                       "fixed order (every sub-cell item a unit of its own, all first, then runs of "
+                       "`tile` OUT elements); same tile and workgroups per CU"),
         "setup_s": {"generate": gen_s, "contexts": setup_s},
         "roofline": roofline(float(kms[1]), n_pts,
                              PEAK_FP64_TFLOPS if prec == vms.VMS_FP64 else PEAK_MFMA_16_TFLOPS,
@@ -789,6 +818,79 @@ def main_batch(args):
         out["cpu_baseline"] = cpu
     for c in ctxs:
         vms.vms_destroy(c)
+    print(json.dumps(out))
+
+
+# algorithmic work per Q2 quadrature point: the dense contraction with B 4 x 27
+# and D 16 x 16: (16 x 4 x 27 x 4 + 16 x 27 x 27 x 4) multiply-adds x 2
+FLOP_PER_POINT_Q2 = 2 * (16 * 4 * 27 * 4 + 16 * 27 * 27 * 4)
+
+
+def main_q2(args):
+    """Triquadratic elements on the uniform 16^3 cube (the paper's quadratic
+    row of its matrix-assembly table): 27 Gauss points per element."""
+    from oracle import core as O
+    from oracle import q2 as Q
+    from paper_2009_00706_amd import inputs as I
+    tree = I.uniform_octree(4)
+    m = Q.derive_q2_mesh(tree)
+    f = I.make_fields(Q.node_xyz(tree, m), 1000)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import ctypes as C
+        n = min(tree.n, 1500 if args.cpu_sample >= 1500 else args.cpu_sample)
+        V = np.zeros(m.nnz)
+        R = np.zeros(4 * m.n_nodes)
+        xi, w = Q.points()
+        c = O._c
+        el = c(m.el_node[:n], np.int32)
+        h = np.full(n, m.h)
+        fl = {k: c(f[k], np.float64) for k in f}
+        prm = O.params()
+        t0 = time.perf_counter()
+        Q._lib().or_q2_assemble(C.byref(prm), n, O._p(el), O._p(h), 27, O._p(c(xi, np.float64)),
+                                O._p(c(w, np.float64)), *(O._p(fl[k]) for k in
+                                                          ("ux", "uy", "uz", "p", "ux0", "uy0", "uz0")),
+                                O._p(m.row_ptr), O._p(m.col_idx), O._p(V), O._p(R))
+        dt = time.perf_counter() - t0
+        cpu = {"value": n / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+               "sample": f"the first {n} of the {tree.n} elements, residual and complex-step Jacobian, "
+                         f"{dt:.1f} s in one process"}
+        log(f"cpu baseline {n / dt:.1f} elements/s")
+    import torch
+    from paper_2009_00706_amd import vms
+    q = vms.vms_q2_create(tree)
+    sz = vms.vms_q2_sizes(q)
+    fd = {k: torch.as_tensor(f[k], device="cuda") for k in f}
+    vals = torch.zeros(sz["nnz"], dtype=torch.float64, device="cuda")
+    res = torch.zeros(sz["n_rows"], dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        vms.vms_q2_assemble(q, fd, vals, res)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        vms.vms_q2_assemble(q, fd, vals, res)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kt = np.array([(vms.vms_q2_assemble(q, fd, vals, res), vms.vms_q2_last_timing(q))[1]
+                   for _ in range(5)]).mean(0)
+    vms.vms_q2_destroy(q)
+    ms = 1e3 * el / args.steps
+    out = {"metric": "VMS elements assembled/s + in-out tests/s; learned+mixed vs FP64 at err<=1e-5",
+           "value": tree.n * args.steps / el, "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "triquadratic (27-node) elements on the uniform 16^3 unit cube, 27 Gauss "
+                                  "points per element, no body", "octants": tree.n,
+                      "n_nodes": sz["n_nodes"], "nnz": sz["nnz"]},
+           "stage_ms": {"element_kernel": float(kt[0]), "gathers": float(kt[1])},
+           "roofline": {"bound": "alu", "achieved": FLOP_PER_POINT_Q2 * 27 * tree.n / (kt[0] * 1e-3) / 1e12,
+                        "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                        "frac": FLOP_PER_POINT_Q2 * 27 * tree.n / (kt[0] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                        "traffic": None, "kernel": "k_q2", "kernel_ms": float(kt[0]),
+                        "points_per_launch": 27 * tree.n, "flop_per_point": FLOP_PER_POINT_Q2}}
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 
@@ -803,6 +905,8 @@ def main():
         return
     if args.workload == "batch64":
         main_batch(args)
+    elif args.workload == "q2uniform16":
+        main_q2(args)
     else:
         main_single(args)
 

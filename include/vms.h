@@ -361,6 +361,9 @@ int vms_q2_create(vms_q2 **out, const vms_octree *tree, const vms_params *prm, v
 int vms_q2_sizes(vms_q2 *q, int64_t *n_nodes, int64_t *n_rows, int64_t *nnz);
 int vms_q2_export(vms_q2 *q, uint32_t what, void *dst);
 int vms_q2_assemble(vms_q2 *q, const vms_fields *fields, double *csr_vals, double *resid);
+/* HOST ms[2]: element kernel and gathers of the last vms_q2_assemble
+ * (synchronises on it; VMS_EINVAL if there was none). */
+int vms_q2_last_timing(vms_q2 *q, float *ms);
 const char *vms_q2_last_error(vms_q2 *q);
 void vms_q2_destroy(vms_q2 *q);
 

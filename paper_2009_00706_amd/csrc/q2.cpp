@@ -34,7 +34,11 @@ struct vms_q2 {
     int32_t *d_el_node = nullptr, *d_contrib = nullptr, *d_vstride = nullptr, *d_rlist = nullptr;
     int64_t *d_cb_off = nullptr, *d_vbase = nullptr, *d_roff = nullptr;
     double *d_em = nullptr, *d_rrec = nullptr;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // element kernel, gathers
+    bool timed = false;
     ~vms_q2() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
         for (void *p : dev) (void)hipFree(p);
     }
     template <typename T>
@@ -188,7 +192,21 @@ int vms_q2_create(vms_q2 **out, const vms_octree *tree, const vms_params *prm, v
         delete q;
         return qfail(nullptr, VMS_ENOMEM, "device allocation failed (Q2 set-up)");
     }
+    for (hipEvent_t &ev : q->ev)
+        if (hipEventCreate(&ev) != hipSuccess) {
+            delete q;
+            return qfail(nullptr, VMS_EHIP, "event creation failed");
+        }
     *out = q;
+    return VMS_OK;
+}
+
+int vms_q2_last_timing(vms_q2 *q, float *ms) {
+    if (!q || !ms) return qfail(q, VMS_EINVAL, "null argument");
+    if (!q->timed) return qfail(q, VMS_EINVAL, "no assembly to time");
+    if (hipEventSynchronize(q->ev[2]) != hipSuccess || hipEventElapsedTime(&ms[0], q->ev[0], q->ev[1]) ||
+        hipEventElapsedTime(&ms[1], q->ev[1], q->ev[2]))
+        return qfail(q, VMS_EHIP, "event timing failed");
     return VMS_OK;
 }
 
@@ -255,10 +273,14 @@ int vms_q2_assemble(vms_q2 *q, const vms_fields *f, double *csr_vals, double *re
     a.tau_b = 3.0 * P.c_i * nu * nu;
     a.em = q->d_em;
     a.rrec = q->d_rrec;
+    (void)hipEventRecord(q->ev[0], q->stream);
     vmsk::launch_q2(q->stream, a);
+    (void)hipEventRecord(q->ev[1], q->stream);
     vmsk::launch_gather_f64(q->stream, q->d_em, q->d_cb_off, q->d_contrib, q->d_vbase, q->d_vstride,
                             q->n_blocks, csr_vals);
     if (resid) vmsk::launch_q2_res_gather(q->stream, q->d_rrec, q->d_roff, q->d_rlist, q->n_nodes, resid);
+    (void)hipEventRecord(q->ev[2], q->stream);
+    q->timed = true;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return qfail(q, VMS_EHIP, std::string("launch failed: ") + hipGetErrorString(e));
     return VMS_OK;

@@ -35,6 +35,7 @@ EXPORTED = ["vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply"
             "inout_classify_static", "inout_static_last_error", "inout_reserve",
             "vms_set_inout", "vms_relabel_stats", "vms_batch_set_order",
             "vms_q2_create", "vms_q2_sizes", "vms_q2_export", "vms_q2_assemble", "vms_q2_last_error",
+            "vms_q2_last_timing",
             "vms_q2_destroy",
             "vms_mesh_create", "vms_mesh_sizes", "vms_mesh_export", "vms_mesh_destroy",
             "vms_set_timing", "vms_last_timing", "vms_mlp_create", "vms_mlp_get_params",
@@ -111,6 +112,8 @@ def lib():
         L.vms_q2_export.restype = C.c_int
         L.vms_q2_assemble.argtypes = [p, C.POINTER(Fields), p, p]
         L.vms_q2_assemble.restype = C.c_int
+        L.vms_q2_last_timing.argtypes = [p, p]
+        L.vms_q2_last_timing.restype = C.c_int
         L.vms_q2_last_error.argtypes = [p]
         L.vms_q2_last_error.restype = C.c_char_p
         L.vms_q2_destroy.argtypes = [p]
@@ -316,6 +319,12 @@ def vms_q2_export(q, what):
 def vms_q2_assemble(q, fields, vals, resid=None):
     fs = _fields(fields)
     _q2_check(lib().vms_q2_assemble(q, C.byref(fs), _ptr(vals), _ptr(resid) if resid is not None else None), q)
+
+
+def vms_q2_last_timing(q):
+    v = (C.c_float * 2)()
+    _q2_check(lib().vms_q2_last_timing(q, v), q)
+    return list(v)
 
 
 def vms_q2_destroy(q):

@@ -183,8 +183,8 @@ def test_batch_tree_against_reference(env, oracle):
 def test_batch_full_size(env, oracle):
     """The 64-tree workload at full size (log-uniform 1e4..5e5 octants, seed
     1003), BF16x3, autotuned and replayed as a graph (the benchmark's launch):
-    every tree's values and residual equal its single-context assembly (values
-    over the rows of active nodes, identity rows exactly; norms on the device);
+    every tree's values and residual equal its single-context assembly bit for
+    bit;
     the fixed queue order gives the same outputs bit for bit as the eq. (Wpart)
     order; sampled rows of the largest tree match the CPU reference within the
     mixed form's bar; a constant state gives a zero residual in every tree."""
@@ -249,7 +249,8 @@ def test_batch_full_size(env, oracle):
             worst_j, worst_r = max(worst_j, ej), max(worst_r, er)
         print(f"batch vs single contexts: worst J {worst_j:.2e}, worst R {worst_r:.2e}, "
               f"bit for bit: {bitwise}", flush=True)
-        assert worst_j <= 1e-6 and worst_r <= 1e-6
+        # the same per-item arithmetic and the same summation order: equal bits
+        assert bitwise
         # sampled rows of the largest tree against the reference (BF16 bar)
         tree, surf = work[big]
         keys = oracle._mesh.independent_node_keys(tree.ax, tree.ay, tree.az, tree.level, tree.max_level)
