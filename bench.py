@@ -265,6 +265,20 @@ def run_single(torch, vms, tree, surf, f, prec, steps, warmup, flags, params=Non
         stage[k] = vms.vms_last_timing(asm.ctx)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # the same step in order (every stage alone on the context stream): the
+    # isolated stage times and what the overlapped schedule gains
+    vms.vms_set_overlap(asm.ctx, False)
+    n_io = min(steps, 5)
+    asm.assemble(flags=flags)
+    torch.cuda.synchronize()
+    stage_io = np.zeros((n_io, 5))
+    t2 = time.perf_counter()
+    for k in range(n_io):
+        asm.assemble(flags=flags)
+        stage_io[k] = vms.vms_last_timing(asm.ctx)
+    torch.cuda.synchronize()
+    ms_io = 1e3 * (time.perf_counter() - t2) / n_io
+    vms.vms_set_overlap(asm.ctx, True)
     # steady state (labels cached), for context
     t1 = time.perf_counter()
     for _ in range(steps):
@@ -275,20 +289,39 @@ def run_single(torch, vms, tree, surf, f, prec, steps, warmup, flags, params=Non
     torch.cuda.synchronize()
     relabel = vms.vms_relabel_stats(asm.ctx) if surf is not None else None
     vms.vms_sizes(asm.ctx)   # raises if a relabel changed an element's kept-point count
-    dev = stage.sum(1)  # device time of each timed step (sum of its stages)
+    # device time of each timed step: the stages on the context stream (the
+    # relabel and INTERCEPTED stages of an overlapped step ran beside the last)
+    dev = stage[:, 1] + stage[:, 2] + stage[:, 4] if overlapped(st) else stage.sum(1)
     out = {"elapsed": elapsed, "value": n_active * steps / elapsed, "ms_step": 1e3 * elapsed / steps,
            "step_device_ms": {"p10": float(np.percentile(dev, 10)), "p50": float(np.median(dev)),
                               "p90": float(np.percentile(dev, 90))},
-           "stage": stage.mean(0), "steady": steady, "setup_s": setup_s, "stats": st,
+           "stage": stage.mean(0), "stage_in_order": stage_io.mean(0), "ms_step_in_order": ms_io,
+           "overlapped": overlapped(st), "steady": steady, "setup_s": setup_s, "stats": st,
            "sizes": asm.sizes, "n_active": n_active, "relabel": relabel, "extra": extra,
            "vals": asm.vals, "resid": asm.resid, "inactive": inactive_entries(torch, vms, asm)}
     asm.close()
     return out
 
 
-def stage_dict(avg):
+def overlapped(st):
+    """Whether vms_assemble (matrix, overlap on) takes the overlapped schedule."""
+    return st["n_intercepted"] > 0 or st.get("n_surfgp", 0) > 0
+
+
+def stage_dict(avg, over=False):
+    if over:
+        return {"relabel_beside": float(avg[0]), "args": float(avg[1]), "out_elements": float(avg[2]),
+                "intercepted_elements_beside": float(avg[3]), "after_out_elements": float(avg[4]),
+                "note": "overlapped step: relabel and INTERCEPTED items on the second stream, beside "
+                        "the span after the OUT kernel (gather of the other blocks, then the late "
+                        "blocks and the residual); device step = args + OUT + that span"}
     return {"relabel": float(avg[0]), "args": float(avg[1]), "out_elements": float(avg[2]),
             "intercepted_elements": float(avg[3]), "csr_gather": float(avg[4])}
+
+
+def schedule_info(m):
+    return {"stage_ms_in_order": stage_dict(m["stage_in_order"]), "ms_per_step_in_order": m["ms_step_in_order"],
+            "overlap_speedup": m["ms_step_in_order"] / m["ms_step"]}
 
 
 def train_filter(torch, surf, n_train):
@@ -314,8 +347,9 @@ def learned_threshold(torch, vms, asm, lf, thresholds=(0, 16, 32, 64, 128, 1 << 
     """Relabel time of the learned mode for each threshold on the element's
     background-triangle count (the network is used at or above it), and of the
     exact mode; the fastest setting is kept (the network is switched off where
-    it loses)."""
+    it loses). The relabel is timed alone (in-order schedule)."""
     vms.vms_set_timing(asm.ctx, True)
+    vms.vms_set_overlap(asm.ctx, False)
 
     def relabel_ms():
         for _ in range(2):
@@ -337,6 +371,7 @@ def learned_threshold(torch, vms, asm, lf, thresholds=(0, 16, 32, 64, 128, 1 << 
         times[tb]["decided_by_network"] = 1.0 - rs["exact_in_last_relabel"] / max(rs["candidates"], 1)
     best = min(times, key=lambda k: times[k]["relabel_ms"])
     vms.vms_set_inout(asm.ctx, vms.VMS_INOUT_LEARNED, lf.net, best)
+    vms.vms_set_overlap(asm.ctx, True)
     return {"exact_relabel_ms": t_exact, "by_min_bt": {str(k): v for k, v in times.items()},
             "min_bt": best, "gain_vs_exact_relabel": t_exact / times[best]["relabel_ms"]}
 
@@ -504,6 +539,7 @@ def weak_bc_cost(torch, vms, tree, surf, f, prec, reps=20):
     asm = vms.Assembler(tree, surf, vms.make_params(quad_depth=3, precision=prec))
     asm.set_fields(f)
     vms.vms_set_timing(asm.ctx, True)
+    vms.vms_set_overlap(asm.ctx, False)   # isolated stage times
 
     def timed():
         for _ in range(3):
@@ -528,7 +564,7 @@ def weak_bc_cost(torch, vms, tree, surf, f, prec, reps=20):
     return {"surface_points": int(n_s), "assembly_ms_without": t0, "assembly_ms_with": t1,
             "surface_kernel_ms": float(s1[3] - s0[3]), "stage_ms_without": s0.tolist(),
             "stage_ms_with": s1.tolist(),
-            "note": "steady-state vms_assemble (no relabel); the surface kernel runs after the "
+            "note": "steady-state vms_assemble (no relabel, in-order schedule); the surface kernel runs after the "
                     "INTERCEPTED items, its time is the difference of that stage; c_b = 4, g = 0"}
 
 
@@ -551,6 +587,7 @@ def cost_model(torch, vms, st, wb, workload_name):
     asm.set_fields(I.make_fields(mh_xyz * tree.root_len + np.asarray(tree.origin), 1001))
     asm.set_weak_bc(True, 4.0, (0.0, 0.0, 0.0))
     vms.vms_set_timing(asm.ctx, True)
+    vms.vms_set_overlap(asm.ctx, False)   # isolated kernel times
     for _ in range(3):
         asm.assemble()
     stg = np.zeros(5)
@@ -575,19 +612,28 @@ def cost_model(torch, vms, st, wb, workload_name):
 PEAK_MFMA_16_TFLOPS = 2500.0  # dense BF16 / FP16 matrix cores
 
 
-def roofline_of(avg, st, prec, vms, traffic):
-    """Roofline of the dominant assembly kernel (the one with the larger time):
-    FP64 against the FP64 peak; the mixed forms against the dense BF16/FP16
-    matrix-core peak of their contraction, with the FP32 vector figure beside
-    it (their per-point work and operand splits run on the FP32 VALU)."""
-    if avg[3] > avg[2]:
-        k_ms, n_pts, kname = avg[3], st["n_subgp"], "k_asm2 (INTERCEPTED elements, sub-cell points)"
+def roofline_of(m, prec, vms, traffic):
+    """Roofline of the dominant assembly kernel (the one with the larger
+    isolated time): FP64 against the FP64 peak; the mixed forms against the
+    dense BF16/FP16 matrix-core peak of their contraction, with the FP32 vector
+    figure beside it (their per-point work and operand splits run on the FP32
+    VALU). The OUT kernel runs alone on the context stream in either schedule:
+    its time is that of the timed steps. The INTERCEPTED kernel of an
+    overlapped step shares the GPU with the gather: its time is that of the
+    in-order steps."""
+    avg, io, st = m["stage"], m["stage_in_order"], m["stats"]
+    if io[3] > io[2]:
+        k_ms, n_pts, kname = io[3], st["n_subgp"], "k_asm2 (INTERCEPTED elements, sub-cell points)"
+        sched = "in-order steps"
     else:
         k_ms, n_pts, kname = avg[2], 8 * st["n_out"], "k_asm2 (OUT elements)"
+        sched = "timed steps"
     if prec == vms.VMS_FP64:
-        return roofline(k_ms, n_pts, PEAK_FP64_TFLOPS, traffic, kname)
-    rf = roofline(k_ms, n_pts, PEAK_MFMA_16_TFLOPS, traffic, kname)
-    rf["frac_of_fp32_vector_peak"] = rf["achieved"] / PEAK_FP32_TFLOPS
+        rf = roofline(k_ms, n_pts, PEAK_FP64_TFLOPS, traffic, kname)
+    else:
+        rf = roofline(k_ms, n_pts, PEAK_MFMA_16_TFLOPS, traffic, kname)
+        rf["frac_of_fp32_vector_peak"] = rf["achieved"] / PEAK_FP32_TFLOPS
+    rf["kernel_ms_from"] = sched
     return rf
 
 
@@ -640,12 +686,14 @@ def main_single(args):
         "config": dict(cfg, n_nodes=r["sizes"]["n_nodes"], nnz=r["sizes"]["nnz"],
                        n_out=st["n_out"], n_intercepted=st["n_intercepted"],
                        n_subgp=st["n_subgp"], precision=pname),
-        "inout_tests_per_s": (st["n_labelled"] / (avg[0] * 1e-3)) if avg[0] > 0 else None,
+        "inout_tests_per_s": (st["n_labelled"] / (r["stage_in_order"][0] * 1e-3))
+                             if r["stage_in_order"][0] > 0 else None,
         "steady_state_elements_per_s": r["steady"],
         "step_device_ms": r["step_device_ms"],
-        "stage_ms": stage_dict(avg),
+        "stage_ms": stage_dict(avg, r["overlapped"]),
+        **schedule_info(r),
         "setup_s": r["setup_s"],
-        "roofline": roofline_of(avg, st, prec, vms, traffic_for(args.traffic, args.workload, pname)),
+        "roofline": roofline_of(r, prec, vms, traffic_for(args.traffic, args.workload, pname)),
     }
     if prec == vms.VMS_FP64 and not args.no_forms:
         forms, keep = {}, {}
@@ -657,9 +705,9 @@ def main_single(args):
             forms[name] = dict({"value": m["value"], "ms_per_step": m["ms_step"],
                                 "speedup_vs_fp64": m["value"] / r["value"]},
                                **form_errors(torch, m, r))
-            forms[name]["stage_ms"] = stage_dict(m["stage"])
-            forms[name]["roofline"] = roofline_of(m["stage"], m["stats"], p, vms,
-                                                  traffic_for(args.traffic, args.workload, name))
+            forms[name]["stage_ms"] = stage_dict(m["stage"], m["overlapped"])
+            forms[name].update(schedule_info(m))
+            forms[name]["roofline"] = roofline_of(m, p, vms, traffic_for(args.traffic, args.workload, name))
             keep[name] = (m["vals"], m["resid"], p)
             del m
         out["forms"] = forms
@@ -717,7 +765,8 @@ def learned_mixed(torch, vms, tree, surf, f, cfg, args, flags, r, best, ref):
                  "speedup_vs_fp64": m["value"] / r["value"],
                  "outputs_equal_to_the_exact_labels_form": same,
                  "decided_by_network": 1.0 - rs["exact_in_last_relabel"] / max(rs["candidates"], 1),
-                 "stage_ms": stage_dict(m["stage"]), "threshold": chosen, "filter": info}, **err)
+                 "stage_ms": stage_dict(m["stage"], m["overlapped"]), **schedule_info(m),
+                 "threshold": chosen, "filter": info}, **err)
 
 
 def main_batch(args):

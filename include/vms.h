@@ -382,11 +382,30 @@ void vms_mesh_destroy(vms_mesh *h);
  * default). vms_last_timing synchronises on the last recorded event and
  * writes HOST ms[5]: relabelling (sub-cell quadrature and in-out tests),
  * host set-up of the kernel arguments (no kernel), OUT-element assembly
- * kernel, INTERCEPTED-element assembly kernel, summation of the element
- * records into the CSR values (with identity rows) and the residual, of the
- * last vms_assemble / vms_apply. */
+ * kernel, INTERCEPTED-element assembly kernel (and surface terms), summation
+ * of the element records into the CSR values (with identity rows) and the
+ * residual, of the last vms_assemble / vms_apply. After an overlapped
+ * vms_assemble (vms_set_overlap) ms[0] and ms[3] are measured on the second
+ * stream and ran beside ms[4], which spans from the end of the OUT elements to
+ * the end of the call: the device time of the call is ms[1] + ms[2] + ms[4]
+ * there, the sum of all five otherwise. */
 int vms_set_timing(vms_ctx *ctx, int on);
 int vms_last_timing(vms_ctx *ctx, float *ms);
+
+/* Schedule of vms_assemble (on = 1, the default, or 0). The element records
+ * of OUT elements are complete once their kernel ends, and most CSR blocks
+ * (those of nodes away from the surface) receive no other records. With
+ * overlap on, a call that assembles the matrix and has INTERCEPTED items (or
+ * weak boundary terms) runs the relabel, the INTERCEPTED items and the surface
+ * terms on a second stream that the context owns (created on first use, on the
+ * current device, default priority), started by an event after the OUT
+ * kernel, while the context stream sums the blocks without late records; the
+ * context stream then waits for the second stream and sums the late blocks.
+ * All of the call's work is ordered before later work on the context stream,
+ * and the outputs are bit for bit those of the in-order schedule (same
+ * records, same per-block summation order). Off: every stage in order on the
+ * context stream (isolated stage times). Errors: VMS_EINVAL (null context). */
+int vms_set_overlap(vms_ctx *ctx, int on);
 
 /* Learned in-out filter (signed-distance network; negative inside):
  * xh = 2 (x - lo)/(hi - lo) - 1, phi = [sin 2 pi B xh; cos 2 pi B xh] with

@@ -302,6 +302,17 @@ struct vms_ctx {
     int32_t *d_rlist = nullptr;
     int64_t *d_cb_off = nullptr, *d_vbase = nullptr;
     int32_t *d_contrib = nullptr, *d_vstride = nullptr;
+    // the late blocks (records of sub-cell or surface items; flagged VS_LATE
+    // in their stride), ascending
+    int64_t n_late = 0;
+    int64_t *d_late = nullptr;
+    // overlapped schedule of the matrix assembly: a second stream of the
+    // context (default priority) runs the relabel, the INTERCEPTED items and the
+    // surface terms beside the summation of the other blocks; fork / join order
+    // it after the OUT elements and before the late blocks
+    bool overlap = true, last_split = false;
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     // bumped whenever the record buffers and gather lists are rebuilt, so that
     // a batch holding this context re-reads them (and drops a captured graph)
     uint64_t gen = 0;
@@ -312,9 +323,10 @@ struct vms_ctx {
     const vmsm::MlpHandle *mlp = nullptr;
     unsigned int *d_flag = nullptr;            // device-side overflow flag
     double *d_norm = nullptr;
-    // optional per-stage timing with events on the context stream
+    // optional per-stage timing with events on the context stream (ev[6..8]
+    // on the second stream in the overlapped schedule)
     bool timing = false;
-    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[9] = {};
     uint64_t n_labelled = 0, n_degenerate = 0;
 };
 
@@ -438,11 +450,12 @@ void gather_bt(vms_ctx *c, std::vector<int64_t> &off, std::vector<int32_t> &ids)
     }
 }
 
-// sub-cell quadrature on the device. At creation: count pass, offsets on the
-// host, fill pass. On relabelling: the fill pass alone, which recomputes every
-// label and verifies each element's point count on the device (a mismatch sets
-// the overflow flag, reported by vms_sizes); no host synchronisation.
-int run_subquad(vms_ctx *c, bool first) {
+// sub-cell quadrature on the device, on stream st. At creation: count pass,
+// offsets on the host, fill pass. On relabelling: the fill pass alone, which
+// recomputes every label and verifies each element's point count on the device
+// (a mismatch sets the overflow flag, reported by vms_sizes); no host
+// synchronisation.
+int run_subquad(vms_ctx *c, bool first, hipStream_t st) {
     if (c->n_sq == 0) return VMS_OK;
     vmsk::GeoArgs g{};
     for (int k = 0; k < 3; ++k) g.origin[k] = c->origin[k];
@@ -462,14 +475,14 @@ int run_subquad(vms_ctx *c, bool first) {
     a.ndeg = c->d_counters + 1;
     a.flag = c->d_flag;
     if (first) {
-        HIPCHK(c, hipMemsetAsync(c->d_counters, 0, 2 * sizeof(unsigned long long), c->stream));
-        vmsk::launch_subquad(c->stream, c->surf.S, g, a, 0);
+        HIPCHK(c, hipMemsetAsync(c->d_counters, 0, 2 * sizeof(unsigned long long), st));
+        vmsk::launch_subquad(st, c->surf.S, g, a, 0);
         HIPCHK(c, hipGetLastError());
         std::vector<int32_t> cnt(c->n_sq);
-        HIPCHK(c, hipMemcpyAsync(cnt.data(), c->d_sq_cnt, c->n_sq * 4, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(cnt.data(), c->d_sq_cnt, c->n_sq * 4, hipMemcpyDeviceToHost, st));
         unsigned long long ctr[2];
-        HIPCHK(c, hipMemcpyAsync(ctr, c->d_counters, sizeof ctr, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipMemcpyAsync(ctr, c->d_counters, sizeof ctr, hipMemcpyDeviceToHost, st));
+        HIPCHK(c, hipStreamSynchronize(st));
         c->n_labelled = ctr[0];
         c->n_degenerate = ctr[1];
         std::vector<int64_t> off(c->n_sq + 1, 0);
@@ -484,7 +497,7 @@ int run_subquad(vms_ctx *c, bool first) {
     a.off = c->d_sq_off;
     a.entries = c->d_entries;
     a.nexact = c->d_counters + 2;
-    vmsk::launch_zero_u64(c->stream, a.nexact);
+    vmsk::launch_zero_u64(st, a.nexact);
     // the set-up pass is exact; relabels use the learned filter in LEARNED
     // mode on the elements at or above the threshold (their own launch), the
     // exact kernel on the others
@@ -512,10 +525,10 @@ int run_subquad(vms_ctx *c, bool first) {
         an.learned.grid = vmsm::mlp_grid(c->mlp);
         an.learned.margin = vmsm::mlp_margin(c->mlp);
         an.learned.min_bt = 0;
-        if (ae.n_order) vmsk::launch_subquad(c->stream, c->surf.S, g, ae, 1);
-        if (an.n_order) vmsk::launch_subquad(c->stream, c->surf.S, g, an, 1);
+        if (ae.n_order) vmsk::launch_subquad(st, c->surf.S, g, ae, 1);
+        if (an.n_order) vmsk::launch_subquad(st, c->surf.S, g, an, 1);
     } else {
-        vmsk::launch_subquad(c->stream, c->surf.S, g, a, 1);
+        vmsk::launch_subquad(st, c->surf.S, g, a, 1);
     }
     HIPCHK(c, hipGetLastError());
     return VMS_OK;
@@ -608,6 +621,22 @@ static int build_gather(vms_ctx *c, const std::vector<int32_t> &stdl) {
             if (!m.node_active[n]) vstride[b0 + m.diag_pos[n]] = -(int32_t)(4 * deg);
         }
     });
+    // late blocks: the last (largest) record of the block's list is not an OUT
+    // element's
+    const int64_t std_recs = 64 * c->n_std;
+    std::vector<int64_t> late;
+    {
+        const int nt = vms::host_threads();
+        std::vector<std::vector<int64_t>> part(nt);
+        vms::parallel_for(c->n_blocks, [&](int64_t b, int64_t f, int t) {
+            for (int64_t k = b; k < f; ++k)
+                if (off[k + 1] > off[k] && contrib[off[k + 1] - 1] >= std_recs) {
+                    vstride[k] |= vmsk::VS_LATE;
+                    part[t].push_back(k);
+                }
+        });
+        for (auto &v : part) late.insert(late.end(), v.begin(), v.end());  // ranges in order: ascending
+    }
     // residual lists: node n receives slot s of every record whose element has
     // master n at slot s (counted, filled, then sorted like the block lists)
     std::vector<int64_t> roff(m.n_nodes + 1, 0);
@@ -646,6 +675,9 @@ static int build_gather(vms_ctx *c, const std::vector<int32_t> &stdl) {
     c->buf.free(c->d_contrib);
     c->buf.free(c->d_vbase);
     c->buf.free(c->d_vstride);
+    c->buf.free(c->d_late);
+    c->d_late = nullptr;
+    c->n_late = (int64_t)late.size();
     c->buf.free(c->d_em);
     c->buf.free(c->d_rrec);
     c->buf.free(c->d_roff);
@@ -655,6 +687,7 @@ static int build_gather(vms_ctx *c, const std::vector<int32_t> &stdl) {
     if (upload(c, &c->d_cb_off, off) || upload(c, &c->d_contrib, contrib) ||
         upload(c, &c->d_vbase, vbase) || upload(c, &c->d_vstride, vstride) ||
         upload(c, &c->d_roff, roff) || upload(c, &c->d_rlist, rlist) ||
+        (c->n_late && upload(c, &c->d_late, late)) ||
         c->buf.alloc(&em, (size_t)std::max<int64_t>(c->n_slots, 1) * 1024 * esz) ||
         c->buf.alloc(&rrec, (size_t)std::max<int64_t>(c->n_slots, 1) * 32 * sizeof(double)))
         return fail(c, VMS_ENOMEM, "device allocation failed (element-matrix records)");
@@ -870,6 +903,12 @@ const char *vms_last_error(vms_ctx *ctx) {
 void vms_destroy(vms_ctx *ctx) {
     if (!ctx) return;
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->side) {
+        (void)hipStreamSynchronize(ctx->side);
+        (void)hipStreamDestroy(ctx->side);
+    }
+    for (hipEvent_t e : {ctx->fork, ctx->join})
+        if (e) (void)hipEventDestroy(e);
     for (hipEvent_t &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     delete ctx;
@@ -1035,7 +1074,7 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
             c->buf.alloc(&c->d_sq_cnt, c->n_sq))
             return bail(VMS_ENOMEM);
         stage("background triangles");
-        rc = run_subquad(c, true);
+        rc = run_subquad(c, true, c->stream);
         if (rc) return bail(rc);
         stage("sub-cell quadrature");
         // split every element's point list into work items of at most ITEM_PTS
@@ -1197,6 +1236,21 @@ int vms_export(vms_ctx *c, uint32_t what, void *dst) {
     }
 }
 
+// the second stream of the overlapped schedule and its events (made on first use)
+static int ensure_side(vms_ctx *c) {
+    if (!c->side) HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    if (!c->fork) HIPCHK(c, hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+    if (!c->join) HIPCHK(c, hipEventCreateWithFlags(&c->join, hipEventDisableTiming));
+    return VMS_OK;
+}
+
+// One assembly. In order on the context stream: relabel (if asked), OUT
+// elements, INTERCEPTED items, surface terms, CSR blocks, residual. With the
+// matrix and any late work, the overlapped schedule instead forks the relabel,
+// the INTERCEPTED items and the surface terms onto the second stream once the
+// OUT elements are done, sums the blocks without late records meanwhile, joins,
+// and sums the late blocks; every block is summed by the same code in the same
+// order either way, so the outputs are identical.
 static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *resid, uint32_t flags,
                          bool mat) {
     if (!c || !f) return fail(c, VMS_EINVAL, "null context or fields");
@@ -1205,50 +1259,83 @@ static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *re
     const double *fp[7] = {f->ux, f->uy, f->uz, f->p, f->ux0, f->uy0, f->uz0};
     for (const double *p : fp)
         if (!p) return fail(c, VMS_EINVAL, "null field pointer");
-    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
-    if (flags & VMS_RELABEL) {
-        if (c->has_surf) {
-            int rc = run_subquad(c, false);
-            if (rc) return rc;
-        }
+    const bool relabel = (flags & VMS_RELABEL) && c->has_surf;
+    const bool late_work = c->n_sub_items > 0 || (c->wbc && c->n_surf_items > 0);
+    const bool split = mat && c->overlap && late_work;
+    if (split) {
+        int rc = ensure_side(c);
+        if (rc) return rc;
     }
-    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+    hipStream_t ms = c->stream, ls = split ? c->side : c->stream;
+    c->last_split = split;
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[0], ms));
+    if (relabel && !split) {
+        int rc = run_subquad(c, false, ms);
+        if (rc) return rc;
+    }
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[1], ms));
     const bool fp64 = c->prm.precision == VMS_FP64;
     vmsk::AsmArgs a = base_args(c);
     for (int k = 0; k < 7; ++k) a.f[k] = fp[k];
     a.rrec = resid ? c->d_rrec : nullptr;
     a.em = c->d_em;
     a.slot0 = 0;
-    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], ms));
     // OUT elements: 2x2x2 Gauss points
     a.n_items = c->n_std;
     a.items = c->d_std;
-    if (fp64) vmsk::launch_assemble_f64(c->stream, a, false, mat);
-    else vmsk::launch_assemble_mixed(c->stream, a, false, mat, c->prm.precision == VMS_MIXED_FP16);
+    if (fp64) vmsk::launch_assemble_f64(ms, a, false, mat);
+    else vmsk::launch_assemble_mixed(ms, a, false, mat, c->prm.precision == VMS_MIXED_FP16);
     HIPCHK(c, hipGetLastError());
-    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[3], ms));
+    int late_rc = VMS_OK;
+    if (split) {
+        HIPCHK(c, hipEventRecord(c->fork, ms));
+        HIPCHK(c, hipStreamWaitEvent(ls, c->fork, 0));
+        if (c->timing) HIPCHK(c, hipEventRecord(c->ev[6], ls));
+        if (relabel) late_rc = run_subquad(c, false, ls);
+        if (c->timing) HIPCHK(c, hipEventRecord(c->ev[7], ls));
+    }
     // INTERCEPTED elements: kept sub-cell points
-    if (c->n_sub_items) {
+    if (late_rc == VMS_OK && c->n_sub_items) {
         a.n_items = c->n_sub_items;
         a.items = c->d_sub_el;
         a.pt_off = c->d_sub_off;
         a.pt_cnt = c->d_sub_cnt;
         a.entries = c->d_entries;
         a.slot0 = c->n_std;
-        if (fp64) vmsk::launch_assemble_f64(c->stream, a, true, mat);
-        else vmsk::launch_assemble_mixed(c->stream, a, true, mat, c->prm.precision == VMS_MIXED_FP16);
+        if (fp64) vmsk::launch_assemble_f64(ls, a, true, mat);
+        else vmsk::launch_assemble_mixed(ls, a, true, mat, c->prm.precision == VMS_MIXED_FP16);
         HIPCHK(c, hipGetLastError());
     }
-    if (c->wbc && c->n_surf_items) {
+    if (late_rc == VMS_OK && c->wbc && c->n_surf_items) {
         // weak boundary terms: records after the sub-cell items
-        vmsk::launch_surface(c->stream, surf_args(c, fp, resid), mat ? 0 : 1, fp64, nullptr);
+        vmsk::launch_surface(ls, surf_args(c, fp, resid), mat ? 0 : 1, fp64, nullptr);
         HIPCHK(c, hipGetLastError());
     }
-    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[4], c->stream));
-    if (mat) gather_csr(c, c->stream, vals);
-    if (resid) gather_resid(c, c->stream, resid);
+    const void *em = c->d_em;
+    if (split) {
+        if (c->timing) HIPCHK(c, hipEventRecord(c->ev[8], ls));
+        HIPCHK(c, hipEventRecord(c->join, ls));
+        if (late_rc == VMS_OK) {
+            if (fp64)
+                vmsk::launch_gather_f64(ms, (const double *)em, c->d_cb_off, c->d_contrib, c->d_vbase,
+                                        c->d_vstride, c->n_blocks, (double *)vals, true);
+            else
+                vmsk::launch_gather_f32(ms, (const float *)em, c->d_cb_off, c->d_contrib, c->d_vbase,
+                                        c->d_vstride, c->n_blocks, (float *)vals, true);
+        }
+        HIPCHK(c, hipStreamWaitEvent(ms, c->join, 0));
+        if (late_rc) return late_rc;
+        vmsk::launch_gather_list(ms, fp64, em, c->d_cb_off, c->d_contrib, c->d_vbase, c->d_vstride, c->d_late,
+                                 c->n_late, vals);
+    } else {
+        if (c->timing) HIPCHK(c, hipEventRecord(c->ev[4], ms));
+        if (mat) gather_csr(c, ms, vals);
+    }
+    if (resid) gather_resid(c, ms, resid);
     HIPCHK(c, hipGetLastError());
-    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[5], c->stream));
+    if (c->timing) HIPCHK(c, hipEventRecord(c->ev[5], ms));
     return VMS_OK;
 }
 
@@ -1265,7 +1352,23 @@ int vms_last_timing(vms_ctx *c, float *ms) {
     if (!c || !ms) return fail(c, VMS_EINVAL, "null argument");
     if (!c->timing) return fail(c, VMS_EINVAL, "timing is off");
     HIPCHK(c, hipEventSynchronize(c->ev[5]));
+    if (c->last_split) {
+        // relabel and late items on the second stream; [4] from the end of the
+        // OUT elements to the end of the call
+        HIPCHK(c, hipEventElapsedTime(&ms[0], c->ev[6], c->ev[7]));
+        HIPCHK(c, hipEventElapsedTime(&ms[1], c->ev[1], c->ev[2]));
+        HIPCHK(c, hipEventElapsedTime(&ms[2], c->ev[2], c->ev[3]));
+        HIPCHK(c, hipEventElapsedTime(&ms[3], c->ev[7], c->ev[8]));
+        HIPCHK(c, hipEventElapsedTime(&ms[4], c->ev[3], c->ev[5]));
+        return VMS_OK;
+    }
     for (int k = 0; k < 5; ++k) HIPCHK(c, hipEventElapsedTime(&ms[k], c->ev[k], c->ev[k + 1]));
+    return VMS_OK;
+}
+
+int vms_set_overlap(vms_ctx *c, int on) {
+    if (!c) return fail(nullptr, VMS_EINVAL, "null context");
+    c->overlap = on != 0;
     return VMS_OK;
 }
 
@@ -1290,6 +1393,7 @@ int vms_apply(vms_ctx *c, const vms_fields *f, double *resid, double *norm2) {
 // y = J x without the matrix; stage events when timed and timing is on
 static int jv_impl(vms_ctx *c, const double *const fp[7], const double *x, double *y, bool timed) {
     const bool tm = timed && c->timing;
+    if (tm) c->last_split = false;
     if (tm) {
         HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
         HIPCHK(c, hipEventRecord(c->ev[1], c->stream));

@@ -822,16 +822,18 @@ void launch_assemble_batch(hipStream_t s, int precision, const AsmArgs *std_args
 // the record entries V at a time and four contributions at a time; the CSR
 // place of entry (i, j) is vbase[B] + i |vstride[B]| + j. A negative stride
 // marks the diagonal block of an inactive node: it has no records and becomes
-// an identity block.
-template <typename T, int V>
+// an identity block. A positive stride may carry the VS_LATE flag (the block
+// has records of sub-cell or surface items); SKIP_LATE leaves such blocks out.
+template <typename T, int V, bool SKIP_LATE = false>
 __device__ inline void gather_block(const T *em, const int64_t *cb_off, const int32_t *contrib,
                                     const int64_t *vbase, const int32_t *vstride, int64_t B, int e0,
                                     T *vals) {
     typedef T vec __attribute__((ext_vector_type(V)));
+    const int st = vstride[B];
+    if (SKIP_LATE && st > 0 && (st & VS_LATE)) return;
     const int64_t c0 = cb_off[B], c1 = cb_off[B + 1];
     const int64_t base = vbase[B];
-    const int st = vstride[B];
-    const int stride = st < 0 ? -st : st;
+    const int stride = st < 0 ? -st : (st & (VS_LATE - 1));
     double s[V];
     for (int q = 0; q < V; ++q) s[q] = (st < 0 && ((e0 + q) >> 2) == ((e0 + q) & 3)) ? 1.0 : 0.0;
     for (int64_t c = c0; c < c1; c += 4) {
@@ -848,14 +850,26 @@ __device__ inline void gather_block(const T *em, const int64_t *cb_off, const in
     for (int q = 0; q < V; ++q) dst[q] = (T)s[q];
 }
 
-template <typename T, int V>
+template <typename T, int V, bool SKIP_LATE>
 __global__ void k_gather(const T *em, const int64_t *cb_off, const int32_t *contrib,
                          const int64_t *vbase, const int32_t *vstride, int64_t nb, T *vals) {
     constexpr int TPB = 16 / V;  // threads per block
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t B = g / TPB;
     if (B >= nb) return;
-    gather_block<T, V>(em, cb_off, contrib, vbase, vstride, B, (int)(g % TPB) * V, vals);
+    gather_block<T, V, SKIP_LATE>(em, cb_off, contrib, vbase, vstride, B, (int)(g % TPB) * V, vals);
+}
+
+// the listed blocks only (the late blocks, after the sub-cell and surface records)
+template <typename T, int V>
+__global__ void k_gather_list(const T *em, const int64_t *cb_off, const int32_t *contrib,
+                              const int64_t *vbase, const int32_t *vstride, const int64_t *list, int64_t n,
+                              T *vals) {
+    constexpr int TPB = 16 / V;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t k = g / TPB;
+    if (k >= n) return;
+    gather_block<T, V>(em, cb_off, contrib, vbase, vstride, list[k], (int)(g % TPB) * V, vals);
 }
 
 // The same summations for every tree of a batch in one launch: the blocks of
@@ -940,18 +954,39 @@ void launch_res_gather(hipStream_t s, const double *rrec, const int64_t *roff, c
 }
 
 void launch_gather_f64(hipStream_t s, const double *em, const int64_t *cb_off, const int32_t *contrib,
-                       const int64_t *vbase, const int32_t *vstride, int64_t nb, double *vals) {
+                       const int64_t *vbase, const int32_t *vstride, int64_t nb, double *vals,
+                       bool skip_late) {
     if (nb <= 0) return;
-    const int64_t n = 8 * nb;
-    hipLaunchKernelGGL((k_gather<double, 2>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, em,
-                       cb_off, contrib, vbase, vstride, nb, vals);
+    const dim3 grid((unsigned)((8 * nb + 255) / 256));
+    if (skip_late)
+        hipLaunchKernelGGL((k_gather<double, 2, true>), grid, dim3(256), 0, s, em, cb_off, contrib, vbase,
+                           vstride, nb, vals);
+    else
+        hipLaunchKernelGGL((k_gather<double, 2, false>), grid, dim3(256), 0, s, em, cb_off, contrib, vbase,
+                           vstride, nb, vals);
 }
 void launch_gather_f32(hipStream_t s, const float *em, const int64_t *cb_off, const int32_t *contrib,
-                       const int64_t *vbase, const int32_t *vstride, int64_t nb, float *vals) {
+                       const int64_t *vbase, const int32_t *vstride, int64_t nb, float *vals,
+                       bool skip_late) {
     if (nb <= 0) return;
-    const int64_t n = 4 * nb;
-    hipLaunchKernelGGL((k_gather<float, 4>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, em,
-                       cb_off, contrib, vbase, vstride, nb, vals);
+    const dim3 grid((unsigned)((4 * nb + 255) / 256));
+    if (skip_late)
+        hipLaunchKernelGGL((k_gather<float, 4, true>), grid, dim3(256), 0, s, em, cb_off, contrib, vbase,
+                           vstride, nb, vals);
+    else
+        hipLaunchKernelGGL((k_gather<float, 4, false>), grid, dim3(256), 0, s, em, cb_off, contrib, vbase,
+                           vstride, nb, vals);
+}
+void launch_gather_list(hipStream_t s, bool fp64, const void *em, const int64_t *cb_off, const int32_t *contrib,
+                        const int64_t *vbase, const int32_t *vstride, const int64_t *list, int64_t n,
+                        void *vals) {
+    if (n <= 0) return;
+    if (fp64)
+        hipLaunchKernelGGL((k_gather_list<double, 2>), dim3((unsigned)((8 * n + 255) / 256)), dim3(256), 0, s,
+                           (const double *)em, cb_off, contrib, vbase, vstride, list, n, (double *)vals);
+    else
+        hipLaunchKernelGGL((k_gather_list<float, 4>), dim3((unsigned)((4 * n + 255) / 256)), dim3(256), 0, s,
+                           (const float *)em, cb_off, contrib, vbase, vstride, list, n, (float *)vals);
 }
 
 void launch_assemble_f64(hipStream_t s, const AsmArgs &a, bool sub, bool mat) {

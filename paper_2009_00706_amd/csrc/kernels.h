@@ -154,11 +154,21 @@ void launch_assemble_batch(hipStream_t s, int precision, const AsmArgs *std_args
                            unsigned long long *counter, int n_groups);
 void launch_assemble_mixed(hipStream_t s, const AsmArgs &a, bool sub, bool mat, int fp16);
 
-// CSR values from element-matrix records (see k_gather)
+// CSR values from element-matrix records (see k_gather). A block whose
+// stride carries VS_LATE (a positive stride only) has records of sub-cell or
+// surface items; skip_late leaves those blocks to launch_gather_list, so that
+// the rest can be summed as soon as the OUT-element records exist.
+constexpr int32_t VS_LATE = 1 << 30;
 void launch_gather_f64(hipStream_t s, const double *em, const int64_t *cb_off, const int32_t *contrib,
-                       const int64_t *vbase, const int32_t *vstride, int64_t nb, double *vals);
+                       const int64_t *vbase, const int32_t *vstride, int64_t nb, double *vals,
+                       bool skip_late = false);
 void launch_gather_f32(hipStream_t s, const float *em, const int64_t *cb_off, const int32_t *contrib,
-                       const int64_t *vbase, const int32_t *vstride, int64_t nb, float *vals);
+                       const int64_t *vbase, const int32_t *vstride, int64_t nb, float *vals,
+                       bool skip_late = false);
+// the same for the n listed blocks only (list: DEVICE, block indices)
+void launch_gather_list(hipStream_t s, bool fp64, const void *em, const int64_t *cb_off, const int32_t *contrib,
+                        const int64_t *vbase, const int32_t *vstride, const int64_t *list, int64_t n,
+                        void *vals);
 void launch_fill_f64(hipStream_t s, double *p, int64_t n, double v);
 void launch_fill_f32(hipStream_t s, float *p, int64_t n, float v);
 // Triquadratic (27-node) elements of a uniform octree, FP64: element node

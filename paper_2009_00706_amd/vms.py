@@ -38,7 +38,7 @@ EXPORTED = ["vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply"
             "vms_q2_last_timing",
             "vms_q2_destroy",
             "vms_mesh_create", "vms_mesh_sizes", "vms_mesh_export", "vms_mesh_destroy",
-            "vms_set_timing", "vms_last_timing", "vms_mlp_create", "vms_mlp_get_params",
+            "vms_set_timing", "vms_last_timing", "vms_set_overlap", "vms_mlp_create", "vms_mlp_get_params",
             "vms_mlp_set_margin", "vms_mlp_set_margin_grid", "vms_mlp_grad", "vms_mlp_train", "vms_mlp_adam_step",
             "vms_mlp_predict", "vms_mlp_last_error", "vms_mlp_destroy", "vms_sdf_sample",
             "vms_batch_create", "vms_batch_set_config", "vms_batch_get_config",
@@ -122,6 +122,8 @@ def lib():
         L.vms_set_inout.restype = C.c_int
         L.vms_relabel_stats.argtypes = [p, p]
         L.vms_relabel_stats.restype = C.c_int
+        L.vms_set_overlap.argtypes = [p, C.c_int]
+        L.vms_set_overlap.restype = C.c_int
         L.inout_reserve.argtypes = [p, i64]
         L.inout_reserve.restype = C.c_int
         L.inout_classify_static.argtypes = [C.POINTER(Surface), p, p, p, i64, p, p]
@@ -489,13 +491,19 @@ def inout_release(h):
     lib().inout_release(h)
 
 
+def vms_set_overlap(ctx, on=True):
+    """Overlapped (default) or in-order schedule of the matrix assembly (same outputs)."""
+    _check(lib().vms_set_overlap(ctx, 1 if on else 0), ctx)
+
+
 def vms_set_timing(ctx, on=True):
     _check(lib().vms_set_timing(ctx, 1 if on else 0), ctx)
 
 
 def vms_last_timing(ctx):
     """ms of the last call: relabel, argument set-up (empty), OUT-element kernel, INTERCEPTED kernel,
-    CSR summation (with identity rows)."""
+    CSR summation (with identity rows). After an overlapped assembly the first and fourth ran on the
+    second stream beside the fifth, which spans from the end of the OUT kernel to the end of the call."""
     v = (C.c_float * 5)()
     _check(lib().vms_last_timing(ctx, v), ctx)
     return list(v)
