@@ -65,6 +65,7 @@ def parse():
     ap.add_argument("--n-trees", type=int, default=64)
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16/FP16 comparison")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned + mixed step")
+    ap.add_argument("--no-scatter", action="store_true", help="skip the atomic-scatter comparison")
     ap.add_argument("--learned-standalone", action="store_true",
                     help="also time the learned filter on the kept sub-cell points outside the assembly")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -243,7 +244,8 @@ def active_rows(vms, asm):
     return np.repeat(act, 4)
 
 
-def run_single(torch, vms, tree, surf, f, prec, steps, warmup, flags, params=None, prepare=None):
+def run_single(torch, vms, tree, surf, f, prec, steps, warmup, flags, params=None, prepare=None,
+               atomic=False):
     """Time `steps` whole steps of one context; returns numbers and the outputs.
     params: vms_params (default: depth 3 at precision prec); prepare(asm) runs
     after the fields are set and before the warm-up."""
@@ -291,12 +293,13 @@ def run_single(torch, vms, tree, surf, f, prec, steps, warmup, flags, params=Non
     vms.vms_sizes(asm.ctx)   # raises if a relabel changed an element's kept-point count
     # device time of each timed step: the stages on the context stream (the
     # relabel and INTERCEPTED stages of an overlapped step ran beside the last)
-    dev = stage[:, 1] + stage[:, 2] + stage[:, 4] if overlapped(st) else stage.sum(1)
+    over = overlapped(st) and not atomic
+    dev = stage[:, 1] + stage[:, 2] + stage[:, 4] if over else stage.sum(1)
     out = {"elapsed": elapsed, "value": n_active * steps / elapsed, "ms_step": 1e3 * elapsed / steps,
            "step_device_ms": {"p10": float(np.percentile(dev, 10)), "p50": float(np.median(dev)),
                               "p90": float(np.percentile(dev, 90))},
            "stage": stage.mean(0), "stage_in_order": stage_io.mean(0), "ms_step_in_order": ms_io,
-           "overlapped": overlapped(st), "steady": steady, "setup_s": setup_s, "stats": st,
+           "overlapped": over, "steady": steady, "setup_s": setup_s, "stats": st,
            "sizes": asm.sizes, "n_active": n_active, "relabel": relabel, "extra": extra,
            "vals": asm.vals, "resid": asm.resid, "inactive": inactive_entries(torch, vms, asm)}
     asm.close()
@@ -722,6 +725,10 @@ def main_single(args):
             out["learned_mixed"] = learned_mixed(torch, vms, tree, surf, f, cfg, args, flags, r,
                                                  best, keep[best])
         keep.clear()
+        torch.cuda.empty_cache()
+    if not args.no_scatter and prec == vms.VMS_FP64:
+        out["atomic_scatter"] = atomic_scatter(torch, vms, tree, surf, f, args, flags, r,
+                                               out.get("forms", {}))
     del r["vals"]
     torch.cuda.empty_cache()
     if not args.no_jv:
@@ -740,6 +747,33 @@ def main_single(args):
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))
+
+
+def atomic_scatter(torch, vms, tree, surf, f, args, flags, r, forms):
+    """The atomic scatter (vms_set_scatter), timed like the headline step in
+    FP64 and in the faster mixed form, with its errors against the FP64 record
+    scatter (in FP64 only the order of the additions differs)."""
+    names = {"fp64": vms.VMS_FP64, "bf16": vms.VMS_MIXED_BF16, "fp16": vms.VMS_MIXED_FP16}
+    cand = ["fp64"] + ([max(forms, key=lambda k: forms[k]["value"])] if forms else [])
+    out = {}
+    for name in cand:
+        m = run_single(torch, vms, tree, surf, f, names[name], args.steps, args.warmup, flags,
+                       prepare=lambda asm: vms.vms_set_scatter(asm.ctx, vms.VMS_SCATTER_ATOMIC), atomic=True)
+        rec_ms = r["ms_step"] if name == "fp64" else forms[name]["ms_per_step"]
+        st = m["stage"]
+        out[name] = dict({"value": m["value"], "ms_per_step": m["ms_step"],
+                          "speedup_vs_record_scatter": rec_ms / m["ms_step"],
+                          "stage_ms": {"relabel": float(st[0]), "zero_fill": float(st[1]),
+                                       "out_elements_with_atomics": float(st[2]),
+                                       "intercepted_elements_with_atomics": float(st[3]),
+                                       "identity_rows_and_residual": float(st[4])}},
+                         **form_errors(torch, m, r))
+        log(f"atomic scatter {name}: {m['ms_step']:.2f} ms per step")
+        del m
+        torch.cuda.empty_cache()
+    out["note"] = ("values zeroed, then hardware atomic adds from the element kernels (no records, no "
+                   "gather); summation order not fixed; errors against the FP64 record scatter")
+    return out
 
 
 def learned_mixed(torch, vms, tree, surf, f, cfg, args, flags, r, best, ref):

@@ -71,6 +71,12 @@ enum {
     VMS_INOUT_LEARNED = 1 /* learned signed-distance filter, exact test inside the margin */
 };
 
+/* scatter of the element matrices into the CSR values (vms_set_scatter) */
+enum {
+    VMS_SCATTER_RECORDS = 0, /* records summed per CSR block in a fixed order (default) */
+    VMS_SCATTER_ATOMIC = 1   /* hardware atomic adds into the values (order not fixed) */
+};
+
 /* vms_assemble flags */
 enum {
     VMS_RELABEL = 1u  /* recompute sub-cell quadrature points and their labels first */
@@ -406,6 +412,22 @@ int vms_last_timing(vms_ctx *ctx, float *ms);
  * records, same per-block summation order). Off: every stage in order on the
  * context stream (isolated stage times). Errors: VMS_EINVAL (null context). */
 int vms_set_overlap(vms_ctx *ctx, int on);
+
+/* Scatter of the element matrices in vms_assemble. VMS_SCATTER_RECORDS (the
+ * default): every work item writes a 1024-entry record and a gather sums each
+ * CSR block from its records in a fixed order (repeatable bits). Scatter
+ * alternative measured beside it, VMS_SCATTER_ATOMIC: the values are zeroed,
+ * then each element kernel adds its entries with hardware atomic adds (FP64
+ * for VMS_FP64, FP32 otherwise) at their CSR places, and the identity blocks of
+ * inactive nodes are written last; no record and no gather, but the order of
+ * the additions, and so the last bits of the values, may change from call to
+ * call. The residual is summed from records in both modes. The first switch to
+ * the atomic mode copies each element's block columns to the device (128
+ * bytes per element). Batches (vms_batch_*) keep the records. Errors:
+ * VMS_EINVAL (null context, unknown mode), VMS_EUNSUPPORTED (atomic mode with
+ * the weak boundary terms on; vms_set_weak_bc refuses them in the atomic
+ * mode), VMS_ENOMEM. */
+int vms_set_scatter(vms_ctx *ctx, uint32_t mode);
 
 /* Learned in-out filter (signed-distance network; negative inside):
  * xh = 2 (x - lo)/(hi - lo) - 1, phi = [sin 2 pi B xh; cos 2 pi B xh] with

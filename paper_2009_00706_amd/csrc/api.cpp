@@ -311,6 +311,10 @@ struct vms_ctx {
     // surface terms beside the summation of the other blocks; fork / join order
     // it after the OUT elements and before the late blocks
     bool overlap = true, last_split = false;
+    // scatter of the element matrices (vms_set_scatter); the atomic mode needs
+    // each element's block columns on the device
+    uint32_t scatter = VMS_SCATTER_RECORDS;
+    uint16_t *d_el_kk = nullptr;
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
     // bumped whenever the record buffers and gather lists are rebuilt, so that
@@ -1236,6 +1240,8 @@ int vms_export(vms_ctx *c, uint32_t what, void *dst) {
     }
 }
 
+static int ensure_diag_pos(vms_ctx *c);
+
 // the second stream of the overlapped schedule and its events (made on first use)
 static int ensure_side(vms_ctx *c) {
     if (!c->side) HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
@@ -1261,7 +1267,8 @@ static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *re
         if (!p) return fail(c, VMS_EINVAL, "null field pointer");
     const bool relabel = (flags & VMS_RELABEL) && c->has_surf;
     const bool late_work = c->n_sub_items > 0 || (c->wbc && c->n_surf_items > 0);
-    const bool split = mat && c->overlap && late_work;
+    const bool atomic = mat && c->scatter == VMS_SCATTER_ATOMIC;
+    const bool split = mat && c->overlap && late_work && !atomic;
     if (split) {
         int rc = ensure_side(c);
         if (rc) return rc;
@@ -1280,6 +1287,15 @@ static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *re
     a.rrec = resid ? c->d_rrec : nullptr;
     a.em = c->d_em;
     a.slot0 = 0;
+    if (atomic) {
+        // the values start at zero; the kernels add every element matrix into them
+        if (fp64) vmsk::launch_fill_f64(ms, (double *)vals, c->mesh.nrow_ptr[c->mesh.n_nodes] * 16, 0.0);
+        else vmsk::launch_fill_f32(ms, (float *)vals, c->mesh.nrow_ptr[c->mesh.n_nodes] * 16, 0.0f);
+        HIPCHK(c, hipGetLastError());
+        a.vals = vals;
+        a.nrow_ptr = c->d_nrow_ptr;
+        a.el_kk = c->d_el_kk;
+    }
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[2], ms));
     // OUT elements: 2x2x2 Gauss points
     a.n_items = c->n_std;
@@ -1331,7 +1347,17 @@ static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *re
                                  c->n_late, vals);
     } else {
         if (c->timing) HIPCHK(c, hipEventRecord(c->ev[4], ms));
-        if (mat) gather_csr(c, ms, vals);
+        if (atomic) {
+            // identity blocks of the inactive nodes (no element adds to them)
+            if (fp64)
+                vmsk::launch_dirichlet_rows_f64(ms, (double *)vals, c->d_nrow_ptr, c->d_diag_pos, c->d_inact,
+                                                c->n_inact, nullptr);
+            else
+                vmsk::launch_dirichlet_rows_f32(ms, (float *)vals, c->d_nrow_ptr, c->d_diag_pos, c->d_inact,
+                                                c->n_inact, nullptr);
+        } else if (mat) {
+            gather_csr(c, ms, vals);
+        }
     }
     if (resid) gather_resid(c, ms, resid);
     HIPCHK(c, hipGetLastError());
@@ -1369,6 +1395,20 @@ int vms_last_timing(vms_ctx *c, float *ms) {
 int vms_set_overlap(vms_ctx *c, int on) {
     if (!c) return fail(nullptr, VMS_EINVAL, "null context");
     c->overlap = on != 0;
+    return VMS_OK;
+}
+
+int vms_set_scatter(vms_ctx *c, uint32_t mode) {
+    if (!c) return fail(nullptr, VMS_EINVAL, "null context");
+    if (mode != VMS_SCATTER_RECORDS && mode != VMS_SCATTER_ATOMIC) return fail(c, VMS_EINVAL, "unknown scatter mode");
+    if (mode == VMS_SCATTER_ATOMIC) {
+        if (c->wbc) return fail(c, VMS_EUNSUPPORTED, "the atomic scatter excludes the weak boundary terms");
+        if (!c->d_el_kk && upload(c, &c->d_el_kk, c->mesh.el_kk))
+            return fail(c, VMS_ENOMEM, "device allocation failed (element block columns)");
+        int rc = ensure_diag_pos(c);
+        if (rc) return rc;
+    }
+    c->scatter = mode;
     return VMS_OK;
 }
 
@@ -1710,6 +1750,8 @@ int vms_set_weak_bc(vms_ctx *c, int enable, double c_b, const double *g) {
         return build_gather(c, c->std_el);
     }
     if (!c->has_surf) return fail(c, VMS_EINVAL, "weak boundary terms need a surface");
+    if (c->scatter == VMS_SCATTER_ATOMIC)
+        return fail(c, VMS_EUNSUPPORTED, "the weak boundary terms need the record scatter");
     if (!g || !std::isfinite(c_b) || c_b < 0 || !std::isfinite(g[0]) || !std::isfinite(g[1]) ||
         !std::isfinite(g[2]))
         return fail(c, VMS_EINVAL, "bad weak-boundary parameters (c_b >= 0, finite g)");

@@ -691,7 +691,52 @@ __device__ __forceinline__ void asm_item(const AsmArgs &a, const int64_t item,
     // (block (a, b) of master slots, entry 4 i + j), stored from the
     // accumulators; the CSR is summed from these records by the gather kernel
     // (no atomics, fixed summation order)
-    if (MAT) {
+    if (MAT && a.vals) {
+        // atomic scatter: no record; each entry is added into its CSR place
+        // (the summation order is the hardware's)
+        T *vals = (T *)a.vals;
+        const int32_t *mst = a.masters + 8 * (int64_t)e;
+        const uint16_t *kk = a.el_kk + 64 * (int64_t)e;
+        if (MODE == 0) {
+            const int m4 = lane >> 4, j4 = (lane >> 2) & 3, n4 = lane & 3;
+            for (int ah = 0; ah < 2; ++ah) {
+                const int av = 4 * ah + m4, ma = mst[av];
+                if (ma < 0) continue;
+                const int64_t r0 = a.nrow_ptr[ma], deg = a.nrow_ptr[ma + 1] - r0;
+                for (int bh = 0; bh < 2; ++bh) {
+                    const int b = 4 * bh + n4;
+                    if (mst[b] < 0) continue;
+                    T *dst = vals + 16 * r0 + 4 * (int64_t)kk[8 * av + b] + j4;
+                    for (int i = 0; i < 4; ++i) atomicAdd(dst + 4 * i * deg, (T)acc4[i][ah][bh]);
+                }
+            }
+        } else {
+            const int col = lane & 15, bb = col >> 2, jc = col & 3;
+            const float unscale = (MODE == 2 && s16 != INT_MAX) ? ldexpf(1.0f, -s16) : 1.0f;
+            // rows av = 4 (lane / 16) + r of the lanes < 32, columns b = 4 h + bb
+            int64_t rb[4], dg[4];
+            bool ok[4];
+            for (int r = 0; r < 4; ++r) {
+                const int ma = mst[(4 * (lane >> 4) + r) & 7];
+                ok[r] = ma >= 0;
+                rb[r] = ok[r] ? a.nrow_ptr[ma] : 0;
+                dg[r] = ok[r] ? a.nrow_ptr[ma + 1] - rb[r] : 0;
+            }
+            for (int t = 0; t < 8; ++t) {
+                v4f v = accf[t];
+                for (int r = 0; r < 4; ++r) v[r] = (v[r] + __shfl_down(v[r], 32, 64)) * unscale;
+                const int i = t >> 1, b = 4 * (t & 1) + bb;
+                if (lane < 32 && mst[b] >= 0) {
+                    for (int r = 0; r < 4; ++r) {
+                        const int av = 4 * (lane >> 4) + r;
+                        if (ok[r])
+                            atomicAdd(vals + 16 * rb[r] + 4 * (int64_t)kk[8 * av + b] + 4 * i * dg[r] + jc,
+                                      (T)v[r]);
+                    }
+                }
+            }
+        }
+    } else if (MAT) {
         const int col = lane & 15, bb = col >> 2, jc = col & 3;
         T *dst = (T *)a.em + (a.slot0 + item) * 1024;
         if (MODE == 0) {

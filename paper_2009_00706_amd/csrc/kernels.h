@@ -122,6 +122,13 @@ struct AsmArgs {
     double *rrec;
     void *em;
     int64_t slot0;
+    // atomic scatter (vals non-null): the element matrix is added straight
+    // into the CSR values (double for FP64, else float) with hardware atomics
+    // instead of being written as a record; entry (i, j) of slot pair (s, t)
+    // goes to 16 nrow_ptr[m_s] + 4 el_kk[64 e + 8 s + t] + 4 i deg(m_s) + j
+    void *vals;
+    const int64_t *nrow_ptr;  // [n_nodes + 1] block rows
+    const uint16_t *el_kk;    // [E][8][8] block column of m_t within row m_s
 };
 inline void set_params(AsmArgs &a, double rho, double mu, double dt, double theta, double c_t,
                        double c_i, double root_len) {

@@ -19,6 +19,7 @@ VMS_OK, VMS_EINVAL, VMS_EMESH, VMS_EHIP, VMS_ENOMEM, VMS_EOVERFLOW, VMS_EUNSUPPO
     0, -1, -2, -3, -4, -5, -6)
 VMS_FP64, VMS_MIXED_BF16, VMS_MIXED_FP16 = 0, 1, 2
 VMS_INOUT_EXACT, VMS_INOUT_LEARNED = 0, 1
+VMS_SCATTER_RECORDS, VMS_SCATTER_ATOMIC = 0, 1
 VMS_RELABEL = 1
 VMS_KSP_BCGS, VMS_KSP_GMRES = 0, 1
 VMS_SOLVE_DIRICHLET = 1
@@ -38,7 +39,7 @@ EXPORTED = ["vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply"
             "vms_q2_last_timing",
             "vms_q2_destroy",
             "vms_mesh_create", "vms_mesh_sizes", "vms_mesh_export", "vms_mesh_destroy",
-            "vms_set_timing", "vms_last_timing", "vms_set_overlap", "vms_mlp_create", "vms_mlp_get_params",
+            "vms_set_timing", "vms_last_timing", "vms_set_overlap", "vms_set_scatter", "vms_mlp_create", "vms_mlp_get_params",
             "vms_mlp_set_margin", "vms_mlp_set_margin_grid", "vms_mlp_grad", "vms_mlp_train", "vms_mlp_adam_step",
             "vms_mlp_predict", "vms_mlp_last_error", "vms_mlp_destroy", "vms_sdf_sample",
             "vms_batch_create", "vms_batch_set_config", "vms_batch_get_config",
@@ -124,6 +125,8 @@ def lib():
         L.vms_relabel_stats.restype = C.c_int
         L.vms_set_overlap.argtypes = [p, C.c_int]
         L.vms_set_overlap.restype = C.c_int
+        L.vms_set_scatter.argtypes = [p, u32]
+        L.vms_set_scatter.restype = C.c_int
         L.inout_reserve.argtypes = [p, i64]
         L.inout_reserve.restype = C.c_int
         L.inout_classify_static.argtypes = [C.POINTER(Surface), p, p, p, i64, p, p]
@@ -494,6 +497,11 @@ def inout_release(h):
 def vms_set_overlap(ctx, on=True):
     """Overlapped (default) or in-order schedule of the matrix assembly (same outputs)."""
     _check(lib().vms_set_overlap(ctx, 1 if on else 0), ctx)
+
+
+def vms_set_scatter(ctx, mode):
+    """VMS_SCATTER_RECORDS (fixed summation order, default) or VMS_SCATTER_ATOMIC."""
+    _check(lib().vms_set_scatter(ctx, int(mode)), ctx)
 
 
 def vms_set_timing(ctx, on=True):
