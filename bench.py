@@ -66,6 +66,7 @@ def parse():
     ap.add_argument("--no-forms", action="store_true", help="skip the BF16/FP16 comparison")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned + mixed step")
     ap.add_argument("--no-scatter", action="store_true", help="skip the atomic-scatter comparison")
+    ap.add_argument("--no-normal", action="store_true", help="skip the normal-based filter comparison")
     ap.add_argument("--learned-standalone", action="store_true",
                     help="also time the learned filter on the kept sub-cell points outside the assembly")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -344,6 +345,35 @@ def train_filter(torch, surf, n_train):
     torch.cuda.synchronize()
     return lf, {"train_samples": n_train, "train_loss": loss, "global_margin": margin,
                 "margin_grid": list(grid), "train_and_calibrate_s": time.perf_counter() - t0}
+
+
+def normal_filter(torch, vms, tree, surf, f, reps=7):
+    """The normal-based test of Alg. 5 as a certified filter (VMS_INOUT_NORMAL)
+    against the exact test alone: relabel time (in-order schedule, HIP events),
+    share of the candidate points the filter decides, bodies and convexity."""
+    asm = vms.Assembler(tree, surf, vms.make_params(quad_depth=3))
+    asm.set_fields(f)
+    vms.vms_set_timing(asm.ctx, True)
+    vms.vms_set_overlap(asm.ctx, False)
+    out = {}
+    for name, mode in (("exact", vms.VMS_INOUT_EXACT), ("normal", vms.VMS_INOUT_NORMAL)):
+        vms.vms_set_inout(asm.ctx, mode)
+        for _ in range(2):
+            asm.assemble(flags=vms.VMS_RELABEL)
+        t = []
+        for _ in range(reps):
+            asm.assemble(flags=vms.VMS_RELABEL)
+            t.append(vms.vms_last_timing(asm.ctx)[0])
+        rs = vms.vms_relabel_stats(asm.ctx)
+        out[name] = {"relabel_ms": float(np.median(t)),
+                     "decided_by_filter": 1.0 - rs["exact_in_last_relabel"] / max(rs["candidates"], 1)}
+    n, convex = vms.vms_components(asm.ctx)
+    vms.vms_sizes(asm.ctx)   # raises if a relabel changed a kept-point count
+    asm.close()
+    out["bodies"] = int(n)
+    out["convex"] = [bool(x) for x in convex]
+    out["speedup"] = out["exact"]["relabel_ms"] / out["normal"]["relabel_ms"]
+    return out
 
 
 def learned_threshold(torch, vms, asm, lf, thresholds=(0, 16, 32, 64, 128, 1 << 30), reps=5):
@@ -741,6 +771,9 @@ def main_single(args):
         out["weak_bc"] = weak_bc_cost(torch, vms, tree, surf, f, prec)
         if prec == vms.VMS_FP64 and args.cost_model != "none":
             out["cost_model"] = cost_model(torch, vms, st, out["weak_bc"], args.cost_model)
+    if surf is not None and not args.no_normal:
+        log("normal-based filter")
+        out["normal_filter"] = normal_filter(torch, vms, tree, surf, f)
     if surf is not None and args.learned_standalone:
         out["learned_inout"] = learned_inout(torch, vms, tree, surf,
                                              cfg.get("learned_train_samples", 1_000_000))

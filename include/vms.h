@@ -65,10 +65,12 @@ enum {
     VMS_MIXED_FP16 = 2  /* B^T D B on FP16 MFMA, FP32 accumulate; CSR values are float */
 };
 
-/* in-out test of quadrature points (inout_classify mode) */
+/* in-out test of quadrature points (inout_classify mode; vms_params.inout_mode) */
 enum {
-    VMS_INOUT_EXACT = 0,  /* exact segment parity with exact orientation predicates */
-    VMS_INOUT_LEARNED = 1 /* learned signed-distance filter, exact test inside the margin */
+    VMS_INOUT_EXACT = 0,   /* exact segment parity with exact orientation predicates */
+    VMS_INOUT_LEARNED = 1, /* learned signed-distance filter, exact test inside the margin */
+    VMS_INOUT_NORMAL = 2   /* the normal-based test of Alg. 5 as a certified filter in front
+                              of the exact test (sub-cell quadrature only; see vms_set_inout) */
 };
 
 /* scatter of the element matrices into the CSR values (vms_set_scatter) */
@@ -120,11 +122,15 @@ typedef struct {
 
 /* Closed, watertight, consistently outward-oriented triangle surface, HOST
  * pointers: verts [n_vert][3] interleaved, tri [n_tri][3] (counter-clockwise
- * seen from outside). */
+ * seen from outside), body_id [n_tri] (nullable) the body each triangle
+ * belongs to. The bodies (components) are the body_id groups, or without
+ * body_id the connected pieces of the triangle mesh (triangles joined by an
+ * edge); bodies are disjoint and none lies inside another (vms_surface_components). */
 typedef struct {
     int32_t n_vert, n_tri;
     const double *verts;
     const int32_t *tri;
+    const int32_t *body_id;
 } vms_surface;
 
 /* Physical and discretisation parameters. theta = 1/2 is Crank-Nicolson (the
@@ -136,8 +142,9 @@ typedef struct {
     int32_t quad_depth;
     uint32_t precision;      /* VMS_FP64 | VMS_MIXED_BF16 | VMS_MIXED_FP16 */
     uint32_t inout_mode;     /* in-out test of the sub-cell quadrature points on relabel:
-                                VMS_INOUT_EXACT, or VMS_INOUT_LEARNED (the network given by
-                                vms_set_inout decides where |prediction| >= margin) */
+                                VMS_INOUT_EXACT, VMS_INOUT_LEARNED (the network given by
+                                vms_set_inout decides where |prediction| >= margin) or
+                                VMS_INOUT_NORMAL (certified normal-based filter) */
     int32_t learned_min_bt;  /* LEARNED: the network is used on INTERCEPTED elements with at
                                 least this many background triangles, the exact test alone
                                 on the others */
@@ -526,6 +533,32 @@ void vms_batch_destroy(vms_batch *b);
  * labelled by the exact test in the last relabel (synchronises). */
 int vms_set_inout(vms_ctx *ctx, uint32_t mode, const vms_mlp *mlp, int32_t min_bt);
 int vms_relabel_stats(vms_ctx *ctx, int64_t *out);
+
+/* VMS_INOUT_NORMAL (vms_set_inout with mlp null, min_bt 0, or inout_mode in
+ * vms_params): the paper's normal-based test (Alg. 5 and the text after it)
+ * used only where it is certain. A body is convex when at every edge the far
+ * vertex of one adjacent triangle is not strictly outside the plane of the
+ * other (checked with exact predicates at vms_create); a point strictly
+ * outside the plane of one of a convex body's triangles (the sign of the
+ * exact orientation of the triangle and the point, i.e. of (P - centroid) . n)
+ * is outside that body. A candidate point of an INTERCEPTED element is labelled
+ * OUT when, for every body with triangles among the element's background
+ * triangles, it is strictly outside one of those triangles' planes and the
+ * body is convex (a body with no background triangle cannot contain a point
+ * of an element it does not cut, bodies being disjoint and not nested); every
+ * other point (inside all planes, on one, a non-convex body, more than 8
+ * bodies or more than 64 background triangles at the element) takes the exact
+ * test. Labels are therefore exact; vms_relabel_stats counts the points the
+ * exact test labelled. vms_components writes HOST n_comp and, if convex is
+ * non-null, convex[n_comp] (1 convex, 0 not) for the context's surface. */
+int vms_components(vms_ctx *ctx, int32_t *n_comp, uint8_t *convex);
+
+/* Host-only: the bodies of a surface (the body_id groups, or the connected
+ * pieces of the mesh), comp (HOST [n_tri], nullable) the body index of each
+ * triangle, 0 .. n_comp - 1 in order of first appearance. Errors: VMS_EINVAL
+ * (invalid surface, or body_id differing across an edge), VMS_EMESH (not
+ * closed / not consistently oriented). */
+int vms_surface_components(const vms_surface *surf, int32_t *comp, int32_t *n_comp);
 
 /* Counters of a context (HOST out[7]): OUT elements, INTERCEPTED elements,
  * points labelled by the last sub-cell quadrature, degenerate directions

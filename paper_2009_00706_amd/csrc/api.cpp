@@ -63,6 +63,61 @@ int check_watertight(const vms_surface *s, std::string &err) {
     return VMS_OK;
 }
 
+// Bodies of a closed surface: the body_id groups, or the connected pieces
+// (triangles joined by an edge, union-find), numbered by first appearance.
+// edges (nullable) receives every edge once as (t1, t2, corner of t2 opposite
+// the edge) for the convexity test. The surface must have passed
+// check_watertight: every undirected edge has exactly two triangles.
+int surface_components(const vms_surface *s, std::vector<int32_t> &comp, int32_t &n_comp,
+                       std::vector<int32_t> *et1, std::vector<int32_t> *et2, std::vector<int8_t> *ecorner,
+                       std::string &err) {
+    const int64_t nt = s->n_tri;
+    struct E { uint64_t key; int32_t t; int8_t k; };
+    std::vector<E> ed;
+    ed.reserve(3 * nt);
+    for (int64_t t = 0; t < nt; ++t)
+        for (int k = 0; k < 3; ++k) {
+            const uint64_t a = (uint32_t)s->tri[3 * t + k], b = (uint32_t)s->tri[3 * t + (k + 1) % 3];
+            ed.push_back({(std::min(a, b) << 32) | std::max(a, b), (int32_t)t, (int8_t)k});
+        }
+    std::sort(ed.begin(), ed.end(), [](const E &x, const E &y) { return x.key != y.key ? x.key < y.key : x.t < y.t; });
+    std::vector<int32_t> par(nt);
+    for (int64_t t = 0; t < nt; ++t) par[t] = (int32_t)t;
+    auto find = [&](int32_t x) {
+        while (par[x] != x) x = par[x] = par[par[x]];
+        return x;
+    };
+    if (s->body_id)
+        for (int64_t t = 0; t < nt; ++t)
+            if (s->body_id[t] < 0) { err = "negative body id"; return VMS_EINVAL; }
+    for (size_t i = 0; i + 1 < ed.size(); i += 2) {
+        if (ed[i].key != ed[i + 1].key) { err = "surface edge without exactly two triangles"; return VMS_EMESH; }
+        const int32_t t1 = ed[i].t, t2 = ed[i + 1].t;
+        if (s->body_id && s->body_id[t1] != s->body_id[t2]) { err = "body id differs across an edge"; return VMS_EINVAL; }
+        const int32_t r1 = find(t1), r2 = find(t2);
+        if (r1 != r2) par[std::max(r1, r2)] = std::min(r1, r2);
+        if (et1) {
+            et1->push_back(t1);
+            et2->push_back(t2);
+            ecorner->push_back((int8_t)((ed[i + 1].k + 2) % 3));
+        }
+    }
+    comp.assign(nt, -1);
+    std::vector<int64_t> ids(nt);
+    for (int64_t t = 0; t < nt; ++t) ids[t] = s->body_id ? (int64_t)s->body_id[t] : (int64_t)find((int32_t)t);
+    std::vector<int64_t> order(ids);
+    std::sort(order.begin(), order.end());
+    order.erase(std::unique(order.begin(), order.end()), order.end());
+    std::vector<int32_t> num(order.size(), -1);
+    n_comp = 0;
+    for (int64_t t = 0; t < nt; ++t) {
+        const size_t j = std::lower_bound(order.begin(), order.end(), ids[t]) - order.begin();
+        if (num[j] < 0) num[j] = n_comp++;
+        comp[t] = num[j];
+    }
+    return VMS_OK;
+}
+
 // bin index, the same arithmetic as the device query
 static inline int host_bin(double v, double v0, double inv, int n) {
     volatile double d = v - v0;
@@ -245,6 +300,13 @@ struct vms_ctx {
     uint8_t *d_sq_level = nullptr, *d_sq_clab = nullptr;
     int64_t *d_bt_off = nullptr;
     std::vector<int32_t> sq_nbt;  // background triangles of each INTERCEPTED element (host)
+    // bodies of the surface and their convexity; per background-triangle entry
+    // the local index of its body at the element, per element the body mask
+    // (0: the normal-based filter is off there)
+    std::vector<int32_t> comp;
+    std::vector<uint8_t> comp_convex;
+    int32_t n_comp = 0;
+    uint8_t *d_bt_lc = nullptr, *d_sq_nmask = nullptr;
     // learned mode: the INTERCEPTED elements (list positions) at or above the
     // threshold on the background-triangle count, and the others
     int32_t split_bt = -1;
@@ -368,7 +430,8 @@ bool params_ok(const vms_params *p, std::string &why) {
         why = "parameter out of range (rho > 0, dt > 0, mu >= 0, c_t > 0, c_i >= 0, 0 <= theta <= 1)";
         return false;
     }
-    if (p->inout_mode != VMS_INOUT_EXACT && p->inout_mode != VMS_INOUT_LEARNED) {
+    if (p->inout_mode != VMS_INOUT_EXACT && p->inout_mode != VMS_INOUT_LEARNED &&
+        p->inout_mode != VMS_INOUT_NORMAL) {
         why = "unknown in-out mode";
         return false;
     }
@@ -501,6 +564,9 @@ int run_subquad(vms_ctx *c, bool first, hipStream_t st) {
     a.off = c->d_sq_off;
     a.entries = c->d_entries;
     a.nexact = c->d_counters + 2;
+    a.normal = (!first && c->prm.inout_mode == VMS_INOUT_NORMAL) ? 1 : 0;
+    a.bt_lc = c->d_bt_lc;
+    a.nmask = c->d_sq_nmask;
     vmsk::launch_zero_u64(st, a.nexact);
     // the set-up pass is exact; relabels use the learned filter in LEARNED
     // mode on the elements at or above the threshold (their own launch), the
@@ -996,6 +1062,40 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
         rc = build_surface(surf, c->stream, c->surf, err);
         if (rc) { c->err = err; return bail(rc); }
         c->has_surf = true;
+        // bodies and their convexity (exact orientation of every edge's far vertex)
+        {
+            std::vector<int32_t> t1, t2;
+            std::vector<int8_t> cor;
+            rc = vms::surface_components(surf, c->comp, c->n_comp, &t1, &t2, &cor, err);
+            if (rc) { c->err = err; return bail(rc); }
+            const int64_t ne = (int64_t)t1.size();
+            DevBuf eb;
+            int32_t *d1, *d2;
+            int8_t *dc;
+            uint8_t *dbad;
+            std::vector<uint8_t> bad(ne);
+            if (eb.alloc(&d1, std::max<int64_t>(ne, 1)) || eb.alloc(&d2, std::max<int64_t>(ne, 1)) ||
+                eb.alloc(&dc, std::max<int64_t>(ne, 1)) || eb.alloc(&dbad, std::max<int64_t>(ne, 1))) {
+                c->err = "device allocation failed (convexity)";
+                return bail(VMS_ENOMEM);
+            }
+            if (ne && (hipMemcpyAsync(d1, t1.data(), ne * 4, hipMemcpyHostToDevice, c->stream) ||
+                       hipMemcpyAsync(d2, t2.data(), ne * 4, hipMemcpyHostToDevice, c->stream) ||
+                       hipMemcpyAsync(dc, cor.data(), ne, hipMemcpyHostToDevice, c->stream))) {
+                c->err = "device copy failed (convexity)";
+                return bail(VMS_EHIP);
+            }
+            vmsk::launch_edge_convex(c->stream, c->surf.S, d1, d2, dc, ne, dbad);
+            if (hipGetLastError() != hipSuccess ||
+                (ne && hipMemcpyAsync(bad.data(), dbad, ne, hipMemcpyDeviceToHost, c->stream)) ||
+                hipStreamSynchronize(c->stream)) {
+                c->err = "convexity kernel failed";
+                return bail(VMS_EHIP);
+            }
+            c->comp_convex.assign(c->n_comp, 1);
+            for (int64_t e = 0; e < ne; ++e)
+                if (bad[e]) c->comp_convex[c->comp[t1[e]]] = 0;
+        }
         const int64_t NV = (int64_t)m.vert_key.size();
         std::vector<int32_t> ix(NV), iy(NV), iz(NV);
         for (int64_t v = 0; v < NV; ++v) {
@@ -1064,6 +1164,26 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
         gather_bt(c, bt_off, bt_ids);
         c->sq_nbt.resize(c->n_sq);
         for (int64_t i = 0; i < c->n_sq; ++i) c->sq_nbt[i] = (int32_t)(bt_off[i + 1] - bt_off[i]);
+        // bodies at each element for the normal-based filter: local index of
+        // each background triangle's body (first appearance), mask of the
+        // element's bodies; 0 (filter off) with a non-convex body or more than 8
+        std::vector<uint8_t> bt_lc(std::max<size_t>(bt_ids.size(), 1), 0), nmask(c->n_sq, 0);
+        for (int64_t i = 0; i < c->n_sq; ++i) {
+            int32_t loc[8];
+            int nl = 0;
+            bool ok = true;
+            for (int64_t j = bt_off[i]; j < bt_off[i + 1] && ok; ++j) {
+                const int32_t cid = c->comp[bt_ids[j]];
+                int k = 0;
+                while (k < nl && loc[k] != cid) ++k;
+                if (k == nl) {
+                    if (nl == 8 || !c->comp_convex[cid]) ok = false;
+                    else loc[nl++] = cid;
+                }
+                if (ok) bt_lc[j] = (uint8_t)k;
+            }
+            nmask[i] = ok && nl ? (uint8_t)((1u << nl) - 1u) : 0;
+        }
         std::vector<int32_t> sax(c->n_sq), say(c->n_sq), saz(c->n_sq);
         std::vector<uint8_t> slev(c->n_sq), sclab(8 * c->n_sq);
         for (int64_t i = 0; i < c->n_sq; ++i) {
@@ -1075,6 +1195,7 @@ int vms_create(vms_ctx **out, const vms_octree *tree, const vms_surface *surf,
             upload(c, &c->d_sq_ay, say) || upload(c, &c->d_sq_az, saz) ||
             upload(c, &c->d_sq_level, slev) || upload(c, &c->d_sq_clab, sclab) ||
             upload(c, &c->d_bt_off, bt_off) || upload(c, &c->d_bt_ids, bt_ids) ||
+            upload(c, &c->d_bt_lc, bt_lc) || upload(c, &c->d_sq_nmask, nmask) ||
             c->buf.alloc(&c->d_sq_cnt, c->n_sq))
             return bail(VMS_ENOMEM);
         stage("background triangles");
@@ -1777,12 +1898,35 @@ int vms_element_weights(vms_ctx *c, double ts_over_tv, double *w) {
 
 int vms_set_inout(vms_ctx *c, uint32_t mode, const vms_mlp *mlp, int32_t min_bt) {
     if (!c) return fail(nullptr, VMS_EINVAL, "null context");
-    if (mode != VMS_INOUT_EXACT && mode != VMS_INOUT_LEARNED) return fail(c, VMS_EINVAL, "unknown in-out mode");
+    if (mode != VMS_INOUT_EXACT && mode != VMS_INOUT_LEARNED && mode != VMS_INOUT_NORMAL)
+        return fail(c, VMS_EINVAL, "unknown in-out mode");
     if (mode == VMS_INOUT_LEARNED && !mlp) return fail(c, VMS_EINVAL, "learned in-out mode needs a network");
     if (min_bt < 0) return fail(c, VMS_EINVAL, "min_bt must be >= 0");
     c->prm.inout_mode = mode;
     c->prm.learned_min_bt = min_bt;
     c->mlp = (const vmsm::MlpHandle *)mlp;
+    return VMS_OK;
+}
+
+int vms_components(vms_ctx *c, int32_t *n_comp, uint8_t *convex) {
+    if (!c || !n_comp) return fail(c, VMS_EINVAL, "null argument");
+    *n_comp = c->n_comp;
+    if (convex && c->n_comp) std::memcpy(convex, c->comp_convex.data(), (size_t)c->n_comp);
+    return VMS_OK;
+}
+
+int vms_surface_components(const vms_surface *surf, int32_t *comp, int32_t *n_comp) {
+    if (!surf || !n_comp || surf->n_tri <= 0 || surf->n_vert <= 0 || !surf->verts || !surf->tri)
+        return fail(nullptr, VMS_EINVAL, "null or empty surface");
+    std::string err;
+    int rc = vms::check_watertight(surf, err);
+    if (rc) return fail(nullptr, rc, err);
+    std::vector<int32_t> cc;
+    int32_t nc = 0;
+    rc = vms::surface_components(surf, cc, nc, nullptr, nullptr, nullptr, err);
+    if (rc) return fail(nullptr, rc, err);
+    *n_comp = nc;
+    if (comp) std::memcpy(comp, cc.data(), cc.size() * sizeof(int32_t));
     return VMS_OK;
 }
 

@@ -128,12 +128,16 @@ __device__ static int local_label_lds(const SurfDev &S, const double *P, const d
 // level; a kept point sets the bit of its key (and records its level) in a
 // bitmap over the key space, so that the canonical (ascending key) position
 // of every kept point is the number of set bits below it: no sort is needed.
-// LEARNED: on elements with at least min_bt background triangles the 64
-// candidate points of a batch first go through the signed-distance network;
-// a point whose |prediction| reaches its margin takes the network's sign,
-// every other point the exact test.
-template <bool LEARNED>
+// FILT 1 (learned): on elements with at least min_bt background triangles
+// the 64 candidate points of a batch first go through the signed-distance
+// network; a point whose |prediction| reaches its margin takes the network's
+// sign, every other point the exact test. FILT 2 (normal-based, Alg. 5 as a
+// certified filter): a point strictly outside the plane of one background
+// triangle of each of the element's bodies (all convex) is OUT; the others
+// take the exact test.
+template <int FILT>
 __global__ __launch_bounds__(64) void k_subquad(SurfDev S, GeoArgs g, SubqArgs a, int pass) {
+    constexpr bool LEARNED = FILT == 1, NORMAL = FILT == 2;
     __shared__ uint32_t cells[2][SQ_MAXCELL];  // path digits, level 1 most significant
     __shared__ unsigned long long kbits[SQ_KEYS / 64];
     __shared__ uint32_t klev[SQ_KEYS / 16];    // 2 bits per key
@@ -142,6 +146,7 @@ __global__ __launch_bounds__(64) void k_subquad(SurfDev S, GeoArgs g, SubqArgs a
     __shared__ uint8_t vl[8];
     __shared__ double tv[SQ_BTMAX][9];
     __shared__ double tb[SQ_BTMAX][6];
+    __shared__ uint8_t tlc[NORMAL ? SQ_BTMAX : 1];
     __shared__ __attribute__((aligned(16))) _Float16 act[LEARNED ? 64 : 1][vmsm::LDH];
     const int lane = threadIdx.x;
     const int64_t i = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
@@ -168,11 +173,13 @@ __global__ __launch_bounds__(64) void k_subquad(SurfDev S, GeoArgs g, SubqArgs a
     const int nbt = (int)(a.bt_off[i + 1] - a.bt_off[i]);
     const bool staged = nbt <= SQ_BTMAX;
     const bool use_net = LEARNED && nbt >= a.learned.min_bt;  // uniform over the workgroup
+    const unsigned nmask = (NORMAL && staged && pass == 1) ? a.nmask[i] : 0u;
     if (staged)
         for (int t = lane; t < nbt; t += 64) {
             const int id = bt[t];
             for (int k = 0; k < 9; ++k) tv[t][k] = S.tv[9 * (int64_t)id + k];
             for (int k = 0; k < 6; ++k) tb[t][k] = S.tbox[6 * (int64_t)id + k];
+            if constexpr (NORMAL) tlc[t] = a.bt_lc[a.bt_off[i] + t];
         }
     __syncthreads();
     int cur = 0;
@@ -222,6 +229,21 @@ __global__ __launch_bounds__(64) void k_subquad(SurfDev S, GeoArgs g, SubqArgs a
                     const float y = vmsm::net_output64(a.learned.net, P, valid, act);
                     if (valid && fabsf(y) >= vmsm::point_margin(a.learned.grid, a.learned.margin, P)) {
                         lab = y < 0.f ? 1 : 0;
+                        decided = true;
+                    }
+                }
+            }
+            if constexpr (NORMAL) {
+                if (valid && nmask) {
+                    // strictly on the outer side of a triangle of every body present
+                    unsigned got = 0;
+                    for (int t = 0; t < nbt && got != nmask; ++t) {
+                        const unsigned bit = 1u << tlc[t];
+                        if (got & bit) continue;
+                        if (orient3d(tv[t], tv[t] + 3, tv[t] + 6, P) < 0) got |= bit;
+                    }
+                    if (got == nmask) {
+                        lab = 0;
                         decided = true;
                     }
                 }
@@ -296,9 +318,27 @@ void launch_subquad(hipStream_t s, const SurfDev &S, const GeoArgs &g, const Sub
     const int64_t n = a.order ? a.n_order : a.n;
     if (n <= 0) return;
     if (a.learned.net.theta)
-        hipLaunchKernelGGL(k_subquad<true>, dim3((unsigned)n), dim3(64), 0, s, S, g, a, pass);
+        hipLaunchKernelGGL(k_subquad<1>, dim3((unsigned)n), dim3(64), 0, s, S, g, a, pass);
+    else if (a.normal && pass == 1)
+        hipLaunchKernelGGL(k_subquad<2>, dim3((unsigned)n), dim3(64), 0, s, S, g, a, pass);
     else
-        hipLaunchKernelGGL(k_subquad<false>, dim3((unsigned)n), dim3(64), 0, s, S, g, a, pass);
+        hipLaunchKernelGGL(k_subquad<0>, dim3((unsigned)n), dim3(64), 0, s, S, g, a, pass);
+}
+
+__global__ void k_edge_convex(SurfDev S, const int32_t *t1, const int32_t *t2, const int8_t *corner,
+                              int64_t n, uint8_t *bad) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const double *a = S.tv + 9 * (int64_t)t1[e];
+    const double *v = S.tv + 9 * (int64_t)t2[e] + 3 * corner[e];
+    bad[e] = orient3d(a, a + 3, a + 6, v) < 0 ? 1 : 0;
+}
+
+void launch_edge_convex(hipStream_t s, const SurfDev &S, const int32_t *t1, const int32_t *t2,
+                        const int8_t *corner, int64_t n, uint8_t *bad) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_edge_convex, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, S, t1, t2, corner,
+                       n, bad);
 }
 
 }  // namespace vmsk

@@ -90,8 +90,19 @@ struct SubqArgs {
     LearnedArgs learned; // learned.net.theta null: exact labels only
     const int32_t *order;  // non-null: only the n_order elements order[..] of the list
     int64_t n_order;
+    // certified normal-based filter (normal != 0, pass 1): per background
+    // triangle of an element the local index (0..7) of its body among the
+    // element's bodies, per element the mask of its bodies (0: filter off there)
+    int32_t normal;
+    const uint8_t *bt_lc;
+    const uint8_t *nmask;
 };
 void launch_subquad(hipStream_t s, const SurfDev &S, const GeoArgs &g, const SubqArgs &a, int pass);
+// bad[e] = 1 when vertex corner[e] of triangle t2[e] lies strictly outside the
+// plane of triangle t1[e] (exact orientation): the surface is not convex at
+// that edge
+void launch_edge_convex(hipStream_t s, const SurfDev &S, const int32_t *t1, const int32_t *t2,
+                        const int8_t *corner, int64_t n, uint8_t *bad);
 void launch_zero_u64(hipStream_t s, unsigned long long *c);
 
 // Assembly.

@@ -308,20 +308,107 @@ def ellipsoid(semi, center, rot, n_lat: int, n_lon: int) -> Surface:
     return s
 
 
+def _orient_sign(a, b, c, d):
+    """Sign of det[a - d; b - d; c - d] for rows of points (negative: d on the
+    side from which a, b, c turn counter-clockwise): float64 with a generous
+    forward error bound, exact rational arithmetic where the bound cannot
+    decide."""
+    from fractions import Fraction
+    ad, bd, cd = a - d, b - d, c - d
+    m1 = bd[:, 0] * cd[:, 1] - cd[:, 0] * bd[:, 1]
+    m2 = cd[:, 0] * ad[:, 1] - ad[:, 0] * cd[:, 1]
+    m3 = ad[:, 0] * bd[:, 1] - bd[:, 0] * ad[:, 1]
+    det = ad[:, 2] * m1 + bd[:, 2] * m2 + cd[:, 2] * m3
+    perm = (np.abs(ad[:, 2]) * (np.abs(bd[:, 0] * cd[:, 1]) + np.abs(cd[:, 0] * bd[:, 1])) +
+            np.abs(bd[:, 2]) * (np.abs(cd[:, 0] * ad[:, 1]) + np.abs(ad[:, 0] * cd[:, 1])) +
+            np.abs(cd[:, 2]) * (np.abs(ad[:, 0] * bd[:, 1]) + np.abs(bd[:, 0] * ad[:, 1])))
+    sign = np.sign(det).astype(np.int64)
+    amb = np.abs(det) <= 1e-13 * perm
+    # four points with one coordinate equal lie in an axis plane: exactly 0
+    same = np.zeros(det.shape, bool)
+    for k in range(3):
+        same |= (a[:, k] == b[:, k]) & (a[:, k] == c[:, k]) & (a[:, k] == d[:, k])
+    sign[amb & same] = 0
+    for r in np.nonzero(amb & ~same)[0]:
+        vals = [float(x) for p in (a, b, c, d) for x in p[r]]
+        if all((x * 2.0 ** 60).is_integer() for x in vals):
+            A, B, C, D = ([int(x * 2.0 ** 60) for x in p[r]] for p in (a, b, c, d))   # exact
+        else:
+            A, B, C, D = ([Fraction(float(x)) for x in p[r]] for p in (a, b, c, d))
+        u = [A[k] - D[k] for k in range(3)]
+        v = [B[k] - D[k] for k in range(3)]
+        w = [C[k] - D[k] for k in range(3)]
+        e = (u[2] * (v[0] * w[1] - w[0] * v[1]) + v[2] * (w[0] * u[1] - u[0] * w[1]) +
+             w[2] * (u[0] * v[1] - v[0] * u[1]))
+        sign[r] = (e > 0) - (e < 0)
+    return sign
+
+
+def _edges(tris):
+    """Every undirected edge once: (t1, t2, k1, k2), the two triangles and the
+    position k of the edge's first vertex in each (edge k runs k -> k + 1)."""
+    nt = tris.shape[0]
+    t = tris.astype(np.int64)
+    a = np.concatenate([t[:, k] for k in range(3)])
+    b = np.concatenate([t[:, (k + 1) % 3] for k in range(3)])
+    tid = np.tile(np.arange(nt), 3)
+    kk = np.repeat(np.arange(3), nt)
+    key = np.minimum(a, b) * (t.max() + 1) + np.maximum(a, b)
+    o = np.lexsort((tid, key))
+    p, q = o[0::2], o[1::2]
+    return tid[p], tid[q], kk[p], kk[q]
+
+
+def _flip_to_convex(v, tris, max_rounds=100):
+    """Flip every edge whose fold is concave (the far vertex of one triangle
+    strictly outside the other's plane, exact sign) until none is left. The
+    vertices lie on a convex surface, so the flips converge to a triangulation
+    of their convex hull; orientation is kept."""
+    tris = tris.astype(np.int64).copy()
+    for _ in range(max_rounds):
+        t1, t2, k1, k2 = _edges(tris)
+        far = tris[t2, (k2 + 2) % 3]
+        bad = np.nonzero(_orient_sign(v[tris[t1, 0]], v[tris[t1, 1]], v[tris[t1, 2]], v[far]) < 0)[0]
+        if bad.size == 0:
+            return tris.astype(np.int32)
+        t = tris.astype(np.int64)
+        nv = int(t.max()) + 1
+        present = set((np.minimum(t[:, [0, 1, 2]], t[:, [1, 2, 0]]) * nv +
+                       np.maximum(t[:, [0, 1, 2]], t[:, [1, 2, 0]])).ravel().tolist())
+        used = set()
+        for e in bad:
+            a, b = int(t1[e]), int(t2[e])
+            if a in used or b in used:
+                continue
+            u, w_ = tris[a, k1[e]], tris[a, (k1[e] + 2) % 3]
+            vv = tris[a, (k1[e] + 1) % 3]
+            x = tris[b, (k2[e] + 2) % 3]
+            if min(x, w_) * nv + max(x, w_) in present:
+                continue
+            tris[a] = (u, x, w_)
+            tris[b] = (x, vv, w_)
+            present.add(min(x, w_) * nv + max(x, w_))
+            used.update((a, b))
+    raise RuntimeError("edge flips did not converge")
+
+
 def rounded_box(half, fillet, center, n_face: int) -> Surface:
     """Box with rounded edges and corners (fillet radius), from a cube-surface grid.
 
     Each point p of a uniform n_face x n_face grid on every face of the cube
     surface [-1,1]^3, scaled to the outer box, maps to c + fillet (p - c)/|p - c|,
     with c the closest point of the inner box (half - fillet): 12 n_face^2
-    triangles.
+    triangles. Each grid quad is split along the diagonal that makes its fold
+    convex (the quad's fourth vertex not strictly outside the first triangle's
+    plane, decided exactly), then any remaining concave fold across a quad edge
+    is flipped, so that the mesh bounds a convex body exactly.
     """
     half = np.asarray(half, dtype=np.float64)
     inner = half - fillet
     t = np.linspace(-1.0, 1.0, n_face + 1)
     verts = {}
     vl = []
-    tris = []
+    quads = []
 
     def vid(p):
         key = tuple(np.round(p, 12))
@@ -347,7 +434,7 @@ def rounded_box(half, fillet, center, n_face: int) -> Surface:
             for i in range(n_face):
                 for j in range(n_face):
                     a, b, c, d = ids[i, j], ids[i + 1, j], ids[i, j + 1], ids[i + 1, j + 1]
-                    tris += [[a, b, d], [a, d, c]] if out else [[a, d, b], [a, c, d]]
+                    quads.append((a, b, d, c) if out else (a, c, d, b))
     cube = np.array(vl)
     pts = cube * half
     cl = np.clip(pts, -inner, inner)
@@ -355,6 +442,15 @@ def rounded_box(half, fillet, center, n_face: int) -> Surface:
     nrm = np.linalg.norm(dv, axis=1, keepdims=True)
     nrm[nrm == 0] = 1.0
     v = cl + fillet * dv / nrm + np.asarray(center)
+    # quad (p0, p1, p2, p3) in outward order: diagonal p0-p2 unless p3 lies
+    # strictly outside the plane of (p0, p1, p2), then diagonal p1-p3
+    q = np.array(quads, dtype=np.int64)
+    concave = _orient_sign(v[q[:, 0]], v[q[:, 1]], v[q[:, 2]], v[q[:, 3]]) < 0
+    tris = np.where(concave[:, None, None],
+                    np.stack([q[:, [0, 1, 3]], q[:, [1, 2, 3]]], 1),
+                    np.stack([q[:, [0, 1, 2]], q[:, [0, 2, 3]]], 1)).reshape(-1, 3)
+    # folds across the quads' edges (where the grid meets the fillets)
+    tris = _flip_to_convex(v, tris)
     s = Surface(v, np.array(tris, dtype=np.int32),
                 {"kind": "rounded_box", "half": half.tolist(), "fillet": fillet,
                  "center": list(map(float, center))})

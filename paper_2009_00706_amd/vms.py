@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libvms.so")
 VMS_OK, VMS_EINVAL, VMS_EMESH, VMS_EHIP, VMS_ENOMEM, VMS_EOVERFLOW, VMS_EUNSUPPORTED = (
     0, -1, -2, -3, -4, -5, -6)
 VMS_FP64, VMS_MIXED_BF16, VMS_MIXED_FP16 = 0, 1, 2
-VMS_INOUT_EXACT, VMS_INOUT_LEARNED = 0, 1
+VMS_INOUT_EXACT, VMS_INOUT_LEARNED, VMS_INOUT_NORMAL = 0, 1, 2
 VMS_SCATTER_RECORDS, VMS_SCATTER_ATOMIC = 0, 1
 VMS_RELABEL = 1
 VMS_KSP_BCGS, VMS_KSP_GMRES = 0, 1
@@ -39,7 +39,7 @@ EXPORTED = ["vms_create", "vms_sizes", "vms_export", "vms_assemble", "vms_apply"
             "vms_q2_last_timing",
             "vms_q2_destroy",
             "vms_mesh_create", "vms_mesh_sizes", "vms_mesh_export", "vms_mesh_destroy",
-            "vms_set_timing", "vms_last_timing", "vms_set_overlap", "vms_set_scatter", "vms_mlp_create", "vms_mlp_get_params",
+            "vms_set_timing", "vms_last_timing", "vms_set_overlap", "vms_set_scatter", "vms_components", "vms_surface_components", "vms_mlp_create", "vms_mlp_get_params",
             "vms_mlp_set_margin", "vms_mlp_set_margin_grid", "vms_mlp_grad", "vms_mlp_train", "vms_mlp_adam_step",
             "vms_mlp_predict", "vms_mlp_last_error", "vms_mlp_destroy", "vms_sdf_sample",
             "vms_batch_create", "vms_batch_set_config", "vms_batch_get_config",
@@ -61,7 +61,7 @@ class Octree(C.Structure):
 
 class Surface(C.Structure):
     _fields_ = [("n_vert", C.c_int32), ("n_tri", C.c_int32), ("verts", C.c_void_p),
-                ("tri", C.c_void_p)]
+                ("tri", C.c_void_p), ("body_id", C.c_void_p)]
 
 
 class Params(C.Structure):
@@ -127,6 +127,10 @@ def lib():
         L.vms_set_overlap.restype = C.c_int
         L.vms_set_scatter.argtypes = [p, u32]
         L.vms_set_scatter.restype = C.c_int
+        L.vms_components.argtypes = [p, p, p]
+        L.vms_components.restype = C.c_int
+        L.vms_surface_components.argtypes = [C.POINTER(Surface), p, p]
+        L.vms_surface_components.restype = C.c_int
         L.inout_reserve.argtypes = [p, i64]
         L.inout_reserve.restype = C.c_int
         L.inout_classify_static.argtypes = [C.POINTER(Surface), p, p, p, i64, p, p]
@@ -203,11 +207,12 @@ def _np(a, dt):
     return np.ascontiguousarray(a, dtype=dt)
 
 
-def make_surface(verts, tris):
+def make_surface(verts, tris, body_id=None):
     v = _np(verts, np.float64).reshape(-1, 3)
     t = _np(tris, np.int32).reshape(-1, 3)
-    s = Surface(v.shape[0], t.shape[0], v.ctypes.data, t.ctypes.data)
-    s._keep = (v, t)
+    b = None if body_id is None else _np(body_id, np.int32).reshape(-1)
+    s = Surface(v.shape[0], t.shape[0], v.ctypes.data, t.ctypes.data, None if b is None else b.ctypes.data)
+    s._keep = (v, t, b)
     return s
 
 
@@ -225,7 +230,7 @@ def vms_create(tree, surf=None, params=None, stream=None):
     """tree: object with ax, ay, az, level, max_level, origin, root_len (host arrays);
     surf: object with verts (n,3), tris (m,3) or None. Returns the context handle."""
     o = _octree(tree)
-    s = make_surface(surf.verts, surf.tris) if surf is not None else None
+    s = make_surface(surf.verts, surf.tris, getattr(surf, "body_id", None)) if surf is not None else None
     prm = params if params is not None else make_params()
     h = C.c_void_p()
     rc = lib().vms_create(C.byref(h), C.byref(o), C.byref(s) if s is not None else None,
@@ -497,6 +502,24 @@ def inout_release(h):
 def vms_set_overlap(ctx, on=True):
     """Overlapped (default) or in-order schedule of the matrix assembly (same outputs)."""
     _check(lib().vms_set_overlap(ctx, 1 if on else 0), ctx)
+
+
+def vms_components(ctx):
+    """(n_comp, convex flags) of the context's surface bodies."""
+    n = C.c_int32(0)
+    _check(lib().vms_components(ctx, C.byref(n), None), ctx)
+    cv = np.zeros(max(n.value, 1), np.uint8)
+    _check(lib().vms_components(ctx, C.byref(n), cv.ctypes.data), ctx)
+    return n.value, cv[:n.value].astype(bool)
+
+
+def vms_surface_components(surf):
+    """Body index of every triangle (body_id groups or connected pieces), host only."""
+    s = make_surface(surf.verts, surf.tris, getattr(surf, "body_id", None))
+    comp = np.zeros(s.n_tri, np.int32)
+    n = C.c_int32(0)
+    _check(lib().vms_surface_components(C.byref(s), comp.ctypes.data, C.byref(n)), None)
+    return comp, n.value
 
 
 def vms_set_scatter(ctx, mode):

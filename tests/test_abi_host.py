@@ -182,3 +182,66 @@ def test_host_setup_independent_of_thread_count():
         out[n] = r.stdout.split()
     assert int(out[1][0]) > 3 * 32768  # at least three ranges of the parallel loops
     assert out[1][1] == out[3][1] == out[8][1]
+
+
+def _first_appearance(labels):
+    out, seen = np.empty_like(labels), {}
+    for i, v in enumerate(labels):
+        out[i] = seen.setdefault(int(v), len(seen))
+    return out
+
+
+def _pieces_scipy(surf):
+    """Connected pieces of a triangle mesh by scipy's graph routine (triangles
+    joined by a shared undirected edge)."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    t = surf.tris.astype(np.int64)
+    nt = t.shape[0]
+    e = np.concatenate([np.sort(t[:, [k, (k + 1) % 3]], 1) for k in range(3)])
+    tid = np.tile(np.arange(nt), 3)
+    key = e[:, 0] * (t.max() + 1) + e[:, 1]
+    o = np.argsort(key, kind="stable")
+    a, b = tid[o][0::2], tid[o][1::2]
+    g = coo_matrix((np.ones(a.size), (a, b)), shape=(nt, nt))
+    return _first_appearance(connected_components(g, directed=False)[1])
+
+
+def test_surface_components():
+    """vms_surface_components: the connected pieces of the mesh (against
+    scipy's connected components), the body_id groups when given, and the
+    errors for a body id that changes across an edge or is negative."""
+    c = np.array([0.5, 0.5, 0.5])
+    one = I.icosphere(2, 0.2, c)
+    comp, n = vms.vms_surface_components(one)
+    assert n == 1 and (comp == 0).all()
+    two = I.two_boxes(6)
+    comp, n = vms.vms_surface_components(two)
+    assert n == 2
+    assert np.array_equal(comp, _pieces_scipy(two))
+    half = two.n_tri // 2
+    assert (comp[:half] == 0).all() and (comp[half:] == 1).all()
+    three = I.merge_surfaces([I.icosphere(1, 0.1, c + 0.3), two, I.icosphere(1, 0.1, c - 0.3)])
+    comp, n = vms.vms_surface_components(three)
+    assert n == 4 and np.array_equal(comp, _pieces_scipy(three))
+    # body ids: groups of whole pieces (ids 7 and 3: numbered by first appearance)
+    two.body_id = np.where(np.arange(two.n_tri) < half, 7, 3).astype(np.int32)
+    comp, n = vms.vms_surface_components(two)
+    assert n == 2 and (comp[:half] == 0).all() and (comp[half:] == 1).all()
+    two.body_id = np.full(two.n_tri, 5, np.int32)          # both boxes one body: allowed
+    comp, n = vms.vms_surface_components(two)
+    assert n == 1
+    bad = np.zeros(one.n_tri, np.int32)
+    bad[0] = 1                                             # differs across triangle 0's edges
+    one.body_id = bad
+    with pytest.raises(vms.VmsError) as e:
+        vms.vms_surface_components(one)
+    assert e.value.code == vms.VMS_EINVAL
+    one.body_id = -np.ones(one.n_tri, np.int32)
+    with pytest.raises(vms.VmsError) as e:
+        vms.vms_surface_components(one)
+    assert e.value.code == vms.VMS_EINVAL
+    open_s = I.Surface(one.verts, one.tris[:-1].copy())
+    with pytest.raises(vms.VmsError) as e:
+        vms.vms_surface_components(open_s)
+    assert e.value.code == vms.VMS_EMESH
