@@ -30,7 +30,7 @@ int vmsm_sdf(hipStream_t s, const vmsk::SurfDev &S, const std::vector<double> &t
 // sub-cell points per assembly work item (longer items: fewer element-matrix
 // records and item set-ups; shorter items: finer load balance)
 #ifndef VMS_ITEM_PTS
-#define VMS_ITEM_PTS 64
+#define VMS_ITEM_PTS 128
 #endif
 
 namespace vms {
