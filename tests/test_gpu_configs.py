@@ -7,8 +7,9 @@
   inactive nodes are exact in every form and would otherwise dominate the
   norm (they are checked entry by entry).
 * The precision form at its full size (sphere, levels 6-10, ~2.1M octants):
-  a property at any size (a constant state has zero residual) and the mixed
-  forms against the FP64 form (itself checked against the reference above).
+  a property at any size (a constant state has zero residual), sampled node
+  rows of every form against the reference, and the mixed forms against the
+  FP64 form over the whole matrix.
 * The learned filter on the two-box geometry (two filleted bluff boxes in an
   8 x 2 x 2 domain): labels equal to the exact ones, reference-checked on a
   subsample, and the fraction of points the network decides.
@@ -88,13 +89,22 @@ def test_deep_levels_all_forms_against_reference(env, oracle):
         asm.close()
 
 
-def test_precision_form_full_size(env):
+def test_precision_form_full_size(env, oracle):
     """~2.1M octants at levels 6-10: zero residual for a constant state in every
-    form, and BF16 / FP16 within 1e-5 of FP64 (norms taken on the device)."""
+    form; the library's node numbering equal to the reference's own numbering of
+    the whole tree; the rows of sampled nodes (near the body and anywhere, with
+    inactive ones) against the reference's rows, FP64 to 1e-12 and BF16 / FP16
+    to 1e-5; BF16 / FP16 within 1e-5 of FP64 over the whole matrix (norms taken
+    on the device)."""
     torch, vms = env
+    import sampled_rows as SR
     tree, surf = I.sphere_workload(lmin=6, lmax=10, beta=3.0)
     assert 2.0e6 < tree.n < 2.3e6
-    ref = None
+    keys = oracle._mesh.independent_node_keys(tree.ax, tree.ay, tree.az, tree.level, tree.max_level)
+    kxyz = oracle._mesh._decode(keys)
+    f = I.make_fields(kxyz.astype(np.float64) / float(1 << tree.max_level) * tree.root_len +
+                      np.asarray(tree.origin), 1001)
+    ref = rows = None
     for prec in (vms.VMS_FP64, vms.VMS_MIXED_BF16, vms.VMS_MIXED_FP16):
         t0 = time.perf_counter()
         asm = vms.Assembler(tree, surf, vms.make_params(quad_depth=3, precision=prec))
@@ -107,9 +117,55 @@ def test_precision_form_full_size(env):
         torch.cuda.synchronize()
         rmax = asm.resid.abs().max().item()
         assert rmax < (1e-15 if prec == vms.VMS_FP64 else 1e-6), rmax
-        asm.set_fields(I.make_fields(node_xyz(vms, asm, tree), 1001))
+        asm.set_fields(f)
         asm.assemble()
         torch.cuda.synchronize()
+        if rows is None:
+            assert np.array_equal(asm.export(vms.VMS_EXPORT_NODE_XYZ).T, kxyz)
+            # nodes to sample (the choice may use the exports; expected values may
+            # not): nodes whose elements all have one level, so that the
+            # reference's window around each stays small (a coarse neighbour of
+            # the refined shell would pull most of the tree into it)
+            from oracle import window as W
+            mk = asm.export(vms.VMS_EXPORT_MARKERS)
+            ma_all = asm.export(vms.VMS_EXPORT_MASTERS)
+            ma = ma_all[mk != 1]
+            active = np.zeros(n, bool)
+            active[ma[ma >= 0]] = True
+            lev = np.repeat(tree.level.astype(np.int64), 8)
+            m = ma_all.ravel()
+            lo, hi = np.full(n, 99), np.full(n, -1)
+            np.minimum.at(lo, m[m >= 0], lev[m >= 0])
+            np.maximum.at(hi, m[m >= 0], lev[m >= 0])
+            uniform = lo == hi
+            cutm = np.unique(ma[mk[mk != 1] == 2].ravel())
+            cutm = cutm[cutm >= 0]
+            rng = np.random.default_rng(2)
+            index = W.LeafIndex(tree)
+
+            def pick(pool, k):
+                out = []
+                for c in rng.permutation(pool[uniform[pool]]):
+                    if W.node_window(index, kxyz[c])[1].size <= 4000:
+                        out.append(int(c))
+                        if len(out) == k:
+                            break
+                assert len(out) == k
+                return out
+
+            nodes = np.unique(np.array(pick(np.nonzero(active)[0], 16) + pick(cutm, 20) +
+                                       pick(np.nonzero(~active)[0], 4)))
+            t1 = time.perf_counter()
+            rows = SR.reference_rows(oracle, tree, surf, f, keys, nodes, depth=3,
+                                     log=lambda m: print(m, flush=True))
+            print(f"reference rows of {nodes.size} nodes ({time.perf_counter() - t1:.1f} s)", flush=True)
+            rp = asm.export(vms.VMS_EXPORT_ROW_PTR)
+            nrp = asm.export(vms.VMS_EXPORT_NODE_ROW_PTR)
+            ncol = asm.export(vms.VMS_EXPORT_NODE_COL)
+        tol = 1e-12 if prec == vms.VMS_FP64 else 1e-5
+        ev, er, _ = SR.compare_rows(rows, rp, nrp, ncol, asm.vals, asm.resid, tol=tol)
+        print(f"precision {prec}: sampled rows against the reference: values {ev:.2e}, residual {er:.2e}",
+              flush=True)
         v = asm.vals.double()
         r = asm.resid.clone()
         if ref is None:
