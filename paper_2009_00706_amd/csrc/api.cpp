@@ -574,6 +574,13 @@ int run_subquad(vms_ctx *c, bool first, hipStream_t st) {
     if (!first && c->prm.inout_mode == VMS_INOUT_LEARNED) {
         if (!c->mlp) return fail(c, VMS_EINVAL, "learned in-out mode needs a network (vms_set_inout)");
         if (c->split_bt != c->prm.learned_min_bt) {
+            // New element lists. Relabels still in flight on either stream read
+            // the old ones, and upload() copies on the context stream while the
+            // kernels below may run on the second stream (overlapped schedule,
+            // whose fork precedes these copies): wait for both streams before
+            // freeing, and for the copies before launching.
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            if (st != c->stream) HIPCHK(c, hipStreamSynchronize(st));
             std::vector<int32_t> net, ex;
             for (int64_t i = 0; i < c->n_sq; ++i)
                 (c->sq_nbt[i] >= c->prm.learned_min_bt ? net : ex).push_back((int32_t)i);
@@ -585,6 +592,7 @@ int run_subquad(vms_ctx *c, bool first, hipStream_t st) {
             c->n_sq_net = (int64_t)net.size();
             c->n_sq_exact = (int64_t)ex.size();
             c->split_bt = c->prm.learned_min_bt;
+            HIPCHK(c, hipStreamSynchronize(c->stream));
         }
         vmsk::SubqArgs ae = a, an = a;
         ae.order = c->d_sq_exact;

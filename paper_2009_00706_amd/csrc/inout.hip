@@ -150,7 +150,7 @@ __global__ __launch_bounds__(64) void k_subquad(SurfDev S, GeoArgs g, SubqArgs a
     __shared__ __attribute__((aligned(16))) _Float16 act[LEARNED ? 64 : 1][vmsm::LDH];
     const int lane = threadIdx.x;
     const int64_t i = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
-    if (i >= a.n) return;
+    if (i < 0 || i >= a.n) return;
     const int D = g.depth;
     const int M = g.max_level;
     const int F = M + D;

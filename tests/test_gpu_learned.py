@@ -131,10 +131,6 @@ def test_learned_labels_bit_exact_and_gain(env, oracle):
     lf.close()
 
 
-@pytest.mark.skip(reason="one run of this test (after 24 passing GPU tests, on a build whose kernels it runs "
-                         "had passed it twice) ended with a library error and the GPU left faulted, the log lost "
-                         "with the box; no cause was found by reading the kernels it runs, so the case stays "
-                         "off the GPU until one is shown")
 def test_learned_filter_inside_the_assembly(env, oracle):
     """The learned filter in front of the exact test of the sub-cell quadrature
     (vms_params.inout_mode / vms_set_inout): a surface much finer than the
