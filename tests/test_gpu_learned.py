@@ -194,8 +194,14 @@ def test_learned_filter_inside_the_assembly(env, oracle):
     t_exact = relabel_ms(ex)
     times = {}
     for tb in (0, 16, 32, 64, 128, 1 << 30):
+        # each new threshold rebuilds the element lists of the learned relabel,
+        # which runs on the second stream of the overlapped schedule: the
+        # outputs must stay those of the exact mode after every rebuild
         vms.vms_set_inout(ln.ctx, vms.VMS_INOUT_LEARNED, lf.net, tb)
         times[tb] = relabel_ms(ln)
+        torch.cuda.synchronize()
+        vms.vms_sizes(ln.ctx)
+        assert torch.equal(ex.vals, ln.vals) and torch.equal(ex.resid, ln.resid), tb
     best = min(times, key=times.get)
     print(f"relabel: exact {t_exact:.3f} ms; learned by threshold "
           + ", ".join(f"{k}: {v:.3f}" for k, v in times.items())
