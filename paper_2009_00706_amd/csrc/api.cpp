@@ -310,6 +310,7 @@ struct vms_ctx {
     // learned mode: the INTERCEPTED elements (list positions) at or above the
     // threshold on the background-triangle count, and the others
     int32_t split_bt = -1;
+    int sub_cap = -1;  // workgroups per CU of the sub-cell items beside the gather (0: no cap; -1: not yet set)
     int64_t n_sq_net = 0, n_sq_exact = 0;
     int32_t *d_sq_net = nullptr, *d_sq_exact = nullptr;
     int32_t *d_bt_ids = nullptr;
@@ -1386,6 +1387,34 @@ static int ensure_side(vms_ctx *c) {
 // OUT elements are done, sums the blocks without late records meanwhile, joins,
 // and sums the late blocks; every block is summed by the same code in the same
 // order either way, so the outputs are identical.
+// Workgroups per CU of the sub-cell item kernel when it runs beside the CSR
+// gather (overlapped schedule). The gather is bound by HBM and needs many
+// waves in flight; when the items' estimated time is well below the gather's,
+// fewer item waves per SIMD leave it that parallelism and still finish inside
+// it. Estimates from rates measured on this GPU: 0.51 ns per sub-cell point
+// over the whole GPU in FP64, 0.33 ns in the mixed forms; the gather's bytes
+// (records read, values written) at 4.7 TB/s (FP64 values) or 4.0 TB/s
+// (FP32). Two-box workload: FP64 4 per CU instead of 8 (step 65.1 -> 62.3
+// ms), FP16x2 8 instead of 12 (44.0 -> 42.6 ms); no cap where the items
+// outlast the gather (sphere workloads). 0 = no cap.
+static int sub_wg_cap(vms_ctx *c) {
+    if (c->sub_cap >= 0) return c->sub_cap;
+    const bool fp64 = c->prm.precision == VMS_FP64;
+    const double vb = fp64 ? 8.0 : 4.0;
+    const double t_sub = (double)c->n_subgp * (fp64 ? 0.51e-9 : 0.33e-9);
+    const double recs = (double)(c->n_std + c->n_sub_items);
+    const double t_gather = (recs * 1024.0 + (double)c->mesh.nnz) * vb / (fp64 ? 4.7e12 : 4.0e12);
+    const int per_cu = vmsk::sub_items_per_cu(fp64 ? 0 : (c->prm.precision == VMS_MIXED_BF16 ? 1 : 2));
+    int cap = 0;
+    if (per_cu >= 8 && t_gather > 0.0) {
+        const int w_full = per_cu / 4;  // waves per SIMD: one-wave workgroups, 4 SIMDs per CU
+        const int w = (int)std::ceil((double)w_full * t_sub / t_gather);
+        if (w < w_full) cap = 4 * std::max(1, w);
+    }
+    c->sub_cap = cap;
+    return cap;
+}
+
 static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *resid, uint32_t flags,
                          bool mat) {
     if (!c || !f) return fail(c, VMS_EINVAL, "null context or fields");
@@ -1449,8 +1478,9 @@ static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *re
         a.pt_cnt = c->d_sub_cnt;
         a.entries = c->d_entries;
         a.slot0 = c->n_std;
-        if (fp64) vmsk::launch_assemble_f64(ls, a, true, mat);
-        else vmsk::launch_assemble_mixed(ls, a, true, mat, c->prm.precision == VMS_MIXED_FP16);
+        const int cap = split ? sub_wg_cap(c) : 0;
+        if (fp64) vmsk::launch_assemble_f64(ls, a, true, mat, cap);
+        else vmsk::launch_assemble_mixed(ls, a, true, mat, c->prm.precision == VMS_MIXED_FP16, cap);
         HIPCHK(c, hipGetLastError());
     }
     if (late_rc == VMS_OK && c->wbc && c->n_surf_items) {

@@ -1039,19 +1039,43 @@ void launch_gather_list(hipStream_t s, bool fp64, const void *em, const int64_t 
                            (const float *)em, cb_off, contrib, vbase, vstride, list, n, (float *)vals);
 }
 
-void launch_assemble_f64(hipStream_t s, const AsmArgs &a, bool sub, bool mat) {
+// dynamic LDS that holds a kernel to at most wg_per_cu resident workgroups per
+// CU (160 KB of LDS each; 512 bytes of slack so that the rounding of the
+// allocation cannot cut one more)
+static size_t lds_for_cap(const void *kernel, int wg_per_cu) {
+    if (wg_per_cu <= 0) return 0;
+    hipFuncAttributes at{};
+    if (hipFuncGetAttributes(&at, kernel) != hipSuccess) return 0;
+    const size_t want = (size_t)163840 / (size_t)wg_per_cu - 512;
+    return want > at.sharedSizeBytes ? want - at.sharedSizeBytes : 0;
+}
+
+int sub_items_per_cu(int precision) {
+    const void *k = precision == 0 ? (const void *)&k_asm2<double, 0, true, true>
+                    : precision == 1 ? (const void *)&k_asm2<float, 1, true, true>
+                                     : (const void *)&k_asm2<float, 2, true, true>;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, 64, 0) != hipSuccess) return 0;
+    return n;
+}
+
+void launch_assemble_f64(hipStream_t s, const AsmArgs &a, bool sub, bool mat, int wg_per_cu) {
     if (a.n_items <= 0) return;
     dim3 grid((unsigned)(sub ? a.n_items : (a.n_items + 1) / 2)), block(64);
     if (!sub) {
         if (mat) hipLaunchKernelGGL((k_asm2<double, 0, false, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((k_asm2<double, 0, false, false>), grid, block, 0, s, a);
     } else {
-        if (mat) hipLaunchKernelGGL((k_asm2<double, 0, true, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_asm2<double, 0, true, false>), grid, block, 0, s, a);
+        if (mat) {
+            const size_t dyn = lds_for_cap((const void *)&k_asm2<double, 0, true, true>, wg_per_cu);
+            hipLaunchKernelGGL((k_asm2<double, 0, true, true>), grid, block, dyn, s, a);
+        } else {
+            hipLaunchKernelGGL((k_asm2<double, 0, true, false>), grid, block, 0, s, a);
+        }
     }
 }
 
-void launch_assemble_mixed(hipStream_t s, const AsmArgs &a, bool sub, bool mat, int fp16) {
+void launch_assemble_mixed(hipStream_t s, const AsmArgs &a, bool sub, bool mat, int fp16, int wg_per_cu) {
     if (a.n_items <= 0) return;
     dim3 grid((unsigned)(sub ? a.n_items : (a.n_items + 1) / 2)), block(64);
 #define VMS_L(MODE)                                                                              \
@@ -1060,7 +1084,9 @@ void launch_assemble_mixed(hipStream_t s, const AsmArgs &a, bool sub, bool mat, 
             if (mat) hipLaunchKernelGGL((k_asm2<float, MODE, false, true>), grid, block, 0, s, a); \
             else hipLaunchKernelGGL((k_asm2<float, MODE, false, false>), grid, block, 0, s, a);    \
         } else {                                                                                 \
-            if (mat) hipLaunchKernelGGL((k_asm2<float, MODE, true, true>), grid, block, 0, s, a);  \
+            if (mat) hipLaunchKernelGGL((k_asm2<float, MODE, true, true>), grid, block,            \
+                                        lds_for_cap((const void *)&k_asm2<float, MODE, true, true>, \
+                                                    wg_per_cu), s, a);                             \
             else hipLaunchKernelGGL((k_asm2<float, MODE, true, false>), grid, block, 0, s, a);     \
         }                                                                                        \
     } while (0)

@@ -154,7 +154,10 @@ inline void set_params(AsmArgs &a, double rho, double mu, double dt, double thet
     a.tau_a = c_t / (dt * dt);
     a.tau_b = 3.0 * c_i * nu * nu;
 }
-void launch_assemble_f64(hipStream_t s, const AsmArgs &a, bool sub, bool mat);
+// wg_per_cu > 0 (sub-cell items only): dynamic LDS so that at most that many
+// workgroups share a CU, leaving the rest of its waves to another stream's
+// kernel
+void launch_assemble_f64(hipStream_t s, const AsmArgs &a, bool sub, bool mat, int wg_per_cu = 0);
 
 // one unit of the persistent batched assembly: items [first, first + count) of
 // tree `tree`'s OUT-element list (sub = 0) or sub-cell work-item list (sub = 1)
@@ -170,7 +173,10 @@ struct BatchUnit {
 void launch_assemble_batch(hipStream_t s, int precision, const AsmArgs *std_args,
                            const AsmArgs *sub_args, const BatchUnit *units, int64_t n_units,
                            unsigned long long *counter, int n_groups);
-void launch_assemble_mixed(hipStream_t s, const AsmArgs &a, bool sub, bool mat, int fp16);
+void launch_assemble_mixed(hipStream_t s, const AsmArgs &a, bool sub, bool mat, int fp16, int wg_per_cu = 0);
+// resident workgroups per CU of the sub-cell item kernel of a precision form
+// (0 FP64, 1 BF16x3, 2 FP16x2; with the matrix), from its registers and LDS
+int sub_items_per_cu(int precision);
 
 // CSR values from element-matrix records (see k_gather). A block whose
 // stride carries VS_LATE (a positive stride only) has records of sub-cell or
