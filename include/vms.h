@@ -414,10 +414,11 @@ int vms_last_timing(vms_ctx *ctx, float *ms);
  * current device, default priority), started by an event after the OUT
  * kernel, while the context stream sums the blocks without late records; the
  * context stream then waits for the second stream and sums the late blocks.
- * When the INTERCEPTED items are estimated to take well under the gather,
- * fewer of their workgroups share a CU (extra LDS requested at their launch),
- * which leaves the HBM-bound gather more waves; the estimate uses the number
- * of sub-cell points and the gather's bytes at rates measured on MI355X.
+ * When the relabel and the INTERCEPTED items are estimated to take well under
+ * the gather, fewer of their workgroups share a CU (extra LDS requested at
+ * their launch), which leaves the HBM-bound gather more waves; the estimate
+ * uses the numbers of labels and sub-cell points and the gather's bytes at
+ * rates measured on MI355X.
  * All of the call's work is ordered before later work on the context stream,
  * and the outputs are bit for bit those of the in-order schedule (same
  * records, same per-block summation order). Off: every stage in order on the

@@ -310,7 +310,7 @@ struct vms_ctx {
     // learned mode: the INTERCEPTED elements (list positions) at or above the
     // threshold on the background-triangle count, and the others
     int32_t split_bt = -1;
-    int sub_cap = -1;  // workgroups per CU of the sub-cell items beside the gather (0: no cap; -1: not yet set)
+    int sub_cap = -1, rel_cap = 0;  // workgroups per CU beside the gather (side_caps; -1: not yet set)
     int64_t n_sq_net = 0, n_sq_exact = 0;
     int32_t *d_sq_net = nullptr, *d_sq_exact = nullptr;
     int32_t *d_bt_ids = nullptr;
@@ -523,7 +523,7 @@ void gather_bt(vms_ctx *c, std::vector<int64_t> &off, std::vector<int32_t> &ids)
 // recomputes every label and verifies each element's point count on the device
 // (a mismatch sets the overflow flag, reported by vms_sizes); no host
 // synchronisation.
-int run_subquad(vms_ctx *c, bool first, hipStream_t st) {
+int run_subquad(vms_ctx *c, bool first, hipStream_t st, int wg_per_cu = 0) {
     if (c->n_sq == 0) return VMS_OK;
     vmsk::GeoArgs g{};
     for (int k = 0; k < 3; ++k) g.origin[k] = c->origin[k];
@@ -604,10 +604,10 @@ int run_subquad(vms_ctx *c, bool first, hipStream_t st) {
         an.learned.grid = vmsm::mlp_grid(c->mlp);
         an.learned.margin = vmsm::mlp_margin(c->mlp);
         an.learned.min_bt = 0;
-        if (ae.n_order) vmsk::launch_subquad(st, c->surf.S, g, ae, 1);
+        if (ae.n_order) vmsk::launch_subquad(st, c->surf.S, g, ae, 1, wg_per_cu);
         if (an.n_order) vmsk::launch_subquad(st, c->surf.S, g, an, 1);
     } else {
-        vmsk::launch_subquad(st, c->surf.S, g, a, 1);
+        vmsk::launch_subquad(st, c->surf.S, g, a, 1, wg_per_cu);
     }
     HIPCHK(c, hipGetLastError());
     return VMS_OK;
@@ -1387,32 +1387,36 @@ static int ensure_side(vms_ctx *c) {
 // OUT elements are done, sums the blocks without late records meanwhile, joins,
 // and sums the late blocks; every block is summed by the same code in the same
 // order either way, so the outputs are identical.
-// Workgroups per CU of the sub-cell item kernel when it runs beside the CSR
-// gather (overlapped schedule). The gather is bound by HBM and needs many
-// waves in flight; when the items' estimated time is well below the gather's,
-// fewer item waves per SIMD leave it that parallelism and still finish inside
-// it. Estimates from rates measured on this GPU: 0.51 ns per sub-cell point
-// over the whole GPU in FP64, 0.33 ns in the mixed forms; the gather's bytes
-// (records read, values written) at 4.7 TB/s (FP64 values) or 4.0 TB/s
-// (FP32). Two-box workload: FP64 4 per CU instead of 8 (step 65.1 -> 62.3
-// ms), FP16x2 8 instead of 12 (44.0 -> 42.6 ms); no cap where the items
-// outlast the gather (sphere workloads). 0 = no cap.
-static int sub_wg_cap(vms_ctx *c) {
-    if (c->sub_cap >= 0) return c->sub_cap;
+// Workgroups per CU of the second stream's kernels (exact relabel, sub-cell
+// items) while they run beside the CSR gather in the overlapped schedule. The
+// gather is bound by HBM and needs many waves in flight; the second stream's
+// kernels are latency-bound and lose little when fewer of their waves are
+// resident. When their estimated work fits well inside the gather's (under
+// 0.8 of it), the sub-cell items keep ceil(w/2) of their w waves per SIMD and
+// the relabel a third of its workgroups per CU (the choices that measured
+// best on MI355X); otherwise neither is limited. Estimates from rates measured
+// on this GPU: 0.51 ns per sub-cell point over the whole GPU in FP64, 0.33 ns
+// in the mixed forms, 1.5e10 exact labels per second in the relabel, the
+// gather's bytes (records read, values written) at 4.7 TB/s (FP64 values) or
+// 4.0 TB/s (FP32). 0 = no limit.
+static void side_caps(vms_ctx *c, bool relabel, int &items_cap, int &relabel_cap) {
+    items_cap = relabel_cap = 0;
     const bool fp64 = c->prm.precision == VMS_FP64;
     const double vb = fp64 ? 8.0 : 4.0;
-    const double t_sub = (double)c->n_subgp * (fp64 ? 0.51e-9 : 0.33e-9);
+    const double t_items = (double)c->n_subgp * (fp64 ? 0.51e-9 : 0.33e-9);
+    const double t_rel = relabel ? (double)c->n_labelled / 1.5e10 : 0.0;
     const double recs = (double)(c->n_std + c->n_sub_items);
     const double t_gather = (recs * 1024.0 + (double)c->mesh.nnz) * vb / (fp64 ? 4.7e12 : 4.0e12);
-    const int per_cu = vmsk::sub_items_per_cu(fp64 ? 0 : (c->prm.precision == VMS_MIXED_BF16 ? 1 : 2));
-    int cap = 0;
-    if (per_cu >= 8 && t_gather > 0.0) {
-        const int w_full = per_cu / 4;  // waves per SIMD: one-wave workgroups, 4 SIMDs per CU
-        const int w = (int)std::ceil((double)w_full * t_sub / t_gather);
-        if (w < w_full) cap = 4 * std::max(1, w);
+    if (!(t_items + t_rel < 0.8 * t_gather)) return;
+    if (c->sub_cap < 0) {
+        const int per_cu = vmsk::sub_items_per_cu(fp64 ? 0 : (c->prm.precision == VMS_MIXED_BF16 ? 1 : 2));
+        const int w = per_cu / 4;  // waves per SIMD: one-wave workgroups, 4 SIMDs per CU
+        c->sub_cap = w >= 2 ? 4 * ((w + 1) / 2) : 0;
+        const int sq = vmsk::subquad_per_cu();
+        c->rel_cap = sq >= 3 ? (sq + 2) / 3 : 0;
     }
-    c->sub_cap = cap;
-    return cap;
+    items_cap = c->sub_cap;
+    relabel_cap = relabel ? c->rel_cap : 0;
 }
 
 static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *resid, uint32_t flags,
@@ -1433,6 +1437,8 @@ static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *re
     }
     hipStream_t ms = c->stream, ls = split ? c->side : c->stream;
     c->last_split = split;
+    int items_cap = 0, relabel_cap = 0;
+    if (split) side_caps(c, relabel, items_cap, relabel_cap);
     if (c->timing) HIPCHK(c, hipEventRecord(c->ev[0], ms));
     if (relabel && !split) {
         int rc = run_subquad(c, false, ms);
@@ -1467,7 +1473,7 @@ static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *re
         HIPCHK(c, hipEventRecord(c->fork, ms));
         HIPCHK(c, hipStreamWaitEvent(ls, c->fork, 0));
         if (c->timing) HIPCHK(c, hipEventRecord(c->ev[6], ls));
-        if (relabel) late_rc = run_subquad(c, false, ls);
+        if (relabel) late_rc = run_subquad(c, false, ls, relabel_cap);
         if (c->timing) HIPCHK(c, hipEventRecord(c->ev[7], ls));
     }
     // INTERCEPTED elements: kept sub-cell points
@@ -1478,9 +1484,8 @@ static int assemble_impl(vms_ctx *c, const vms_fields *f, void *vals, double *re
         a.pt_cnt = c->d_sub_cnt;
         a.entries = c->d_entries;
         a.slot0 = c->n_std;
-        const int cap = split ? sub_wg_cap(c) : 0;
-        if (fp64) vmsk::launch_assemble_f64(ls, a, true, mat, cap);
-        else vmsk::launch_assemble_mixed(ls, a, true, mat, c->prm.precision == VMS_MIXED_FP16, cap);
+        if (fp64) vmsk::launch_assemble_f64(ls, a, true, mat, items_cap);
+        else vmsk::launch_assemble_mixed(ls, a, true, mat, c->prm.precision == VMS_MIXED_FP16, items_cap);
         HIPCHK(c, hipGetLastError());
     }
     if (late_rc == VMS_OK && c->wbc && c->n_surf_items) {

@@ -1042,7 +1042,7 @@ void launch_gather_list(hipStream_t s, bool fp64, const void *em, const int64_t 
 // dynamic LDS that holds a kernel to at most wg_per_cu resident workgroups per
 // CU (160 KB of LDS each; 512 bytes of slack so that the rounding of the
 // allocation cannot cut one more)
-static size_t lds_for_cap(const void *kernel, int wg_per_cu) {
+size_t lds_for_cap(const void *kernel, int wg_per_cu) {
     if (wg_per_cu <= 0) return 0;
     hipFuncAttributes at{};
     if (hipFuncGetAttributes(&at, kernel) != hipSuccess) return 0;

@@ -314,15 +314,24 @@ void launch_zero_u64(hipStream_t s, unsigned long long *c) {
 }
 
 void launch_subquad(hipStream_t s, const SurfDev &S, const GeoArgs &g, const SubqArgs &a,
-                    int pass) {
+                    int pass, int wg_per_cu) {
     const int64_t n = a.order ? a.n_order : a.n;
     if (n <= 0) return;
-    if (a.learned.net.theta)
+    if (a.learned.net.theta) {
         hipLaunchKernelGGL(k_subquad<1>, dim3((unsigned)n), dim3(64), 0, s, S, g, a, pass);
-    else if (a.normal && pass == 1)
+    } else if (a.normal && pass == 1) {
         hipLaunchKernelGGL(k_subquad<2>, dim3((unsigned)n), dim3(64), 0, s, S, g, a, pass);
-    else
-        hipLaunchKernelGGL(k_subquad<0>, dim3((unsigned)n), dim3(64), 0, s, S, g, a, pass);
+    } else {
+        const size_t dyn = pass == 1 ? lds_for_cap((const void *)&k_subquad<0>, wg_per_cu) : 0;
+        hipLaunchKernelGGL(k_subquad<0>, dim3((unsigned)n), dim3(64), dyn, s, S, g, a, pass);
+    }
+}
+
+int subquad_per_cu() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void *)&k_subquad<0>, 64, 0) != hipSuccess)
+        return 0;
+    return n;
 }
 
 __global__ void k_edge_convex(SurfDev S, const int32_t *t1, const int32_t *t2, const int8_t *corner,

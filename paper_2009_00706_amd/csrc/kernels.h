@@ -97,7 +97,12 @@ struct SubqArgs {
     const uint8_t *bt_lc;
     const uint8_t *nmask;
 };
-void launch_subquad(hipStream_t s, const SurfDev &S, const GeoArgs &g, const SubqArgs &a, int pass);
+// wg_per_cu > 0: the exact relabel pass (k_subquad<0>, pass 1) gets dynamic LDS
+// so that at most that many workgroups share a CU
+void launch_subquad(hipStream_t s, const SurfDev &S, const GeoArgs &g, const SubqArgs &a, int pass,
+                    int wg_per_cu = 0);
+// resident workgroups per CU of the exact relabel kernel
+int subquad_per_cu();
 // bad[e] = 1 when vertex corner[e] of triangle t2[e] lies strictly outside the
 // plane of triangle t1[e] (exact orientation): the surface is not convex at
 // that edge
@@ -177,6 +182,8 @@ void launch_assemble_mixed(hipStream_t s, const AsmArgs &a, bool sub, bool mat, 
 // resident workgroups per CU of the sub-cell item kernel of a precision form
 // (0 FP64, 1 BF16x3, 2 FP16x2; with the matrix), from its registers and LDS
 int sub_items_per_cu(int precision);
+// dynamic LDS that holds a kernel to at most wg_per_cu resident workgroups per CU
+size_t lds_for_cap(const void *kernel, int wg_per_cu);
 
 // CSR values from element-matrix records (see k_gather). A block whose
 // stride carries VS_LATE (a positive stride only) has records of sub-cell or
