@@ -1413,7 +1413,8 @@ static void side_caps(vms_ctx *c, bool relabel, int &items_cap, int &relabel_cap
         const int w = per_cu / 4;  // waves per SIMD: one-wave workgroups, 4 SIMDs per CU
         c->sub_cap = w >= 2 ? 4 * ((w + 1) / 2) : 0;
         const int sq = vmsk::subquad_per_cu();
-        c->rel_cap = sq >= 3 ? (sq + 2) / 3 : 0;
+        // caps of 3 or more keep a capped workgroup within 64 KB of LDS
+        c->rel_cap = sq >= 9 ? (sq + 2) / 3 : 0;
     }
     items_cap = c->sub_cap;
     relabel_cap = relabel ? c->rel_cap : 0;
