@@ -605,7 +605,7 @@ int run_subquad(vms_ctx *c, bool first, hipStream_t st, int wg_per_cu = 0) {
         an.learned.margin = vmsm::mlp_margin(c->mlp);
         an.learned.min_bt = 0;
         if (ae.n_order) vmsk::launch_subquad(st, c->surf.S, g, ae, 1, wg_per_cu);
-        if (an.n_order) vmsk::launch_subquad(st, c->surf.S, g, an, 1);
+        if (an.n_order) vmsk::launch_subquad(st, c->surf.S, g, an, 1, wg_per_cu);
     } else {
         vmsk::launch_subquad(st, c->surf.S, g, a, 1, wg_per_cu);
     }

@@ -318,9 +318,11 @@ void launch_subquad(hipStream_t s, const SurfDev &S, const GeoArgs &g, const Sub
     const int64_t n = a.order ? a.n_order : a.n;
     if (n <= 0) return;
     if (a.learned.net.theta) {
-        hipLaunchKernelGGL(k_subquad<1>, dim3((unsigned)n), dim3(64), 0, s, S, g, a, pass);
+        const size_t dyn = pass == 1 ? lds_for_cap((const void *)&k_subquad<1>, wg_per_cu) : 0;
+        hipLaunchKernelGGL(k_subquad<1>, dim3((unsigned)n), dim3(64), dyn, s, S, g, a, pass);
     } else if (a.normal && pass == 1) {
-        hipLaunchKernelGGL(k_subquad<2>, dim3((unsigned)n), dim3(64), 0, s, S, g, a, pass);
+        const size_t dyn = lds_for_cap((const void *)&k_subquad<2>, wg_per_cu);
+        hipLaunchKernelGGL(k_subquad<2>, dim3((unsigned)n), dim3(64), dyn, s, S, g, a, pass);
     } else {
         const size_t dyn = pass == 1 ? lds_for_cap((const void *)&k_subquad<0>, wg_per_cu) : 0;
         hipLaunchKernelGGL(k_subquad<0>, dim3((unsigned)n), dim3(64), dyn, s, S, g, a, pass);

@@ -97,8 +97,8 @@ struct SubqArgs {
     const uint8_t *bt_lc;
     const uint8_t *nmask;
 };
-// wg_per_cu > 0: the exact relabel pass (k_subquad<0>, pass 1) gets dynamic LDS
-// so that at most that many workgroups share a CU
+// wg_per_cu > 0: the relabel pass (pass 1) gets dynamic LDS so that at most
+// that many workgroups share a CU
 void launch_subquad(hipStream_t s, const SurfDev &S, const GeoArgs &g, const SubqArgs &a, int pass,
                     int wg_per_cu = 0);
 // resident workgroups per CU of the exact relabel kernel
