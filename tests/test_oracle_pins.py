@@ -5,6 +5,7 @@ values of the paper, closed forms from exact 1D integrals, invariants, exact
 rational arithmetic, brute force, or analytic point sets.
 """
 import itertools
+import os
 from fractions import Fraction
 
 import numpy as np
@@ -58,10 +59,31 @@ def one_element(oracle, h=0.3, seed=0, **kw):
 # ---------------------------------------------------------------------------
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _sketch():
+    """The printed values of the adaptive-quadrature sketch (tests/golden)."""
+    vals, cells = {}, []
+    with open(os.path.join(GOLDEN, "adaptive_quadrature_sketch.txt")) as fh:
+        for line in fh:
+            f = line.split("#", 1)[0].split()
+            if not f:
+                continue
+            if f[0] == "cell":
+                ex, ey, side, lvl, i, j = (int(v) for v in f[1:7])
+                cells.append((ex, ey, side, lvl, i, j, float(f[7]), float(f[8])))
+            else:
+                vals[f[0]] = (float(f[1]), int(f[2]))
+    return vals, cells
+
+
 def test_gauss_abscissae_match_paper(oracle):
-    # printed [0,1] abscissae of the Gauss-point figure
-    assert abs(oracle.G_MINUS - 0.2113248654) < 1e-10
-    assert abs(oracle.G_PLUS - 0.78867513459) < 1e-11
+    # printed [0,1] abscissae of the Gauss-point figure, to their printed digits
+    vals, _ = _sketch()
+    for name, g in (("g_minus", oracle.G_MINUS), ("g_plus", oracle.G_PLUS)):
+        v, digits = vals[name]
+        assert abs(g - v) <= 0.5 * 10.0 ** -digits
     from decimal import Decimal, getcontext
     getcontext().prec = 60
     s3 = Decimal(3).sqrt()
@@ -495,6 +517,46 @@ def test_adaptive_quadrature_stop_rule_and_order(oracle):
         m = sq["lvl"] == lv
         cells = (el[m] << 12) | (key[m] >> (3 * (3 - lv) + 3))
         assert np.all(np.unique(cells, return_counts=True)[1] == 8)
+
+
+def test_subcell_points_sit_where_the_sketch_draws_them(oracle):
+    # the sketch of the adaptive quadrature prints its points: a point of split
+    # level l lies at (i + g) / 2^l of its element's side, g one of the two
+    # printed offsets, (i, j) its sub-cell; the fixture's worked cells follow
+    # that rule to their printed digits
+    vals, cells = _sketch()
+    gm, gp = vals["g_minus"][0], vals["g_plus"][0]
+    for ex, ey, side, lvl, i, j, x, y in cells:
+        c = side / 2 ** lvl
+        assert abs(ex + c * (i + gm) - x) < 1e-9 and abs(ey + c * (j + gm) - y) < 1e-9
+    # every kept point of the reference's adaptive quadrature (its C routine)
+    # follows it at every split level, and the key decoding agrees
+    c0 = np.array([0.5, 0.5, 0.5]) + I.BODY_OFFSET
+    s = I.icosphere(2, 0.3, c0)
+    t = I.uniform_octree(2)
+    ms = oracle.derive_mesh(t.ax, t.ay, t.az, t.level, t.max_level)
+    mk, _, _ = oracle.markers(t, ms, s)
+    cut = np.nonzero(mk == oracle.INTERCEPTED)[0]
+    h = oracle.element_h(t)
+    corner = np.asarray(t.origin, np.float64)[None] + t.root_len * np.stack(
+        [t.ax, t.ay, t.az], 1).astype(np.float64) / float(1 << t.max_level)
+    for depth in (2, 3):
+        sq = oracle.subquad(t, s, cut, depth)
+        el, lvl, xyz = sq["el"], sq["lvl"].astype(np.int64), sq["xyz"]
+        assert set(np.unique(lvl)) == set(range(1, depth + 1))
+        u = (xyz - corner[el]) / h[el, None] * (2.0 ** lvl)[:, None]
+        i = np.floor(u)
+        f = u - i
+        assert np.all((i >= 0) & (i < (2 ** lvl)[:, None]))
+        near = np.minimum(np.abs(f - gm), np.abs(f - gp))
+        assert near.max() < 1e-9
+        # both offsets occur on every axis at every level
+        for lv in range(1, depth + 1):
+            for ax in range(3):
+                fl = f[lvl == lv, ax]
+                assert np.any(np.abs(fl - gm) < 1e-9) and np.any(np.abs(fl - gp) < 1e-9)
+        xi, _ = oracle.subgp_xi(t, el, sq["key"], sq["lvl"], depth)
+        np.testing.assert_allclose(corner[el] + (xi + 1.0) / 2.0 * h[el, None], xyz, rtol=0, atol=1e-15)
 
 
 def test_adaptive_quadrature_sphere_converges_to_polyhedron_volume(oracle):
