@@ -7,6 +7,9 @@
   OUT (the marker rule of Alg. 4) and no sub-cell quadrature happens, but the
   weak boundary terms still live on the body's surface points, inside one OUT
   element: residual and Jacobian to 1e-12 against the reference.
+* In-out classification of empty and ragged point counts (0, 1, and one
+  below, at and above a 128-point workgroup): labels bit-exact against the
+  reference; an empty call writes nothing.
 """
 import numpy as np
 import pytest
@@ -85,3 +88,33 @@ def test_body_inside_one_element_weak_terms(vms, oracle):
     # the surface terms are there: far above the tolerance
     assert np.linalg.norm(res - R_vol) > 1e-6 * np.linalg.norm(R)
     asm.close()
+
+
+def test_inout_empty_and_ragged_counts(vms, oracle):
+    import torch
+    c = np.array([0.5, 0.5, 0.5]) + I.BODY_OFFSET
+    s = I.icosphere(2, 0.2, c)
+    rng = np.random.default_rng(21)
+    h = vms.inout_prepare(s)
+    try:
+        for n in (0, 1, 127, 128, 129, 1000):
+            print(f"in-out of {n} points", flush=True)
+            p = c + rng.uniform(-0.3, 0.3, size=(n, 3))
+            ref, _ = oracle.label_points(s, p) if n else (np.zeros(0, np.uint8), None)
+            pt = torch.tensor(p.reshape(n, 3), dtype=torch.float64, device="cuda")
+            cols = [pt[:, k].contiguous() for k in range(3)]
+            # one guard label after the points: no call may write past n
+            for call in ("one-shot", "prepared", "static"):
+                lab = torch.full((n + 1,), 7, dtype=torch.uint8, device="cuda")
+                if call == "one-shot":
+                    vms.inout_classify(s, *cols, lab[:n])
+                elif call == "prepared":
+                    vms.inout_classify_prepared(h, *cols, lab[:n])
+                else:
+                    vms.inout_classify_static(s, *cols, lab[:n])
+                torch.cuda.synchronize()
+                got = lab.cpu().numpy()
+                assert got[n] == 7, call
+                assert np.array_equal(got[:n], ref), (call, n)
+    finally:
+        vms.inout_release(h)
