@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned + mixed step")
     ap.add_argument("--no-scatter", action="store_true", help="skip the atomic-scatter comparison")
     ap.add_argument("--no-normal", action="store_true", help="skip the normal-based filter comparison")
+    ap.add_argument("--no-classify", action="store_true", help="skip the standalone in-out classification rate")
     ap.add_argument("--learned-standalone", action="store_true",
                     help="also time the learned filter on the kept sub-cell points outside the assembly")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -374,6 +375,40 @@ def normal_filter(torch, vms, tree, surf, f, reps=7):
     out["convex"] = [bool(x) for x in convex]
     out["speedup"] = out["exact"]["relabel_ms"] / out["normal"]["relabel_ms"]
     return out
+
+
+def classify_rate(torch, vms, tree, surf, reps=5):
+    """Exact in-out tests per second of the standalone classification
+    (inout_classify_prepared: bin grid of the surface, +x ray parity with exact
+    predicates) on the workload's kept sub-cell points, against the labels of
+    the adaptive quadrature (all OUT), HIP events on the handle's stream."""
+    asm = vms.Assembler(tree, surf, vms.make_params(quad_depth=3))
+    xyz = asm.export(vms.VMS_EXPORT_SUBGP)["xyz"]
+    asm.close()
+    n = int(xyz.shape[0])
+    cols = [torch.as_tensor(np.ascontiguousarray(xyz[:, k]), device="cuda") for k in range(3)]
+    del xyz
+    lab = torch.full((n,), 7, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()   # the copies and the fill ran on torch's stream
+    stream = torch.cuda.Stream()
+    h = vms.inout_prepare(surf, stream.cuda_stream)
+    try:
+        vms.inout_classify_prepared(h, *cols, lab)
+        stream.synchronize()
+        all_out = bool((lab == 0).all())
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            vms.inout_classify_prepared(h, *cols, lab)
+        b.record(stream)
+        b.synchronize()
+        ms = a.elapsed_time(b) / reps
+    finally:
+        vms.inout_release(h)
+    return {"points": n, "exact_tests_per_s": n / (ms * 1e-3), "ms_per_call": ms,
+            "labels_all_out": all_out,
+            "note": "the kept sub-cell points of the workload, classified one by one without their "
+                    "elements (the quadrature's own tests are the top-level inout_tests_per_s)"}
 
 
 def learned_threshold(torch, vms, asm, lf, thresholds=(0, 16, 32, 64, 128, 1 << 30), reps=5):
@@ -774,6 +809,9 @@ def main_single(args):
     if surf is not None and not args.no_normal:
         log("normal-based filter")
         out["normal_filter"] = normal_filter(torch, vms, tree, surf, f)
+    if surf is not None and not args.no_classify:
+        log("standalone in-out classification")
+        out["inout_classify"] = classify_rate(torch, vms, tree, surf)
     if surf is not None and args.learned_standalone:
         out["learned_inout"] = learned_inout(torch, vms, tree, surf,
                                              cfg.get("learned_train_samples", 1_000_000))
