@@ -379,7 +379,7 @@ def normal_filter(torch, vms, tree, surf, f, reps=7):
 
 def classify_rate(torch, vms, tree, surf, reps=5):
     """Exact in-out tests per second of the standalone classification
-    (inout_classify_prepared: bin grid of the surface, +x ray parity with exact
+    (inout_classify_prepared: bin grid of the surface, ray parity along x with exact
     predicates) on the workload's kept sub-cell points, against the labels of
     the adaptive quadrature (all OUT), HIP events on the handle's stream."""
     asm = vms.Assembler(tree, surf, vms.make_params(quad_depth=3))
@@ -496,7 +496,7 @@ def learned_inout(torch, vms, tree, surf, n_train=1_000_000):
                         "exact_tests_per_s": q.shape[0] / tq[False],
                         "learned_tests_per_s": q.shape[0] / tq[True], "gain": tq[False] / tq[True],
                         "sample": "90% within 0.02 of the surface, the rest uniform in its box grown by 0.1"},
-            "note": "kept sub-cell points of the workload; exact: +x ray parity with exact predicates; "
+            "note": "kept sub-cell points of the workload; exact: ray parity along x with exact predicates; "
                     "learned: FP16-MFMA network, exact test inside the per-cell margin"}
 
 

@@ -156,7 +156,7 @@ int pack_surface(const vms_surface *s, SurfacePack &P, std::string &err) {
             P.tbox[6 * t + 3 + k] = std::max(a, std::max(b, c));
         }
     }
-    // (y, z) bins for +x rays
+    // (y, z) bins for rays along +x or -x
     int nb = (int)std::ceil(std::sqrt((double)nt));
     nb = std::max(1, std::min(nb, 1024));
     S.n_tri = (int32_t)nt;

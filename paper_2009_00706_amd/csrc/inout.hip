@@ -3,10 +3,11 @@
 // Labels are exact point-in-polyhedron membership (1 = inside or on the
 // surface, 0 = fluid), the truth that the paper's normal-based test (Alg. 5)
 // and its ray-tracing fallback estimate:
-//   * ray_label: parity of crossings of the segment from P along +x to a point
-//     beyond the surface's box, against the triangles of P's (y, z) bin; on a
-//     degenerate crossing (through an edge or a vertex) the next direction of
-//     a fixed list is tried against all triangles;
+//   * ray_label: parity of crossings of the segment from P along +x or -x
+//     (towards the nearer end of the surface's box) to a point beyond that
+//     box, against the triangles of P's (y, z) bin; on a degenerate crossing
+//     (through an edge or a vertex) the next direction of a fixed list is
+//     tried against all triangles;
 //   * local_label: label(V) XOR parity(P -> V) for a corner V of the element
 //     holding P, against the element's background triangles B_T (every
 //     triangle whose box meets the closed element, so every triangle the

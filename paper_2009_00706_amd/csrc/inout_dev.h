@@ -3,10 +3,11 @@
 // Labels are exact point-in-polyhedron membership (1 = inside or on the
 // surface, 0 = fluid), the truth that the paper's normal-based test (Alg. 5)
 // and its ray-tracing fallback estimate:
-//   * ray_label: parity of crossings of the segment from P along +x to a point
-//     beyond the surface's box, against the triangles of P's (y, z) bin; on a
-//     degenerate crossing (through an edge or a vertex) the next direction of
-//     a fixed list is tried against all triangles;
+//   * ray_label: parity of crossings of the segment from P along +x or -x
+//     (towards the nearer end of the surface's box) to a point beyond that
+//     box, against the triangles of P's (y, z) bin; on a degenerate crossing
+//     (through an edge or a vertex) the next direction of a fixed list is
+//     tried against all triangles;
 //   * local_label: label(V) XOR parity(P -> V) for a corner V of the element
 //     holding P, against the element's background triangles B_T (every
 //     triangle whose box meets the closed element, so every triangle the
@@ -71,13 +72,18 @@ __device__ static int ray_label(const SurfDev &S, const double *P, unsigned long
         if (P[k] < S.lo[k] || P[k] > S.hi[k]) return 0;
     int by = bin_of(P[1], S.y0, S.iny, S.nby), bz = bin_of(P[2], S.z0, S.inz, S.nbz);
     int bin = bz * S.nby + by;
-    double Q[3] = {__dadd_rn(S.hi[0], 1.0), P[1], P[2]};
+    // along -x when the surface's box ends nearer on that side: only the
+    // triangles of the bin on that side of P can be crossed
+    const bool neg = __dsub_rn(P[0], S.lo[0]) < __dsub_rn(S.hi[0], P[0]);
+    double Q[3] = {neg ? __dsub_rn(S.lo[0], 1.0) : __dadd_rn(S.hi[0], 1.0), P[1], P[2]};
     int cnt = 0;
     bool deg = false;
     for (int i = S.bin_off[bin]; i < S.bin_off[bin + 1]; ++i) {
         int t = S.bin_tri[i];
         const double *bx = S.tbox + 6 * (int64_t)t;
-        if (bx[3] < P[0] || bx[1] > P[1] || bx[4] < P[1] || bx[2] > P[2] || bx[5] < P[2]) continue;
+        if ((neg ? bx[0] > P[0] : bx[3] < P[0]) || bx[1] > P[1] || bx[4] < P[1] || bx[2] > P[2] ||
+            bx[5] < P[2])
+            continue;
         double a[3], b[3], c[3];
         tri_load(S, t, a, b, c);
         int r = segment_triangle(P, Q, a, b, c);

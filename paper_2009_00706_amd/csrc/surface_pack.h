@@ -1,6 +1,6 @@
 // Host packing of a triangle surface for the exact in-out kernels of libvms
 // (internal header): triangle coordinates and boxes, and a (y, z) bin grid of
-// the triangles for +x rays. The device pointers of S are left unset; the
+// the triangles for rays along +x or -x. The device pointers of S are left unset; the
 // caller places the four arrays in device memory and fills them in.
 #pragma once
 #include <stdint.h>
