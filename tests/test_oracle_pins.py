@@ -421,6 +421,56 @@ def test_labels_sphere_analytic(oracle):
     assert np.all(lab_v == 1)
 
 
+def _winding_number(surf, p):
+    """Generalised winding number: the solid angles of the triangles seen from
+    each point (Van Oosterom and Strackee's formula) summed over 4 pi; 1 inside
+    a closed, outward-oriented surface, 0 outside."""
+    w = np.zeros(p.shape[0])
+    for t in surf.tris:
+        A, B, C = (surf.verts[t[k]][None] - p for k in range(3))
+        la, lb, lc = (np.linalg.norm(X, axis=1) for X in (A, B, C))
+        num = np.einsum("ij,ij->i", A, np.cross(B, C))
+        den = (la * lb * lc + np.einsum("ij,ij->i", A, B) * lc + np.einsum("ij,ij->i", A, C) * lb
+               + np.einsum("ij,ij->i", B, C) * la)
+        w += 2.0 * np.arctan2(num, den)
+    return w / (4.0 * np.pi)
+
+
+def test_labels_against_winding_number(oracle):
+    # an independent definition of inside, on a convex body (including the
+    # shell between the polyhedron and its sphere), a dented (non-convex) body
+    # and two separate filleted boxes
+    c = np.array([0.5, 0.5, 0.5]) + I.BODY_OFFSET
+    ico = I.icosphere(3, 0.2, c)
+    v = ico.verts.copy()
+    v[0] = c + (v[0] - c) * 0.6
+    dent = I.Surface(v, ico.tris.copy(), {"kind": "dented icosphere"})
+    boxes = I.two_boxes(4)
+    rng = np.random.default_rng(31)
+    for surf in (ico, dent, boxes):
+        lo, hi = surf.verts.min(0), surf.verts.max(0)
+        pad = 0.1 * (hi - lo)
+        p = rng.uniform(lo - pad, hi + pad, (1500, 3))
+        # points near vertex 0 (the dent) and near the surface
+        k = 300
+        p[:k] = surf.verts[rng.integers(0, surf.verts.shape[0], k)] + rng.normal(scale=0.02 * (hi - lo).max(), size=(k, 3))
+        p[k:k + 100] = surf.verts[0] + rng.normal(scale=0.05 * (hi - lo).max(), size=(100, 3))
+        if surf is dent:
+            # inside the dent: between the pushed vertex and its place on the
+            # sphere (inside the convex hull, outside the body)
+            s_ = rng.uniform(0.1, 0.9, 100)[:, None]
+            p[k + 100:k + 200] = v[0] + s_ * (ico.verts[0] - v[0]) + rng.normal(scale=1e-3, size=(100, 3))
+        lab, _ = oracle.label_points(surf, p)
+        w = _winding_number(surf, p)
+        clear = np.abs(w - np.round(w)) < 1e-6     # away from the surface
+        assert clear.mean() > 0.95
+        assert set(np.unique(np.round(w[clear]))) <= {0.0, 1.0}
+        assert np.array_equal(lab[clear], np.round(w[clear]).astype(np.uint8))
+        assert 0 < lab[clear].sum() < clear.sum()
+        if surf is dent:
+            assert (lab[k + 100:k + 200] == 0).sum() > 50
+
+
 def test_labels_box_analytic_and_brute_force(oracle):
     lo, hi = np.array([0.21, 0.33, 0.4]), np.array([0.74, 0.61, 0.83])
     s = I.box_surface(lo, hi)
