@@ -1,6 +1,7 @@
 """CPU-only checks of libvms: the C-ABI loads and exports every declared symbol,
 the host mesh derivation matches the CPU reference bit for bit, and error codes
-that the host can force come back as documented (no device call is made)."""
+that the host can force come back as documented (no device call is made),
+including a null handle passed to any entry point that takes one."""
 import os
 import re
 
@@ -245,3 +246,44 @@ def test_surface_components():
     with pytest.raises(vms.VmsError) as e:
         vms.vms_surface_components(open_s)
     assert e.value.code == vms.VMS_EMESH
+
+
+# entry points whose first argument is a handle: each checks it before any
+# device call and returns VMS_EINVAL for a null one
+NULL_HANDLE_CALLS = [
+    "vms_sizes", "vms_export", "vms_stats", "vms_assemble", "vms_apply", "vms_apply_jacobian", "vms_spmv",
+    "vms_set_weak_bc", "vms_element_weights", "vms_dirichlet_nodes", "vms_dirichlet_in_nodes", "vms_solve",
+    "vms_set_inout", "vms_relabel_stats", "vms_set_timing", "vms_last_timing", "vms_set_overlap",
+    "vms_set_scatter", "vms_components",
+    "vms_batch_set_config", "vms_batch_get_config", "vms_batch_use_graph", "vms_batch_assemble",
+    "vms_batch_autotune", "vms_batch_last_timing", "vms_batch_set_order",
+    "inout_classify_prepared", "inout_reserve", "vms_sdf_sample",
+    "vms_q2_sizes", "vms_q2_export", "vms_q2_assemble",
+    "vms_mesh_sizes", "vms_mesh_export",
+    "vms_mlp_get_params", "vms_mlp_set_margin", "vms_mlp_set_margin_grid", "vms_mlp_grad", "vms_mlp_train",
+    "vms_mlp_adam_step", "vms_mlp_predict",
+]
+
+
+def _null_args(fn):
+    import ctypes as C
+    args = []
+    for t in fn.argtypes:
+        if t in (C.c_double, C.c_float):
+            args.append(1.0)      # a valid value: only the handle is wrong
+        elif t in (C.c_int, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_uint8):
+            args.append(1)
+        else:
+            args.append(None)     # pointers, structures by pointer, handles
+    return args
+
+
+def test_null_handles_rejected():
+    L = vms.lib()
+    for name in NULL_HANDLE_CALLS:
+        fn = getattr(L, name)
+        assert fn.argtypes is not None, name
+        assert fn(*_null_args(fn)) == vms.VMS_EINVAL, name
+    # the reason of the last failure without a context is kept globally
+    assert L.vms_sizes(None, None, None, None, None) == vms.VMS_EINVAL
+    assert b"null" in L.vms_last_error(None)
