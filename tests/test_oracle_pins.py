@@ -64,18 +64,17 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 def _sketch():
     """The printed values of the adaptive-quadrature sketch (tests/golden)."""
-    vals, cells = {}, []
+    vals, points = {}, []
     with open(os.path.join(GOLDEN, "adaptive_quadrature_sketch.txt")) as fh:
         for line in fh:
             f = line.split("#", 1)[0].split()
             if not f:
                 continue
-            if f[0] == "cell":
-                ex, ey, side, lvl, i, j = (int(v) for v in f[1:7])
-                cells.append((ex, ey, side, lvl, i, j, float(f[7]), float(f[8])))
+            if f[0] == "point":
+                points.append((int(f[1]), float(f[2]), float(f[3])))
             else:
                 vals[f[0]] = (float(f[1]), int(f[2]))
-    return vals, cells
+    return vals, points
 
 
 def test_gauss_abscissae_match_paper(oracle):
@@ -570,15 +569,28 @@ def test_adaptive_quadrature_stop_rule_and_order(oracle):
 
 
 def test_subcell_points_sit_where_the_sketch_draws_them(oracle):
-    # the sketch of the adaptive quadrature prints its points: a point of split
-    # level l lies at (i + g) / 2^l of its element's side, g one of the two
-    # printed offsets, (i, j) its sub-cell; the fixture's worked cells follow
-    # that rule to their printed digits
-    vals, cells = _sketch()
+    # the sketch of the adaptive quadrature prints its points: every point of
+    # split level l lies at (i + g) / 2^l of its element's side (4), g one of
+    # the two printed offsets and i its sub-cell index; a sub-cell of the first
+    # level is kept whole (all 4 of its points in the plane), one of the last
+    # level keeps the points on the fluid side only
+    vals, points = _sketch()
     gm, gp = vals["g_minus"][0], vals["g_plus"][0]
-    for ex, ey, side, lvl, i, j, x, y in cells:
-        c = side / 2 ** lvl
-        assert abs(ex + c * (i + gm) - x) < 1e-9 and abs(ey + c * (j + gm) - y) < 1e-9
+    assert len(points) == 51
+    cells = {}
+    for lvl, x, y in points:
+        key = [lvl]
+        for v in (x, y):
+            e = 4.0 * np.floor(v / 4.0)
+            u = (v - e) / 4.0 * 2 ** lvl
+            i = int(np.floor(u))
+            assert min(abs(u - i - gm), abs(u - i - gp)) < 1e-9, (lvl, x, y)
+            key += [e, i]
+        cells.setdefault(tuple(key), set()).add((round(x, 6), round(y, 6)))
+    sizes = {k: len(v) for k, v in cells.items()}
+    assert all(n == 4 for k, n in sizes.items() if k[0] == 1) and any(k[0] == 1 for k in sizes)
+    assert all(1 <= n <= 4 for k, n in sizes.items() if k[0] == 2)
+    assert any(n < 4 for k, n in sizes.items() if k[0] == 2)
     # every kept point of the reference's adaptive quadrature (its C routine)
     # follows it at every split level, and the key decoding agrees
     c0 = np.array([0.5, 0.5, 0.5]) + I.BODY_OFFSET
